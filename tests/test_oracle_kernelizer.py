@@ -1,0 +1,180 @@
+"""Pins of the oracle kernelizer and the FP64 learned-cost reference:
+brute force over all contiguous partitions, special cases, the greedy
+comparator, finite differences and hand-derived gradients.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import CostTables, KOpts
+
+
+def _rand_tables(rng, scale=100):
+    t = CostTables()
+    t.fused = [0] + sorted(int(x) for x in rng.integers(1, scale, 7))
+    t.alpha = int(rng.integers(0, scale))
+    t.gate = [int(x) for x in rng.integers(0, scale // 4 + 1, oracle.NUM_CLASSES)]
+    return t
+
+
+def _rand_gates(n, m, rng):
+    c = W.random_circuit(n, m, rng, kinds=[W.H, W.X, W.U3, W.CX, W.CZ, W.CP, W.RZZ])
+    gates, _ = oracle.canonicalize(c)
+    return gates
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_dp_equals_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 7))
+    m = int(rng.integers(1, 12))
+    gates = _rand_gates(n, m, rng)
+    opts = KOpts(k_max=int(rng.integers(2, 6)), m_max=int(rng.integers(3, 7)),
+                 ell=int(rng.integers(0, 3)))
+    tab = _rand_tables(rng)
+    c_dp, k_dp = oracle.ordered_kernelize(gates, opts, tab)
+    c_bf, k_bf = oracle.brute_force_kernelize(gates, opts, tab)
+    assert c_dp == c_bf
+    assert k_dp == k_bf          # identical partition under the total order
+    assert oracle.check_plan(gates, k_dp, opts, tab) == c_dp
+
+
+def test_dp_ties_resolved_identically():
+    """All-equal costs make every partition with the same kernel count tie;
+    the DP and the brute force still pick the same one."""
+    rng = np.random.default_rng(7)
+    gates = _rand_gates(4, 10, rng)
+    tab = CostTables(fused=[0] + [5] * 7, alpha=5, gate=[0] * 7)
+    opts = KOpts(k_max=4, m_max=4, ell=0)
+    assert oracle.ordered_kernelize(gates, opts, tab) == oracle.brute_force_kernelize(gates, opts, tab)
+
+
+def test_special_cases():
+    rng = np.random.default_rng(3)
+    gates = _rand_gates(6, 15, rng)
+    # constant per-kernel cost with unbounded qubit count -> one kernel
+    opts = KOpts(k_max=7, m_max=64, ell=0)
+    tab = CostTables(fused=[0] + [50] * 7, alpha=50, gate=[0] * 7)
+    c, ks = oracle.ordered_kernelize(gates, opts, tab)
+    assert len(ks) == 1 and c == 50
+    # a single gate -> one kernel
+    c, ks = oracle.ordered_kernelize(gates[:1], opts, tab)
+    assert ks == [(0, 1, oracle.TYPE_FUSED, 50)]
+    # empty circuit
+    assert oracle.ordered_kernelize([], opts, tab) == (0, [])
+
+
+def test_one_kernel_per_gate_when_merging_never_pays():
+    """Disjoint-qubit gates with superadditive costs: every gate alone."""
+    n = 8
+    c = W.from_list(n, [W.gate(W.H, [q]) for q in range(n)])
+    gates, _ = oracle.canonicalize(c)
+    tab = CostTables(fused=[0, 1, 3, 9, 27, 81, 243, 729], alpha=10 ** 6, gate=[0] * 7)
+    cost, ks = oracle.ordered_kernelize(gates, KOpts(k_max=7, m_max=8, ell=0), tab)
+    assert cost == n and len(ks) == n
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_dp_not_worse_than_greedy(seed):
+    rng = np.random.default_rng(100 + seed)
+    gates = _rand_gates(10, 80, rng)
+    opts = KOpts(k_max=5, m_max=8, ell=2)
+    tab = _rand_tables(rng, 1000)
+    c_dp, k_dp = oracle.ordered_kernelize(gates, opts, tab)
+    c_gr, k_gr = oracle.greedy_pack(gates, opts, tab)
+    assert oracle.check_plan(gates, k_gr, opts, tab) == c_gr
+    assert c_dp <= c_gr
+
+
+def test_swap_absorption():
+    c = W.from_list(3, [W.gate(W.SWAP, [0, 2]), W.gate(W.H, [0]), W.gate(W.CX, [0, 1])])
+    gates, P = oracle.canonicalize(c)
+    assert P == [2, 1, 0]
+    assert gates == [(W.H, (2,), 1), (W.CX, (2, 1), 2)]
+    gates2, P2 = oracle.canonicalize(c, absorb_swaps=False)
+    assert P2 == [0, 1, 2] and len(gates2) == 3
+
+
+def test_features_by_hand():
+    c = W.from_list(8, [W.gate(W.H, [1]), W.gate(W.CZ, [1, 7]), W.gate(W.U3, [7], [1, 2, 3]),
+                        W.gate(W.RZ, [3], [0.5])])
+    gates, _ = oracle.canonicalize(c)
+    f = oracle.features(gates, 8, oracle.TYPE_LDS, False)
+    exp = np.zeros(oracle.NUM_FEATURES)
+    exp[0] = 3; exp[1] = 4
+    exp[2 + oracle.CLASS_H] = 1; exp[2 + oracle.CLASS_CZ] = 1; exp[2 + oracle.CLASS_U3] = 2
+    exp[9] = 1; exp[10] = 7; exp[11] = 11 / 3; exp[12] = 2; exp[13] = 2
+    exp[14] = 0; exp[15] = 1; exp[16] = 8; exp[17] = 0; exp[18] = 0; exp[19] = 4
+    assert np.allclose(f, exp)
+
+
+# --------------------------------------------------------------------------
+# FP64 MLP reference
+# --------------------------------------------------------------------------
+def test_mlp_gradient_finite_differences():
+    rng = np.random.default_rng(0)
+    p = oracle.mlp_init(6, 8, 1)
+    for k in p:
+        p[k] = p[k] + 0.1 * rng.standard_normal(p[k].shape)
+    x = rng.standard_normal((13, 6))
+    t = rng.standard_normal(13)
+    _, g = oracle.mlp_loss_grad(p, x, t)
+    h = 1e-6
+    for k in p:
+        flat = p[k].reshape(-1)
+        for idx in range(0, flat.size, max(1, flat.size // 7)):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = oracle.mlp_loss_grad(p, x, t)
+            flat[idx] = old - h
+            lm, _ = oracle.mlp_loss_grad(p, x, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[k].reshape(-1)[idx]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_mlp_tiny_closed_form():
+    """One input, one hidden unit per layer, batch of one, active ReLUs:
+    y = w3 (w2 (w1 x + b1) + b2) + b3, loss = (y - t)^2, so
+    dL/dw1 = 2 (y - t) w3 w2 x, dL/db3 = 2 (y - t), dL/dw3 = 2 (y - t) h2."""
+    p = {"W1": np.array([[0.5]]), "b1": np.array([0.25]), "W2": np.array([[2.0]]),
+         "b2": np.array([-0.5]), "W3": np.array([[3.0]]), "b3": np.array([1.0])}
+    x = np.array([[2.0]]); t = np.array([4.0])
+    h1 = 0.5 * 2.0 + 0.25; h2 = 2.0 * h1 - 0.5; y = 3.0 * h2 + 1.0
+    loss, g = oracle.mlp_loss_grad(p, x, t)
+    r = y - 4.0
+    assert loss == pytest.approx(r * r)
+    assert g["W1"][0, 0] == pytest.approx(2 * r * 3.0 * 2.0 * 2.0)
+    assert g["b1"][0] == pytest.approx(2 * r * 3.0 * 2.0)
+    assert g["W2"][0, 0] == pytest.approx(2 * r * 3.0 * h1)
+    assert g["W3"][0, 0] == pytest.approx(2 * r * h2)
+    assert g["b3"][0] == pytest.approx(2 * r)
+    # a dead ReLU passes no gradient
+    p["b1"] = np.array([-5.0])
+    _, g = oracle.mlp_loss_grad(p, x, t)
+    assert g["W1"][0, 0] == 0.0
+
+
+def test_adam_first_step_is_signed_lr():
+    """With bias correction the first Adam step is -lr * g / (|g| + eps)."""
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -4.0, 1e-3])}
+    st = {}
+    oracle.adam_step(p, g, st, lr=0.1)
+    exp = np.array([1.0, -2.0, 3.0]) - 0.1 * g["w"] / (np.abs(g["w"]) + 1e-8)
+    assert np.allclose(p["w"], exp, atol=1e-12)
+
+
+def test_mlp_training_reduces_loss():
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((256, 5))
+    t = np.sin(x[:, 0]) + 0.5 * x[:, 1] ** 2
+    p = oracle.mlp_init(5, 32, 3)
+    st = {}
+    l0, _ = oracle.mlp_loss_grad(p, x, t)
+    for _ in range(300):
+        l, g = oracle.mlp_loss_grad(p, x, t)
+        oracle.adam_step(p, g, st, lr=1e-2)
+    assert l < 0.2 * l0
