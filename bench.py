@@ -1,0 +1,210 @@
+"""Benchmark: 32-qubit circuit wall time and HBM bandwidth on one MI355X.
+
+One step = the three 32-qubit evaluation circuits, each started from its input
+state already in HBM and run through its kernelized plan (every kernel of the
+plan plus the final permutation pass):
+    QFT-32 from a seeded basis state, RL-32 (20 layers, seed 31) from |0>,
+    GHZ-32 from |0>; complex64 state (32 GiB), FP32 arithmetic.
+The state re-initialisation before each circuit is outside the timed events.
+
+Prints one JSON line (see the keys below).  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--cost analytic|learned|both]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def build_circuits(n: int):
+    import workloads as W
+    return [
+        ("qft", W.qft(n), W.random_basis_index(n, 30)),
+        ("rl", W.random_layered(n, 20, 31), 0),
+        ("ghz", W.ghz(n), 0),
+    ]
+
+
+def plan_summary(plan):
+    ks = plan.kernels()
+    return {"kernels": len(ks), "fused": sum(1 for k in ks if k.type == 0),
+            "lds": sum(1 for k in ks if k.type == 1), "cost_ps": plan.total_cost()}
+
+
+def run_gpu(args):
+    import torch
+    import paper_2408_09055_amd as qk
+
+    torch.cuda.set_device(0)
+    n = args.qubits
+    dtype = qk.QK_C64
+    ctx = qk.Context()
+    stream = torch.cuda.current_stream()
+    st = qk.sv_alloc(ctx, n, dtype)
+    circuits = build_circuits(n)
+    models = ["analytic"] if args.cost == "analytic" else ["learned"] if args.cost == "learned" else ["analytic", "learned"]
+
+    plans = {}
+    kern_s = {}
+    for model in models:
+        cm = qk.QK_COST_ANALYTIC if model == "analytic" else qk.QK_COST_LEARNED
+        for name, circ, _ in circuits:
+            t0 = time.perf_counter()
+            plans[(model, name)] = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, cost_model=cm))
+            kern_s[(model, name)] = time.perf_counter() - t0
+
+    amp_bytes = 8
+    pass_bytes = 2 * (1 << n) * amp_bytes
+
+    def one_step(model, record_kernels):
+        """Runs the three circuits; returns per-circuit ms and kernel timings."""
+        ms = {}
+        ktimes = []
+        for name, circ, x in circuits:
+            plan = plans[(model, name)]
+            st.init_basis(x)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            evs = []
+            for i in range(len(plan)):
+                if record_kernels:
+                    a = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                qk.apply_kernel(ctx, plan, i, st)
+                if record_kernels:
+                    b = torch.cuda.Event(enable_timing=True)
+                    b.record(stream)
+                    evs.append((a, b))
+            qk.plan_finish(ctx, plan, st)
+            e1.record(stream)
+            ms[name] = (e0, e1)
+            ktimes.append(evs)
+        torch.cuda.synchronize()
+        out = {k: v[0].elapsed_time(v[1]) for k, v in ms.items()}
+        kt = [a.elapsed_time(b) for evs in ktimes for (a, b) in evs]
+        return out, kt
+
+    results = {}
+    for model in models:
+        for _ in range(args.warmup):
+            one_step(model, False)
+        torch.cuda.synchronize()
+        per = {name: [] for name, _, _ in circuits}
+        kt_all = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ms, kt = one_step(model, True)
+            for k, v in ms.items():
+                per[k].append(v)
+            kt_all.extend(kt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        results[model] = {"per": per, "kernel_ms": kt_all, "wall_s": wall}
+    norm = st.norm2()
+    st.free()
+    ctx.close()
+    return n, circuits, plans, kern_s, results, pass_bytes, norm
+
+
+def cpu_baseline(circuits_n: int, sample_n: int, gates_per_circuit: int):
+    """Oracle timed on a bounded sample: the first `gates_per_circuit` gates of
+    each evaluation circuit rebuilt at `sample_n` qubits (complex128 FP64),
+    scaled by gate count and 2^(n - sample_n) to the full 32-qubit step."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    full = build_circuits(circuits_n)
+    small = build_circuits(sample_n)
+    psi = np.zeros(1 << sample_n, np.complex128)
+    psi[0] = 1.0
+    t_total = 0.0
+    sample_desc = []
+    scale_total = 0.0
+    for (name, fc, _), (_, sc, _) in zip(full, small):
+        g = min(gates_per_circuit, len(sc))
+        part = W.Circuit(sample_n, sc.gates[:g], sc.name)
+        t0 = time.perf_counter()
+        oracle.run(part, psi)
+        dt = time.perf_counter() - t0
+        t_total += dt
+        est = dt / g * len(fc) * (2.0 ** (circuits_n - sample_n))
+        scale_total += est
+        sample_desc.append(f"{name}: first {g} gates at n={sample_n}")
+    return {"value": scale_total * 1e3, "unit": "ms", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "; ".join(sample_desc) + f" (complex128, {t_total:.1f} s measured), scaled per gate "
+                      f"and by 2^{circuits_n - sample_n} to the {circuits_n}-qubit step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--qubits", type=int, default=32)
+    ap.add_argument("--cost", default="analytic", choices=["analytic", "learned", "both"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample-qubits", type=int, default=26)
+    ap.add_argument("--cpu-sample-gates", type=int, default=24)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this simulator runs on one GPU; multi-GPU sharding is not built "
+                                   "(--gpus must be 1)"}))
+        sys.exit(2)
+
+    n, circuits, plans, kern_s, results, pass_bytes, norm = run_gpu(args)
+    import numpy as np
+    model = "learned" if "learned" in results else "analytic"
+    r = results[model]
+    per_ms = {k: float(np.median(v)) for k, v in r["per"].items()}
+    step_ms = sum(per_ms.values())
+    n_passes = sum(len(plans[(model, name)]) + (1 if name == "qft" else 0) for name, _, _ in circuits)
+    gbps = n_passes * pass_bytes / (step_ms * 1e-3) / 1e9
+    kms = np.array(r["kernel_ms"])
+    achieved = pass_bytes / (float(kms.mean()) * 1e-3) / 1e9
+    line = {
+        "metric": "32q circuit wall time (QFT-32 + RL-32 + GHZ-32, complex64) + HBM GB/s",
+        "value": round(step_ms, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["wall_s"] / args.steps * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"qft{n}(basis seed 30) + rl{n}x20(seed 31) + ghz{n}; complex64; "
+                               f"{model}-cost OrderedKernelize plans", "qubits": n, "cost_model": model},
+        "hbm_gbps": round(gbps, 1),
+        "per_circuit_ms": {k: round(v, 3) for k, v in per_ms.items()},
+        "plans": {f"{m}/{name}": plan_summary(plans[(m, name)]) for (m, name) in plans},
+        "kernelize_s": {f"{m}/{name}": round(v, 4) for (m, name), v in kern_s.items()},
+        "norm2_after": norm,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "k_block (staged-block kernel)", "launches": int(kms.size),
+                     "bytes_per_launch": pass_bytes, "avg_ms": round(float(kms.mean()), 4)},
+    }
+    if len(results) == 2:
+        a = sum(float(np.median(v)) for v in results["analytic"]["per"].values())
+        line["analytic_ms"] = round(a, 3)
+        line["learned_ms"] = round(step_ms, 3)
+        line["learned_speedup"] = round(a / step_ms, 4)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_qubits, args.cpu_sample_gates)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

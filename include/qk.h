@@ -1,0 +1,237 @@
+/*
+ * qk -- kernelized state-vector simulation on one AMD MI355X (gfx950).
+ *
+ * C ABI of libqk.so.  The library follows the problem statement of
+ * "Atlas: Hierarchical Partitioning for Quantum Circuit Simulation on GPUs"
+ * (arXiv 2408.09055): a circuit and an input state go in, the final state
+ * comes out (Simulate = Partition + Execute, Algorithm alg:atlas).  On one GPU
+ * the partition is a single stage whose gates are split into kernels by the
+ * OrderedKernelize dynamic program (appendix, Algorithm alg:dp-simple); each
+ * kernel runs either as one fused 2^k x 2^k unitary or as a gate sequence on
+ * amplitude blocks staged in LDS (the two kernel types of the section "Cost
+ * Function in Kernelize").
+ *
+ * Conventions (apply to every function below):
+ *  - Every function returns an int status: QK_OK (0) or a negative QK_E* code.
+ *    qk_last_error() returns a thread-local message describing the last
+ *    failure of the calling thread.
+ *  - Amplitude i of an n-qubit state is complex; qubit q is bit q of i (the
+ *    one-qubit update in the paper's background section).  Complex numbers are
+ *    interleaved (re, im): complex64 = 2 x float, complex128 = 2 x double.
+ *  - Pointers passed in are borrowed for the duration of the call and copied
+ *    if retained.  Handles returned through out-parameters are owned by the
+ *    caller and released with the matching *_free call.
+ *  - Device work is ordered on the context's HIP stream (the stream given to
+ *    qk_ctx_create).  Functions that return host data synchronise that stream;
+ *    the others only enqueue.  A device fault surfaces as QK_EDEVICE at the
+ *    next synchronising call or at qk_sync.
+ *  - No function allocates or frees memory it does not document.
+ */
+#ifndef QK_PUBLIC_API_H
+#define QK_PUBLIC_API_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define QK_OK            0
+#define QK_EINVAL       -1  /* bad argument (qubit index, size, option) */
+#define QK_ENOMEM       -2  /* device or host allocation failed */
+#define QK_EDEVICE      -3  /* HIP runtime error or no usable GPU */
+#define QK_ESTATE       -4  /* state layout does not match what the call needs */
+#define QK_EUNSUPPORTED -5  /* valid request this build does not support */
+
+/* ---- element types ----------------------------------------------------- */
+typedef enum { QK_C64 = 0, QK_C128 = 1 } qk_dtype;
+
+/* ---- circuits ------------------------------------------------------------
+ * A circuit is a gate sequence applied in order (psi -> U psi per gate, the
+ * state-evolution rule of the background section).  Gate matrices follow the
+ * OpenQASM 2 definitions; for two-qubit gates the matrix index bit j belongs
+ * to the j-th listed qubit and controls are listed first (CX q[0] -> q[1]).
+ *   H X Y Z S T        fixed one-qubit gates
+ *   RX RY RZ (theta)    rotations; RZ = diag(e^{-i t/2}, e^{i t/2})
+ *   P (lambda)          diag(1, e^{i lambda})
+ *   U3 (theta, phi, lambda)
+ *   CX CZ SWAP          fixed two-qubit gates
+ *   CP (phi)            diag(1, 1, 1, e^{i phi})
+ *   RZZ (theta)         exp(-i theta/2 Z(x)Z)
+ */
+enum {
+    QK_H = 0, QK_X, QK_Y, QK_Z, QK_S, QK_T, QK_RX, QK_RY, QK_RZ, QK_P, QK_U3,
+    QK_CX, QK_CZ, QK_CP, QK_RZZ, QK_SWAP, QK_NUM_KINDS
+};
+
+typedef struct qk_gate {
+    uint32_t kind;   /* QK_H ... QK_SWAP */
+    uint32_t nq;     /* number of qubits (1 or 2), must match the kind */
+    uint32_t q[3];   /* qubits, controls first; unused entries ignored */
+    uint32_t flags;  /* reserved, must be 0 */
+    double p[3];     /* angles in radians; unused entries ignored */
+} qk_gate;           /* 48 bytes */
+
+typedef struct qk_circuit {
+    int32_t n_qubits;      /* 1..34 */
+    int32_t reserved;
+    int64_t n_gates;       /* >= 0 */
+    const qk_gate* gates;  /* host array of n_gates records */
+} qk_circuit;
+
+/* ---- opaque handles ----------------------------------------------------- */
+typedef struct qk_ctx qk_ctx;
+typedef struct qk_state qk_state;
+typedef struct qk_plan qk_plan;
+
+/* ---- context ------------------------------------------------------------ */
+#define QK_CTX_HOST_ONLY 1   /* planning only: no HIP call is ever made */
+
+/* Create a context bound to the current HIP device and to hip_stream (a
+ * hipStream_t; NULL = the null stream).  With QK_CTX_HOST_ONLY the context can
+ * kernelize with analytic costs but every device call returns QK_EDEVICE.
+ * Holds the analytic cost tables, the learned-model weights and scratch
+ * buffers.  QK_EDEVICE if no gfx950 device is visible (without the flag). */
+int qk_ctx_create(void* hip_stream, uint32_t flags, qk_ctx** out);
+int qk_ctx_free(qk_ctx* ctx);
+/* Wait for all work queued on the context's stream; QK_EDEVICE on a fault. */
+int qk_sync(qk_ctx* ctx);
+const char* qk_last_error(void);
+/* Library version string, static storage. */
+const char* qk_version(void);
+
+/* ---- state vectors ------------------------------------------------------ */
+/* hipMalloc 2^n amplitudes of dtype (8 or 16 bytes each), uninitialised, in
+ * logical order (physical layout = identity).  QK_EINVAL for n outside 1..34,
+ * QK_ENOMEM if the allocation fails. */
+int sv_alloc(qk_ctx* ctx, int n_qubits, int dtype, qk_state** out);
+/* Wrap caller-owned device memory of 2^n amplitudes (e.g. a torch tensor).
+ * The memory must stay valid until sv_free; libqk never frees it.  dev_ptr
+ * must be 16-byte aligned. */
+int sv_wrap(qk_ctx* ctx, void* dev_ptr, int n_qubits, int dtype, qk_state** out);
+int sv_free(qk_state* st);
+/* Device pointer of the amplitudes (it changes after a permutation pass on an
+ * sv_alloc'ed state; it never changes for a wrapped state). */
+int sv_device_ptr(const qk_state* st, void** out);
+int sv_info(const qk_state* st, int* n_qubits, int* dtype);
+/* Physical position of each logical qubit: perm[q] = bit of the amplitude
+ * index that holds logical qubit q (identity = logical order). */
+int sv_layout(const qk_state* st, int32_t* perm);
+/* Set the state to the basis state |x> (logical index x). */
+int sv_init_basis(qk_state* st, uint64_t x);
+/* Copy 2^n amplitudes of the state's dtype from host (logical order). */
+int sv_upload(qk_state* st, const void* host);
+/* Copy 2^n amplitudes to host.  QK_ESTATE unless the layout is logical. */
+int sv_download(qk_state* st, void* host);
+/* Copy amplitudes [offset, offset+count) (logical order) to host. */
+int sv_download_range(qk_state* st, uint64_t offset, uint64_t count, void* host);
+/* Bring the state back to logical order with one permutation pass (a no-op
+ * when it already is). */
+int sv_restore(qk_state* st);
+/* Qubit-permutation pass: the amplitude at physical index x moves to index
+ * pi(x), where bit b of x goes to bit perm[b] (perm is a permutation of
+ * 0..n-1).  The logical layout is updated accordingly, so the state's logical
+ * content is unchanged.  Out of place through a scratch buffer of the state's
+ * size (held by the state until sv_free). */
+int sv_permute(qk_state* st, const int32_t* perm);
+/* ||psi||^2 in FP64 (compensated per-thread sums, fixed-order tree). */
+int sv_norm2(qk_state* st, double* out);
+/* <psi|ref> restricted to logical indices [offset, offset+count), FP64;
+ * ref is a host complex128 array of count amplitudes.  QK_ESTATE unless the
+ * layout is logical.  Summing over consecutive chunks gives the full overlap. */
+int sv_overlap_host(qk_state* st, const double* ref_c128, uint64_t offset,
+                    uint64_t count, double out[2]);
+/* Amplitudes at cnt logical indices, returned as complex128 on host. */
+int sv_gather(qk_state* st, const uint64_t* idx, uint64_t cnt, double* out_c128);
+
+/* ---- kernelization (Partition on one GPU) -------------------------------
+ * Kernelization depends on the circuit only, never on the state.  Cost of a
+ * kernel (section "Cost Function in Kernelize"):
+ *   fused (fusion) kernel on k qubits : fused_ps[k]
+ *   LDS (shared-memory) kernel        : lds_alpha_ps + sum_g lds_gate_ps[class(g)]
+ * classes: 0 H, 1 X/Y, 2 other one-qubit (U3 RX RY RZ P Z S T), 3 CX/SWAP,
+ *          4 CZ, 5 CP, 6 RZZ.
+ * A segment's cost is the minimum over the feasible types (fused on an exact
+ * tie); the fused type is feasible iff k <= k_max, the LDS type iff
+ * |qubits U {0..ell-1}| <= m_max.  OrderedKernelize minimises the sum over a
+ * partition into contiguous segments; ties go to fewer kernels, then to the
+ * shorter last kernel.  Costs are integer picoseconds. */
+enum { QK_COST_ANALYTIC = 0, QK_COST_LEARNED = 1 };
+enum { QK_KERNEL_FUSED = 0, QK_KERNEL_LDS = 1 };
+#define QK_NUM_CLASSES 7
+
+typedef struct qk_cost_tables {
+    int64_t fused_ps[8];                  /* index k = 1..7; [0] unused */
+    int64_t lds_alpha_ps;                 /* empty LDS kernel over the state */
+    int64_t lds_gate_ps[QK_NUM_CLASSES];  /* per gate, inside an LDS kernel */
+} qk_cost_tables;
+
+typedef struct qk_kopts {
+    int32_t dtype;         /* QK_C64 or QK_C128: the state the plan runs on */
+    int32_t cost_model;    /* QK_COST_ANALYTIC or QK_COST_LEARNED */
+    int32_t k_max;         /* fused kernels: 1..7 qubits */
+    int32_t m_max;         /* LDS kernels: active set bound, ell..14 */
+    int32_t ell;           /* lowest qubits forced into every LDS kernel, 1..m_max */
+    int32_t absorb_swaps;  /* relabel SWAP gates into the layout instead of running them */
+    int32_t allow_fused;
+    int32_t allow_lds;
+    int32_t block_qubits;  /* amplitudes per staged block = 2^block_qubits
+                              (>= m_max and >= k_max; 0 = m_max) */
+    int32_t learned_flags; /* out: 1 if a learned request fell back to analytic */
+    const qk_cost_tables* tables;  /* explicit analytic tables, or NULL for the
+                                      context's tables for (n, dtype) */
+} qk_kopts;
+
+/* Defaults: complex64, analytic, k_max 5, m_max 12, ell 3, swaps absorbed,
+ * both kernel types, block_qubits 0, tables NULL. */
+void qk_kopts_default(qk_kopts* ko);
+
+typedef struct qk_kernel_info {
+    int32_t type;          /* QK_KERNEL_FUSED or QK_KERNEL_LDS */
+    int32_t k;             /* number of distinct qubits of the kernel's gates */
+    int64_t gate_begin;    /* canonical gate range [begin, end) */
+    int64_t gate_end;
+    uint64_t qubit_mask;   /* physical qubits of the kernel's gates */
+    int64_t cost_ps;       /* cost the DP charged for this kernel */
+    int32_t block_qubits;  /* staged block size used at run time */
+    int32_t n_ops;         /* device operations (1 for a fused kernel) */
+} qk_kernel_info;
+
+/* Run canonicalisation (SWAP absorption), segment costing, OrderedKernelize
+ * and plan building (FP64 products of the fused kernels' gate matrices,
+ * rounded once to the state dtype; LDS operation tables), then upload the
+ * plan to the device on the context's stream (skipped for host-only
+ * contexts).  ko may be NULL for defaults.  QK_EINVAL for a malformed
+ * circuit or options. */
+int kernelize(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_plan** out);
+int plan_num_kernels(const qk_plan* p, int64_t* out);
+int plan_kernel_info(const qk_plan* p, int64_t i, qk_kernel_info* out);
+int plan_total_cost(const qk_plan* p, int64_t* out);
+/* Canonical gates (after SWAP absorption): count, then source index of gate
+ * i in the input circuit. */
+int plan_num_gates(const qk_plan* p, int64_t* out);
+int plan_gate_source(const qk_plan* p, int64_t i, int64_t* out);
+/* Layout after the last kernel: perm[q] = physical bit of logical qubit q. */
+int plan_final_layout(const qk_plan* p, int32_t* perm);
+int plan_free(qk_plan* p);
+
+/* ---- execution (Execute on one GPU) ------------------------------------- */
+/* Enqueue kernel i of plan p on st (LaunchKernel of alg:atlas).  The state
+ * must have the plan's n and dtype and the layout the plan expects before
+ * kernel i (identity for i = 0 and every i on a single-stage plan):
+ * QK_ESTATE otherwise. */
+int apply_kernel(qk_ctx* ctx, const qk_plan* p, int64_t i, qk_state* st);
+/* After the last kernel: record the plan's final layout on the state and
+ * restore logical order with one permutation pass if it is not identity. */
+int plan_finish(qk_ctx* ctx, const qk_plan* p, qk_state* st);
+/* Simulate: kernelize c, apply every kernel, restore logical order.  The
+ * state must be in logical order on entry and is on return. */
+int simulate(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_state* st);
+/* Enqueue all kernels of p and plan_finish, without re-planning. */
+int execute_plan(qk_ctx* ctx, const qk_plan* p, qk_state* st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QK_PUBLIC_API_H */

@@ -342,6 +342,8 @@ def ordered_kernelize(gates, opts: KOpts, tab: CostTables):
             if cand < best[i + 1]:   # strict: on a tie the larger j (seen first) stays
                 best[i + 1] = cand
                 back[i + 1] = (j, t, c)
+        if back[i + 1] is None:
+            raise ValueError(f"gate {i} fits no kernel type")
     kernels = []
     i = m
     while i > 0:

@@ -1,0 +1,382 @@
+"""qk: kernelized state-vector simulation on one AMD MI355X (gfx950).
+
+Thin ctypes binding over ``libqk.so`` (declared in ``include/qk.h``).  Every
+step of the simulation runs in the library's HIP kernels; this module only
+marshals arguments.  Importing it fails loudly when the library has not been
+built (``python -m paper_2408_09055_amd.build``).
+
+PyTorch provides device memory and the stream: ``State.from_torch`` wraps a
+``torch.complex64``/``complex128`` CUDA tensor, and contexts bind to
+``torch.cuda.current_stream()`` by default.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libqk.so not found at {LIB_PATH}: build it with `python -m paper_2408_09055_amd.build` "
+        "(there is no fallback implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+QK_OK, QK_EINVAL, QK_ENOMEM, QK_EDEVICE, QK_ESTATE, QK_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+QK_C64, QK_C128 = 0, 1
+QK_COST_ANALYTIC, QK_COST_LEARNED = 0, 1
+QK_KERNEL_FUSED, QK_KERNEL_LDS = 0, 1
+QK_CTX_HOST_ONLY = 1
+NUM_CLASSES = 7
+
+_ERRNAMES = {QK_EINVAL: "QK_EINVAL", QK_ENOMEM: "QK_ENOMEM", QK_EDEVICE: "QK_EDEVICE",
+             QK_ESTATE: "QK_ESTATE", QK_EUNSUPPORTED: "QK_EUNSUPPORTED"}
+
+
+class QkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------- structures
+class qk_circuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_gates", ctypes.c_int64), ("gates", ctypes.c_void_p)]
+
+
+class qk_cost_tables(ctypes.Structure):
+    _fields_ = [("fused_ps", ctypes.c_int64 * 8), ("lds_alpha_ps", ctypes.c_int64),
+                ("lds_gate_ps", ctypes.c_int64 * NUM_CLASSES)]
+
+
+class qk_kopts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("cost_model", ctypes.c_int32), ("k_max", ctypes.c_int32),
+                ("m_max", ctypes.c_int32), ("ell", ctypes.c_int32), ("absorb_swaps", ctypes.c_int32),
+                ("allow_fused", ctypes.c_int32), ("allow_lds", ctypes.c_int32),
+                ("block_qubits", ctypes.c_int32), ("learned_flags", ctypes.c_int32),
+                ("tables", ctypes.POINTER(qk_cost_tables))]
+
+
+class qk_kernel_info(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("k", ctypes.c_int32), ("gate_begin", ctypes.c_int64),
+                ("gate_end", ctypes.c_int64), ("qubit_mask", ctypes.c_uint64), ("cost_ps", ctypes.c_int64),
+                ("block_qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_i32, _i64, _u64, _u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
+_dbl_p = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "qk_ctx_create": [_P, _u32, _PP], "qk_ctx_free": [_P], "qk_sync": [_P],
+    "sv_alloc": [_P, ctypes.c_int, ctypes.c_int, _PP],
+    "sv_wrap": [_P, _P, ctypes.c_int, ctypes.c_int, _PP], "sv_free": [_P],
+    "sv_device_ptr": [_P, _PP], "sv_info": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+    "sv_layout": [_P, _P], "sv_init_basis": [_P, _u64], "sv_upload": [_P, _P], "sv_download": [_P, _P],
+    "sv_download_range": [_P, _u64, _u64, _P], "sv_restore": [_P], "sv_permute": [_P, _P],
+    "sv_norm2": [_P, _dbl_p], "sv_overlap_host": [_P, _P, _u64, _u64, _P],
+    "sv_gather": [_P, _P, _u64, _P],
+    "kernelize": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _PP],
+    "plan_num_kernels": [_P, ctypes.POINTER(_i64)],
+    "plan_kernel_info": [_P, _i64, ctypes.POINTER(qk_kernel_info)],
+    "plan_total_cost": [_P, ctypes.POINTER(_i64)], "plan_num_gates": [_P, ctypes.POINTER(_i64)],
+    "plan_gate_source": [_P, _i64, ctypes.POINTER(_i64)], "plan_final_layout": [_P, _P],
+    "plan_free": [_P],
+    "apply_kernel": [_P, _P, _i64, _P], "plan_finish": [_P, _P, _P],
+    "simulate": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _P],
+    "execute_plan": [_P, _P, _P],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.qk_last_error.restype = ctypes.c_char_p
+_lib.qk_last_error.argtypes = []
+_lib.qk_version.restype = ctypes.c_char_p
+_lib.qk_kopts_default.restype = None
+_lib.qk_kopts_default.argtypes = [ctypes.POINTER(qk_kopts)]
+
+
+def lib():
+    return _lib
+
+
+def _check(rc: int):
+    if rc != QK_OK:
+        raise QkError(rc, _lib.qk_last_error().decode(errors="replace"))
+
+
+def version() -> str:
+    return _lib.qk_version().decode()
+
+
+# ---------------------------------------------------------------- options
+def kopts(dtype=QK_C64, cost_model=QK_COST_ANALYTIC, k_max=None, m_max=None, ell=None,
+          absorb_swaps=None, allow_fused=None, allow_lds=None, block_qubits=None, tables=None) -> qk_kopts:
+    ko = qk_kopts()
+    _lib.qk_kopts_default(ctypes.byref(ko))
+    ko.dtype = int(dtype)
+    ko.cost_model = int(cost_model)
+    for name, val in (("k_max", k_max), ("m_max", m_max), ("ell", ell), ("absorb_swaps", absorb_swaps),
+                      ("allow_fused", allow_fused), ("allow_lds", allow_lds), ("block_qubits", block_qubits)):
+        if val is not None:
+            setattr(ko, name, int(val))
+    if tables is not None:
+        t = tables if isinstance(tables, qk_cost_tables) else make_tables(*tables)
+        ko._tables_keep = t
+        ko.tables = ctypes.pointer(t)
+    return ko
+
+
+def make_tables(fused, alpha, gate) -> qk_cost_tables:
+    t = qk_cost_tables()
+    for k in range(8):
+        t.fused_ps[k] = int(fused[k])
+    t.lds_alpha_ps = int(alpha)
+    for c in range(NUM_CLASSES):
+        t.lds_gate_ps[c] = int(gate[c])
+    return t
+
+
+def _circuit_struct(circ) -> qk_circuit:
+    gates = np.ascontiguousarray(circ.gates)
+    assert gates.dtype.itemsize == 48
+    c = qk_circuit()
+    c.n_qubits = circ.n_qubits
+    c.n_gates = len(gates)
+    c.gates = gates.ctypes.data if len(gates) else None
+    c._keep = gates
+    return c
+
+
+# ---------------------------------------------------------------- objects
+class Context:
+    """A libqk context bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None, host_only: bool = False):
+        self.host_only = host_only
+        if stream is None and not host_only:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(_lib.qk_ctx_create(ctypes.c_void_p(stream or 0), QK_CTX_HOST_ONLY if host_only else 0,
+                                  ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _lib.qk_ctx_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        _check(_lib.qk_sync(self.h))
+
+
+class State:
+    """A 2^n-amplitude state vector on the device."""
+
+    def __init__(self, ctx: Context, handle, n: int, dtype: int, keep=None):
+        self.ctx = ctx
+        self.h = handle
+        self.n = n
+        self.dtype = dtype
+        self._keep = keep
+
+    @classmethod
+    def alloc(cls, ctx: Context, n: int, dtype: int = QK_C64) -> "State":
+        h = ctypes.c_void_p()
+        _check(_lib.sv_alloc(ctx.h, n, dtype, ctypes.byref(h)))
+        return cls(ctx, h, n, dtype)
+
+    @classmethod
+    def from_torch(cls, ctx: Context, t) -> "State":
+        import torch
+        assert t.is_cuda and t.is_contiguous() and t.dim() == 1
+        dtype = {torch.complex64: QK_C64, torch.complex128: QK_C128}[t.dtype]
+        n = int(t.numel()).bit_length() - 1
+        assert (1 << n) == t.numel()
+        h = ctypes.c_void_p()
+        _check(_lib.sv_wrap(ctx.h, ctypes.c_void_p(t.data_ptr()), n, dtype, ctypes.byref(h)))
+        return cls(ctx, h, n, dtype, keep=t)
+
+    def free(self):
+        if self.h:
+            _lib.sv_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def np_dtype(self):
+        return np.complex64 if self.dtype == QK_C64 else np.complex128
+
+    def device_ptr(self) -> int:
+        p = ctypes.c_void_p()
+        _check(_lib.sv_device_ptr(self.h, ctypes.byref(p)))
+        return p.value
+
+    def layout(self) -> list:
+        out = np.zeros(self.n, np.int32)
+        _check(_lib.sv_layout(self.h, out.ctypes.data))
+        return [int(x) for x in out]
+
+    def init_basis(self, x: int = 0):
+        _check(_lib.sv_init_basis(self.h, int(x)))
+
+    def upload(self, host: np.ndarray):
+        a = np.ascontiguousarray(host, dtype=self.np_dtype)
+        assert a.size == (1 << self.n)
+        _check(_lib.sv_upload(self.h, a.ctypes.data))
+
+    def download(self) -> np.ndarray:
+        out = np.empty(1 << self.n, self.np_dtype)
+        _check(_lib.sv_download(self.h, out.ctypes.data))
+        return out
+
+    def download_range(self, offset: int, count: int) -> np.ndarray:
+        out = np.empty(count, self.np_dtype)
+        _check(_lib.sv_download_range(self.h, offset, count, out.ctypes.data))
+        return out
+
+    def restore(self):
+        _check(_lib.sv_restore(self.h))
+
+    def permute(self, perm):
+        p = np.ascontiguousarray(perm, np.int32)
+        _check(_lib.sv_permute(self.h, p.ctypes.data))
+
+    def norm2(self) -> float:
+        out = ctypes.c_double()
+        _check(_lib.sv_norm2(self.h, ctypes.byref(out)))
+        return out.value
+
+    def overlap_host(self, ref: np.ndarray, offset: int = 0) -> complex:
+        r = np.ascontiguousarray(ref, np.complex128)
+        out = np.zeros(2)
+        _check(_lib.sv_overlap_host(self.h, r.ctypes.data, offset, r.size, out.ctypes.data))
+        return complex(out[0], out[1])
+
+    def gather(self, idx) -> np.ndarray:
+        i = np.ascontiguousarray(idx, np.uint64)
+        out = np.zeros(i.size, np.complex128)
+        _check(_lib.sv_gather(self.h, i.ctypes.data, i.size, out.ctypes.data))
+        return out
+
+
+class KernelInfo:
+    def __init__(self, s: qk_kernel_info):
+        self.type = s.type
+        self.k = s.k
+        self.gate_begin = s.gate_begin
+        self.gate_end = s.gate_end
+        self.qubit_mask = s.qubit_mask
+        self.cost_ps = s.cost_ps
+        self.block_qubits = s.block_qubits
+        self.n_ops = s.n_ops
+
+    def as_tuple(self):
+        return (self.gate_begin, self.gate_end, self.type, self.cost_ps)
+
+    def __repr__(self):
+        t = "fused" if self.type == QK_KERNEL_FUSED else "lds"
+        return f"<{t} k={self.k} gates[{self.gate_begin}:{self.gate_end}] cost={self.cost_ps}>"
+
+
+class Plan:
+    """Output of ``kernelize``: a kernel sequence ready to run."""
+
+    def __init__(self, ctx: Context, handle, n: int):
+        self.ctx = ctx
+        self.h = handle
+        self.n = n
+
+    def free(self):
+        if self.h:
+            _lib.plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __len__(self):
+        v = ctypes.c_int64()
+        _check(_lib.plan_num_kernels(self.h, ctypes.byref(v)))
+        return v.value
+
+    def kernel(self, i: int) -> KernelInfo:
+        s = qk_kernel_info()
+        _check(_lib.plan_kernel_info(self.h, i, ctypes.byref(s)))
+        return KernelInfo(s)
+
+    def kernels(self) -> list:
+        return [self.kernel(i) for i in range(len(self))]
+
+    def total_cost(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.plan_total_cost(self.h, ctypes.byref(v)))
+        return v.value
+
+    def num_gates(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.plan_num_gates(self.h, ctypes.byref(v)))
+        return v.value
+
+    def gate_source(self, i: int) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.plan_gate_source(self.h, i, ctypes.byref(v)))
+        return v.value
+
+    def final_layout(self) -> list:
+        out = np.zeros(self.n, np.int32)
+        _check(_lib.plan_final_layout(self.h, out.ctypes.data))
+        return [int(x) for x in out]
+
+
+# ---------------------------------------------------------------- entry points
+def sv_alloc(ctx: Context, n: int, dtype: int = QK_C64) -> State:
+    return State.alloc(ctx, n, dtype)
+
+
+def kernelize(ctx: Context, circuit, ko: qk_kopts | None = None) -> Plan:
+    c = _circuit_struct(circuit)
+    h = ctypes.c_void_p()
+    _check(_lib.kernelize(ctx.h, ctypes.byref(c), ctypes.byref(ko) if ko is not None else None,
+                          ctypes.byref(h)))
+    return Plan(ctx, h, circuit.n_qubits)
+
+
+def apply_kernel(ctx: Context, plan: Plan, i: int, state: State):
+    _check(_lib.apply_kernel(ctx.h, plan.h, i, state.h))
+
+
+def plan_finish(ctx: Context, plan: Plan, state: State):
+    _check(_lib.plan_finish(ctx.h, plan.h, state.h))
+
+
+def execute_plan(ctx: Context, plan: Plan, state: State):
+    _check(_lib.execute_plan(ctx.h, plan.h, state.h))
+
+
+def simulate(ctx: Context, circuit, state: State, ko: qk_kopts | None = None):
+    c = _circuit_struct(circuit)
+    _check(_lib.simulate(ctx.h, ctypes.byref(c), ctypes.byref(ko) if ko is not None else None, state.h))

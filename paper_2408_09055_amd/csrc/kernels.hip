@@ -1,0 +1,589 @@
+// HIP kernels of libqk for gfx950 (CDNA4, wave64).
+//
+// k_block      -- staged-block kernel.  A block is the 2^m amplitudes whose
+//                 index bits outside the active qubit set are fixed (the k-qubit
+//                 generalisation of the pairing f(i) of the one-qubit update).
+//                 The block is loaded from HBM into LDS with 16-byte accesses
+//                 along the contiguous low-qubit run, the kernel's operations
+//                 are applied in LDS (a gate sequence for an LDS kernel, one
+//                 dense 2^k x 2^k product for a fused kernel), and the block is
+//                 written back.  Every amplitude is read and written exactly
+//                 once per launch.
+// k_permute    -- out-of-place qubit-permutation pass through LDS tiles whose
+//                 active set covers the low bits on both sides, so reads and
+//                 writes are both contiguous runs.
+// k_norm2 / k_overlap / k_sum_partials / k_gather / k_fill_basis -- FP64
+//                 reductions with compensated sums and a fixed-order tree.
+#include <hip/hip_runtime.h>
+
+#include "qk_internal.hpp"
+
+namespace qk {
+
+namespace {
+
+constexpr int kNT = 256;   // threads per workgroup (4 waves of 64)
+
+__device__ __forceinline__ uint32_t ins0(uint32_t x, int pos)
+{
+    return ((x >> pos) << (pos + 1)) | (x & ((1u << pos) - 1u));
+}
+
+__device__ __forceinline__ uint64_t ins0_64(uint64_t x, int pos)
+{
+    return ((x >> pos) << (pos + 1)) | (x & ((1ull << pos) - 1ull));
+}
+
+template <typename C> struct Real;
+template <> struct Real<float2> { using T = float; };
+template <> struct Real<double2> { using T = double; };
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b)
+{
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+// acc + a*b
+template <typename C>
+__device__ __forceinline__ C cmadd(C a, C b, C acc)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+
+template <typename C>
+__device__ __forceinline__ C czero()
+{
+    C r;
+    r.x = 0;
+    r.y = 0;
+    return r;
+}
+
+// Split offset tables: an index h over `nb` bits maps to
+// tab_lo[h & lomask] + tab_hi[h >> nlo]; each table has at most 128 entries.
+struct SplitTab {
+    uint64_t lo[128];
+    uint64_t hi[128];
+};
+
+__device__ __forceinline__ void build_split(SplitTab& t, const uint8_t* qubits, int nb, int tid, int nt)
+{
+    const int nlo = nb / 2, nhi = nb - nlo;
+    for (int h = tid; h < (1 << nlo); h += nt) {
+        uint64_t o = 0;
+        for (int j = 0; j < nlo; ++j) if ((h >> j) & 1) o |= 1ull << qubits[j];
+        t.lo[h] = o;
+    }
+    for (int h = tid; h < (1 << nhi); h += nt) {
+        uint64_t o = 0;
+        for (int j = 0; j < nhi; ++j) if ((h >> j) & 1) o |= 1ull << qubits[nlo + j];
+        t.hi[h] = o;
+    }
+}
+
+__device__ __forceinline__ uint64_t split_off(const SplitTab& t, uint32_t h, int nb)
+{
+    const int nlo = nb / 2;
+    return t.lo[h & ((1u << nlo) - 1u)] + t.hi[h >> nlo];
+}
+
+// ----------------------------------------------------------- block operations
+template <typename C>
+__device__ void op_dense1(C* sm, int m, int j, const C* __restrict__ u)
+{
+    const C u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+    const uint32_t half = 1u << (m - 1);
+    for (uint32_t p = threadIdx.x; p < half; p += kNT) {
+        const uint32_t r0 = ins0(p, j), r1 = r0 | (1u << j);
+        const C a = sm[r0], b = sm[r1];
+        sm[r0] = cmadd(u01, b, cmul(u00, a));
+        sm[r1] = cmadd(u11, b, cmul(u10, a));
+    }
+}
+
+template <typename C>
+__device__ void op_diag1(C* sm, int m, int j, const C* __restrict__ u)
+{
+    const C d1 = u[1], d0 = u[0];
+    for (uint32_t r = threadIdx.x; r < (1u << m); r += kNT)
+        sm[r] = cmul(sm[r], ((r >> j) & 1u) ? d1 : d0);
+}
+
+template <typename C>
+__device__ void op_x(C* sm, int m, int j)
+{
+    for (uint32_t p = threadIdx.x; p < (1u << (m - 1)); p += kNT) {
+        const uint32_t r0 = ins0(p, j), r1 = r0 | (1u << j);
+        const C a = sm[r0];
+        sm[r0] = sm[r1];
+        sm[r1] = a;
+    }
+}
+
+// Enumerate the 2^(m-2) indices with zero bits at a and b (a != b).
+__device__ __forceinline__ uint32_t ins00(uint32_t p, int a, int b)
+{
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return ins0(ins0(p, lo), hi);
+}
+
+template <typename C>
+__device__ void op_cx(C* sm, int m, int c, int t)
+{
+    for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
+        const uint32_t r0 = ins00(p, c, t) | (1u << c), r1 = r0 | (1u << t);
+        const C a = sm[r0];
+        sm[r0] = sm[r1];
+        sm[r1] = a;
+    }
+}
+
+template <typename C>
+__device__ void op_cz(C* sm, int m, int a, int b)
+{
+    for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
+        const uint32_t r = ins00(p, a, b) | (1u << a) | (1u << b);
+        C v = sm[r];
+        v.x = -v.x;
+        v.y = -v.y;
+        sm[r] = v;
+    }
+}
+
+template <typename C>
+__device__ void op_cphase(C* sm, int m, int a, int b, const C* __restrict__ u)
+{
+    const C ph = u[0];
+    for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
+        const uint32_t r = ins00(p, a, b) | (1u << a) | (1u << b);
+        sm[r] = cmul(sm[r], ph);
+    }
+}
+
+template <typename C>
+__device__ void op_diag2(C* sm, int m, int a, int b, const C* __restrict__ u)
+{
+    const C d0 = u[0], d1 = u[1], d2 = u[2], d3 = u[3];
+    for (uint32_t r = threadIdx.x; r < (1u << m); r += kNT) {
+        const uint32_t s = ((r >> a) & 1u) | (((r >> b) & 1u) << 1);
+        const C d = s == 0 ? d0 : s == 1 ? d1 : s == 2 ? d2 : d3;
+        sm[r] = cmul(sm[r], d);
+    }
+}
+
+template <typename C>
+__device__ void op_swap(C* sm, int m, int a, int b)
+{
+    for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
+        const uint32_t base = ins00(p, a, b);
+        const uint32_t r0 = base | (1u << a), r1 = base | (1u << b);
+        const C v = sm[r0];
+        sm[r0] = sm[r1];
+        sm[r1] = v;
+    }
+}
+
+// Dense 2^K x 2^K product on block bits bits[0..K) (ascending).  Each thread
+// owns whole groups: it gathers the group's 2^K amplitudes into registers,
+// then writes the 2^K outputs back in place (groups are disjoint).
+template <typename C, int K>
+__device__ void op_densek_group(C* sm, int m, const uint8_t* bits, const C* __restrict__ U)
+{
+    constexpr int D = 1 << K;
+    uint32_t off[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) if ((r >> j) & 1) o |= 1u << bits[j];
+        off[r] = o;
+    }
+    const uint32_t ngroups = 1u << (m - K);
+    for (uint32_t g = threadIdx.x; g < ngroups; g += kNT) {
+        uint32_t base = g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) base = ins0(base, bits[j]);
+        C v[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) v[r] = sm[base + off[r]];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            C acc = czero<C>();
+#pragma unroll
+            for (int c = 0; c < D; ++c) acc = cmadd(U[r * D + c], v[c], acc);
+            sm[base + off[r]] = acc;
+        }
+    }
+}
+
+// Dense product for K = 6, 7: thread-per-output.  Rounds of kNT * 4 outputs
+// (whole groups, since 2^K divides the round) are first all read, then, after
+// a barrier, all written, so the in-place update never reads a new value.
+template <typename C, int K>
+__device__ void op_densek_rows(C* sm, int m, const uint8_t* bits, const C* __restrict__ U)
+{
+    constexpr int D = 1 << K;
+    constexpr int PER = 4;
+    uint32_t off[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) if ((r >> j) & 1) o |= 1u << bits[j];
+        off[r] = o;
+    }
+    const uint32_t total = 1u << m;
+    for (uint32_t e0 = 0; e0 < total; e0 += kNT * PER) {
+        C out[PER];
+        uint32_t dst[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t e = e0 + threadIdx.x + (uint32_t)i * kNT;
+            out[i] = czero<C>();
+            dst[i] = 0xffffffffu;
+            if (e < total) {
+                const uint32_t g = e >> K, r = e & (D - 1);
+                uint32_t base = g;
+#pragma unroll
+                for (int j = 0; j < K; ++j) base = ins0(base, bits[j]);
+                C acc = czero<C>();
+                for (int c = 0; c < D; ++c) acc = cmadd(U[r * D + c], sm[base + off[c]], acc);
+                out[i] = acc;
+                uint32_t o = 0;
+#pragma unroll
+                for (int j = 0; j < K; ++j) if ((r >> j) & 1) o |= 1u << bits[j];
+                dst[i] = base + o;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+            if (dst[i] != 0xffffffffu) sm[dst[i]] = out[i];
+        __syncthreads();
+    }
+}
+
+template <typename C>
+__device__ void op_densek(C* sm, int m, const Op& op, const C* __restrict__ U)
+{
+    switch (op.k) {
+    case 1: op_densek_group<C, 1>(sm, m, op.b, U); break;
+    case 2: op_densek_group<C, 2>(sm, m, op.b, U); break;
+    case 3: op_densek_group<C, 3>(sm, m, op.b, U); break;
+    case 4: op_densek_group<C, 4>(sm, m, op.b, U); break;
+    case 5: op_densek_group<C, 5>(sm, m, op.b, U); break;
+    case 6: op_densek_rows<C, 6>(sm, m, op.b, U); break;
+    case 7: op_densek_rows<C, 7>(sm, m, op.b, U); break;
+    default: break;
+    }
+}
+
+// ----------------------------------------------------------- staged block kernel
+template <typename C>
+__global__ __launch_bounds__(kNT) void k_block(C* __restrict__ psi, BlockDesc d,
+                                               const Op* __restrict__ ops,
+                                               const C* __restrict__ coef)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ SplitTab tab;
+    C* sm = reinterpret_cast<C*>(smem);
+    const int m = d.m, ell0 = d.ell0, nhi = m - ell0;
+    const int tid = threadIdx.x;
+    build_split(tab, d.act + ell0, nhi, tid, kNT);
+    constexpr int CH = 16 / sizeof(C);          // amplitudes per 16-byte access
+    const uint32_t nch = (1u << m) / CH;
+    const uint32_t lomask = (1u << ell0) - 1u;
+    for (uint64_t blk = blockIdx.x; blk < d.nblocks; blk += gridDim.x) {
+        uint64_t base = blk;
+        for (int j = 0; j < m; ++j) base = ins0_64(base, d.act[j]);
+        __syncthreads();
+        for (uint32_t c = tid; c < nch; c += kNT) {
+            const uint32_t r = c * CH;
+            const uint64_t a = base + split_off(tab, r >> ell0, nhi) + (r & lomask);
+            *reinterpret_cast<uint4*>(&sm[r]) = *reinterpret_cast<const uint4*>(&psi[a]);
+        }
+        __syncthreads();
+        for (int o = 0; o < d.n_ops; ++o) {
+            const Op op = ops[o];
+            const C* u = coef + op.coef;
+            switch (op.code) {
+            case OP_DENSE1: op_dense1(sm, m, op.b[0], u); break;
+            case OP_DIAG1: op_diag1(sm, m, op.b[0], u); break;
+            case OP_X: op_x(sm, m, op.b[0]); break;
+            case OP_CX: op_cx(sm, m, op.b[0], op.b[1]); break;
+            case OP_CZ: op_cz(sm, m, op.b[0], op.b[1]); break;
+            case OP_CPHASE: op_cphase(sm, m, op.b[0], op.b[1], u); break;
+            case OP_DIAG2: op_diag2(sm, m, op.b[0], op.b[1], u); break;
+            case OP_SWAP: op_swap(sm, m, op.b[0], op.b[1]); break;
+            case OP_DENSEK: op_densek(sm, m, op, u); break;
+            default: break;
+            }
+            __syncthreads();
+        }
+        for (uint32_t c = tid; c < nch; c += kNT) {
+            const uint32_t r = c * CH;
+            const uint64_t a = base + split_off(tab, r >> ell0, nhi) + (r & lomask);
+            *reinterpret_cast<uint4*>(&psi[a]) = *reinterpret_cast<const uint4*>(&sm[r]);
+        }
+    }
+}
+
+// ----------------------------------------------------------- permutation pass
+template <typename C>
+__global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* __restrict__ dst, PermDesc d)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ SplitTab tsrc, tdst;
+    __shared__ uint16_t rlo[128], rhi[128];   // dest-local index -> source-local index
+    C* sm = reinterpret_cast<C*>(smem);
+    const int m = d.m, tid = threadIdx.x;
+    const int nhs = m - d.lo_src, nhd = m - d.lo_dst;
+    build_split(tsrc, d.act_src + d.lo_src, nhs, tid, kNT);
+    build_split(tdst, d.act_dst + d.lo_dst, nhd, tid, kNT);
+    const int nlo = m / 2, nhi = m - nlo;
+    for (int h = tid; h < (1 << nlo); h += kNT) {
+        uint32_t r = 0;
+        for (int j = 0; j < nlo; ++j) if ((h >> j) & 1) r |= 1u << d.src_of_dst[j];
+        rlo[h] = (uint16_t)r;
+    }
+    for (int h = tid; h < (1 << nhi); h += kNT) {
+        uint32_t r = 0;
+        for (int j = 0; j < nhi; ++j) if ((h >> j) & 1) r |= 1u << d.src_of_dst[nlo + j];
+        rhi[h] = (uint16_t)r;
+    }
+    constexpr int CH = 16 / sizeof(C);
+    const uint32_t nch = (1u << m) / CH;
+    const uint32_t ms = (1u << d.lo_src) - 1u, md = (1u << d.lo_dst) - 1u;
+    for (uint64_t blk = blockIdx.x; blk < d.nblocks; blk += gridDim.x) {
+        uint64_t sb = blk;
+        for (int j = 0; j < m; ++j) sb = ins0_64(sb, d.act_src[j]);
+        uint64_t db = 0;
+        for (int b = 0; b < d.n; ++b) if ((sb >> b) & 1) db |= 1ull << d.perm[b];
+        __syncthreads();
+        for (uint32_t c = tid; c < nch; c += kNT) {
+            const uint32_t r = c * CH;
+            const uint64_t a = sb + split_off(tsrc, r >> d.lo_src, nhs) + (r & ms);
+            *reinterpret_cast<uint4*>(&sm[r]) = *reinterpret_cast<const uint4*>(&src[a]);
+        }
+        __syncthreads();
+        for (uint32_t c = tid; c < nch; c += kNT) {
+            const uint32_t s = c * CH;
+            union { C v[CH]; uint4 w; } u;
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const uint32_t se = s + e;
+                u.v[e] = sm[rlo[se & ((1u << nlo) - 1u)] | rhi[se >> nlo]];
+            }
+            const uint64_t a = db + split_off(tdst, s >> d.lo_dst, nhd) + (s & md);
+            *reinterpret_cast<uint4*>(&dst[a]) = u.w;
+        }
+    }
+}
+
+// ----------------------------------------------------------- reductions
+constexpr int kRedBlocks = 1024;
+
+// Neumaier compensated accumulation
+__device__ __forceinline__ void comp_add(double& s, double& c, double x)
+{
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+__device__ void block_reduce2(double a, double b, double* out)
+{
+    __shared__ double ra[kNT], rb[kNT];
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = kNT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            ra[threadIdx.x] += ra[threadIdx.x + s];
+            rb[threadIdx.x] += rb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = ra[0];
+        out[1] = rb[0];
+    }
+}
+
+template <typename C>
+__global__ __launch_bounds__(kNT) void k_norm2(const C* __restrict__ psi, uint64_t N, double* partials)
+{
+    double s = 0, c = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * kNT;
+    for (uint64_t i = (uint64_t)blockIdx.x * kNT + threadIdx.x; i < N; i += stride) {
+        const C v = psi[i];
+        const double x = (double)v.x, y = (double)v.y;
+        comp_add(s, c, x * x + y * y);
+    }
+    block_reduce2(s + c, 0.0, partials + 2 * blockIdx.x);
+}
+
+template <typename C>
+__global__ __launch_bounds__(kNT) void k_overlap(const C* __restrict__ psi, uint64_t offset, uint64_t count,
+                                                 const double2* __restrict__ ref, double* partials)
+{
+    double sr = 0, cr = 0, si = 0, ci = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * kNT;
+    for (uint64_t i = (uint64_t)blockIdx.x * kNT + threadIdx.x; i < count; i += stride) {
+        const C v = psi[offset + i];
+        const double2 w = ref[i];
+        const double x = (double)v.x, y = (double)v.y;
+        // conj(v) * w
+        comp_add(sr, cr, x * w.x + y * w.y);
+        comp_add(si, ci, x * w.y - y * w.x);
+    }
+    block_reduce2(sr + cr, si + ci, partials + 2 * blockIdx.x);
+}
+
+// Single workgroup: sums `np` (re, im) partials in a fixed order.
+__global__ __launch_bounds__(kNT) void k_sum_partials(const double* partials, int np, double* result)
+{
+    double sr = 0, cr = 0, si = 0, ci = 0;
+    for (int i = threadIdx.x; i < np; i += kNT) {
+        comp_add(sr, cr, partials[2 * i]);
+        comp_add(si, ci, partials[2 * i + 1]);
+    }
+    block_reduce2(sr + cr, si + ci, result);
+}
+
+template <typename C>
+__global__ void k_gather(const C* __restrict__ psi, const uint64_t* __restrict__ idx, uint64_t cnt, double2* out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) {
+        const C v = psi[idx[i]];
+        out[i] = make_double2((double)v.x, (double)v.y);
+    }
+}
+
+template <typename C>
+__global__ void k_fill_basis(C* psi, uint64_t N, uint64_t x)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        C v = czero<C>();
+        if (i == x) v.x = 1;
+        psi[i] = v;
+    }
+}
+
+uint32_t grid_for(uint64_t nblocks)
+{
+    return (uint32_t)(nblocks < (1ull << 30) ? nblocks : (1ull << 30));
+}
+
+}  // namespace
+
+size_t block_lds_bytes(int dtype, int m, int /*ell0*/)
+{
+    return (size_t)(dtype == QK_C128 ? 16 : 8) << m;
+}
+
+// Dynamic LDS of up to 64 KiB plus the static tables exceeds the default
+// per-launch limit, so raise it once per kernel instantiation.
+template <typename F>
+void allow_lds(F* f)
+{
+    static bool done = false;
+    if (!done) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  96 * 1024);
+        done = true;
+    }
+}
+
+int launch_block(int dtype, void* psi, const BlockDesc& d, const Op* ops, const void* coef, void* stream)
+{
+    const size_t lds = block_lds_bytes(dtype, d.m, d.ell0);
+    if (dtype == QK_C128) allow_lds(k_block<double2>); else allow_lds(k_block<float2>);
+    const dim3 grid(grid_for(d.nblocks)), block(kNT);
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == QK_C128)
+        hipLaunchKernelGGL(k_block<double2>, grid, block, lds, s, (double2*)psi, d, ops, (const double2*)coef);
+    else
+        hipLaunchKernelGGL(k_block<float2>, grid, block, lds, s, (float2*)psi, d, ops, (const float2*)coef);
+    return (int)hipGetLastError();
+}
+
+int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream)
+{
+    const size_t lds = (size_t)(dtype == QK_C128 ? 16 : 8) << d.m;
+    if (dtype == QK_C128) allow_lds(k_permute<double2>); else allow_lds(k_permute<float2>);
+    const dim3 grid(grid_for(d.nblocks)), block(kNT);
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == QK_C128)
+        hipLaunchKernelGGL(k_permute<double2>, grid, block, lds, s, (const double2*)src, (double2*)dst, d);
+    else
+        hipLaunchKernelGGL(k_permute<float2>, grid, block, lds, s, (const float2*)src, (float2*)dst, d);
+    return (int)hipGetLastError();
+}
+
+int launch_fill_basis(int dtype, void* psi, uint64_t N, uint64_t x, void* stream)
+{
+    const uint64_t blocks = std::min<uint64_t>((N + kNT - 1) / kNT, 1u << 16);
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == QK_C128)
+        hipLaunchKernelGGL(k_fill_basis<double2>, dim3((uint32_t)blocks), dim3(kNT), 0, s, (double2*)psi, N, x);
+    else
+        hipLaunchKernelGGL(k_fill_basis<float2>, dim3((uint32_t)blocks), dim3(kNT), 0, s, (float2*)psi, N, x);
+    return (int)hipGetLastError();
+}
+
+int reduce_partials() { return kRedBlocks; }
+
+int launch_norm2(int dtype, const void* psi, uint64_t N, double* partials, double* result, void* stream)
+{
+    const int nb = (int)std::min<uint64_t>(kRedBlocks, (N + kNT - 1) / kNT);
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == QK_C128)
+        hipLaunchKernelGGL(k_norm2<double2>, dim3(nb), dim3(kNT), 0, s, (const double2*)psi, N, partials);
+    else
+        hipLaunchKernelGGL(k_norm2<float2>, dim3(nb), dim3(kNT), 0, s, (const float2*)psi, N, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kNT), 0, s, (const double*)partials, nb, result);
+    return (int)hipGetLastError();
+}
+
+int launch_overlap(int dtype, const void* psi, uint64_t offset, uint64_t count, const double* ref,
+                   double* partials, double* result, void* stream)
+{
+    const int nb = (int)std::max<uint64_t>(1, std::min<uint64_t>(kRedBlocks, (count + kNT - 1) / kNT));
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == QK_C128)
+        hipLaunchKernelGGL(k_overlap<double2>, dim3(nb), dim3(kNT), 0, s, (const double2*)psi, offset, count,
+                           (const double2*)ref, partials);
+    else
+        hipLaunchKernelGGL(k_overlap<float2>, dim3(nb), dim3(kNT), 0, s, (const float2*)psi, offset, count,
+                           (const double2*)ref, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kNT), 0, s, (const double*)partials, nb, result);
+    return (int)hipGetLastError();
+}
+
+int launch_gather(int dtype, const void* psi, const uint64_t* idx, uint64_t cnt, double* out, void* stream)
+{
+    if (cnt == 0) return 0;
+    const uint64_t blocks = (cnt + kNT - 1) / kNT;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == QK_C128)
+        hipLaunchKernelGGL(k_gather<double2>, dim3((uint32_t)blocks), dim3(kNT), 0, s, (const double2*)psi, idx, cnt,
+                           (double2*)out);
+    else
+        hipLaunchKernelGGL(k_gather<float2>, dim3((uint32_t)blocks), dim3(kNT), 0, s, (const float2*)psi, idx, cnt,
+                           (double2*)out);
+    return (int)hipGetLastError();
+}
+
+}  // namespace qk

@@ -1,0 +1,60 @@
+// Plan representation shared by the planner (kernelize) and the executor.
+#pragma once
+
+#include <vector>
+
+#include "qk_internal.hpp"
+
+namespace qk {
+
+// A gate after canonicalisation: physical qubits, SWAPs possibly absorbed.
+struct CGate {
+    uint32_t kind;
+    int nq;
+    int q[2];
+    double p[3];
+    int64_t src;   // index in the input circuit
+};
+
+struct PKernel {
+    int type;          // QK_KERNEL_FUSED / QK_KERNEL_LDS
+    int k;             // distinct qubits of the kernel's gates
+    int64_t g0, g1;    // canonical gate range [g0, g1)
+    uint64_t mask;     // physical qubits of the gates
+    int64_t cost;      // DP cost (ps)
+    BlockDesc desc;    // staged-block launch
+    int op_off, n_ops; // slice of the plan's op table
+};
+
+// Feature vector of a candidate kernel for the learned cost model.
+constexpr int kNumFeatures = 20;
+void segment_features(const CGate* g, int count, int n, int type, int dtype, float* out);
+
+// Learned-model hook: predicts log(ps per amplitude) for `cnt` feature rows.
+// Returns QK_OK or an error (then the planner falls back to analytic costs).
+int learned_predict(qk_ctx* ctx, int dtype, const float* feats, int64_t cnt, float* out);
+bool learned_available(qk_ctx* ctx, int dtype);
+
+// Analytic tables used when a context has none for (n, dtype).
+qk_cost_tables default_tables(int n, int dtype);
+bool ctx_lookup_tables(const qk_ctx* ctx, int n, int dtype, qk_cost_tables* out);
+
+}  // namespace qk
+
+struct qk_plan {
+    int n = 0;
+    int dtype = 0;
+    qk_kopts ko{};
+    qk_cost_tables tab{};
+    bool learned_used = false;
+    bool learned_fallback = false;
+    std::vector<qk::CGate> gates;
+    std::vector<qk::PKernel> kernels;
+    std::vector<int32_t> final_layout;   // logical q -> physical bit
+    std::vector<qk::Op> ops;
+    std::vector<qk::cd> coefs;           // FP64 master copy
+    int64_t total_cost = 0;
+    qk_ctx* ctx = nullptr;
+    void* d_ops = nullptr;
+    void* d_coef = nullptr;
+};

@@ -1,0 +1,403 @@
+// Host planner: canonicalisation, segment costs, OrderedKernelize and plan
+// building.
+//
+// * Canonicalisation relabels logical qubits to physical ones and absorbs
+//   SWAP gates into the layout, which is the permutation tracking of Execute
+//   (Algorithm alg:atlas) on a single stage.
+// * The kernel cost follows the section "Cost Function in Kernelize": a
+//   fused kernel costs a constant per qubit count, a shared-memory (here LDS)
+//   kernel costs alpha plus a per-gate term; both copies of every kernel are
+//   considered and the cheaper type is kept.
+// * OrderedKernelize is the appendix's dynamic program over contiguous
+//   segments, DP[i+1] = min_j DP[j] + Cost(C[j..i]) (objective
+//   eqn:dp_objective).  Walking j down from i only grows the segment's qubit
+//   set, so once both kernel types are infeasible every smaller j is too and
+//   the walk stops early without changing the result.
+// * Plan building fuses each fused kernel's gates into one 2^k x 2^k matrix in
+//   FP64 (later gates on the left) and turns each LDS kernel's gates into
+//   block-local operations.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "plan.hpp"
+
+namespace qk {
+
+namespace {
+
+constexpr int64_t kInf = int64_t(1) << 62;
+
+int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+// Build the active set of a staged block: the kernel qubits, the forced low
+// qubits, then the lowest remaining qubits until m are active.
+uint64_t active_set(uint64_t mask, int ell, int m, int n)
+{
+    uint64_t a = mask | ((ell >= 64) ? ~0ull : ((1ull << ell) - 1));
+    for (int q = 0; q < n && popcount64(a) < m; ++q) a |= 1ull << q;
+    return a;
+}
+
+void fill_desc(BlockDesc& d, uint64_t act, int n)
+{
+    std::memset(&d, 0, sizeof(d));
+    int m = 0;
+    for (int q = 0; q < n; ++q)
+        if ((act >> q) & 1) d.act[m++] = (uint8_t)q;
+    d.n = n;
+    d.m = m;
+    d.nblocks = 1ull << (n - m);
+    int e = 0;
+    while (e < m && d.act[e] == e) ++e;
+    d.ell0 = e;
+}
+
+int block_bit(const BlockDesc& d, int q)
+{
+    for (int j = 0; j < d.m; ++j)
+        if (d.act[j] == q) return j;
+    return -1;
+}
+
+// Multiply the 2^k x 2^k matrix U (row-major) on the left by gate g embedded
+// on local bits loc[0..nq) of the kernel's k qubits.
+void left_multiply(std::vector<cd>& U, int k, const CGate& g, const int* loc)
+{
+    const int dim = 1 << k;
+    cd G[16];
+    qk_gate rec{};
+    rec.kind = g.kind;
+    rec.nq = g.nq;
+    rec.p[0] = g.p[0]; rec.p[1] = g.p[1]; rec.p[2] = g.p[2];
+    gate_unitary(rec, G);
+    const int gd = 1 << g.nq;
+    uint64_t gmask = 0;
+    for (int j = 0; j < g.nq; ++j) gmask |= 1ull << loc[j];
+    std::vector<cd> col(gd), res(gd);
+    for (int c = 0; c < dim; ++c) {            // each column is a k-qubit state
+        for (int base = 0; base < dim; ++base) {
+            if (base & gmask) continue;
+            for (int r = 0; r < gd; ++r) {
+                int idx = base;
+                for (int j = 0; j < g.nq; ++j) if ((r >> j) & 1) idx |= 1 << loc[j];
+                col[r] = U[(size_t)idx * dim + c];
+            }
+            for (int r = 0; r < gd; ++r) {
+                cd acc = 0.0;
+                for (int s = 0; s < gd; ++s) acc += G[r * gd + s] * col[s];
+                res[r] = acc;
+            }
+            for (int r = 0; r < gd; ++r) {
+                int idx = base;
+                for (int j = 0; j < g.nq; ++j) if ((r >> j) & 1) idx |= 1 << loc[j];
+                U[(size_t)idx * dim + c] = res[r];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ tables
+qk_cost_tables default_tables(int n, int dtype)
+{
+    // A bandwidth model: one pass reads and writes the state once at an
+    // assumed 5 TB/s; fused kernels are limited by the larger of that pass
+    // and their 8 * 2^(n+k) flops at an assumed 60 TFLOP/s (c64) or
+    // 40 TFLOP/s (c128); LDS gates add a fraction of a pass.  Calibration on
+    // the device replaces these numbers.
+    qk_cost_tables t{};
+    const double amps = std::ldexp(1.0, n);
+    const double bytes = 2.0 * amps * (dtype == QK_C128 ? 16.0 : 8.0);
+    const double pass_ps = bytes / 5e12 * 1e12;
+    const double rate = dtype == QK_C128 ? 40e12 : 60e12;
+    for (int k = 1; k <= 7; ++k) {
+        const double flops_ps = 8.0 * amps * std::ldexp(1.0, k) / rate * 1e12;
+        t.fused_ps[k] = (int64_t)std::llround(std::max(pass_ps, flops_ps) * (1.0 + 0.02 * k));
+    }
+    t.lds_alpha_ps = (int64_t)std::llround(pass_ps * 1.05);
+    const double f[QK_NUM_CLASSES] = {0.05, 0.03, 0.06, 0.03, 0.02, 0.02, 0.03};
+    for (int c = 0; c < QK_NUM_CLASSES; ++c) t.lds_gate_ps[c] = (int64_t)std::llround(pass_ps * f[c]);
+    return t;
+}
+
+bool ctx_lookup_tables(const qk_ctx* ctx, int n, int dtype, qk_cost_tables* out)
+{
+    if (!ctx) return false;
+    for (auto& e : ctx->tables)
+        if (e.first == n * 2 + dtype) { *out = e.second; return true; }
+    return false;
+}
+
+// ------------------------------------------------------------------ features
+void segment_features(const CGate* g, int count, int n, int type, int dtype, float* f)
+{
+    for (int i = 0; i < kNumFeatures; ++i) f[i] = 0.0f;
+    uint64_t mask = 0;
+    int diag = 0;
+    for (int i = 0; i < count; ++i) {
+        for (int j = 0; j < g[i].nq; ++j) mask |= 1ull << g[i].q[j];
+        f[2 + gate_class(g[i].kind)] += 1.0f;
+        if (kind_is_diagonal(g[i].kind)) ++diag;
+    }
+    const int k = popcount64(mask);
+    int lo = 64, hi = -1, below6 = 0;
+    double sum = 0.0;
+    for (int q = 0; q < 64; ++q) {
+        if (!((mask >> q) & 1)) continue;
+        lo = std::min(lo, q);
+        hi = std::max(hi, q);
+        sum += q;
+        if (q < 6) ++below6;
+    }
+    f[0] = (float)k;
+    f[1] = (float)count;
+    f[9] = (float)lo;
+    f[10] = (float)hi;
+    f[11] = (float)(sum / k);
+    f[12] = (float)below6;
+    f[13] = (float)diag;
+    f[14] = type == QK_KERNEL_FUSED ? 1.0f : 0.0f;
+    f[15] = 1.0f - f[14];
+    f[16] = (float)n;
+    f[17] = dtype == QK_C128 ? 1.0f : 0.0f;
+    f[18] = (float)k * f[14];
+    f[19] = (float)count * f[15];
+}
+
+// ------------------------------------------------------------------ kernelize
+int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan** out)
+{
+    if (!c || !out) return fail(QK_EINVAL, "kernelize: null argument");
+    qk_kopts ko;
+    if (ko_in) ko = *ko_in; else qk_kopts_default(&ko);
+    const int n = c->n_qubits;
+    if (n < 1 || n > kMaxQubits) return fail(QK_EINVAL, "kernelize: n_qubits out of range 1..34");
+    if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) return fail(QK_EINVAL, "kernelize: bad gate array");
+    if (ko.dtype != QK_C64 && ko.dtype != QK_C128) return fail(QK_EINVAL, "kernelize: bad dtype");
+    if (ko.k_max < 1 || ko.k_max > kMaxFusedQubits) return fail(QK_EINVAL, "kernelize: k_max must be 1..7");
+    if (ko.ell < 1 || ko.ell > ko.m_max) return fail(QK_EINVAL, "kernelize: ell must be 1..m_max");
+    if (ko.m_max < 2 || ko.m_max > kMaxBlockQubits) return fail(QK_EINVAL, "kernelize: m_max must be 2..14");
+    if (!ko.allow_fused && !ko.allow_lds) return fail(QK_EINVAL, "kernelize: no kernel type allowed");
+    int mblk = ko.block_qubits ? ko.block_qubits : ko.m_max;
+    if (mblk < ko.m_max || mblk <= ko.k_max || mblk > kMaxBlockQubits)
+        return fail(QK_EINVAL, "kernelize: block_qubits must be >= m_max, > k_max and <= 14");
+    const int64_t bytes_per_amp = ko.dtype == QK_C128 ? 16 : 8;
+    if (((int64_t)bytes_per_amp << std::min(mblk, n)) > 64 * 1024)
+        return fail(QK_EINVAL, "kernelize: block of 2^block_qubits amplitudes exceeds 64 KiB of LDS");
+
+    qk_plan* P = new qk_plan();
+    P->n = n;
+    P->dtype = ko.dtype;
+    P->ko = ko;
+    P->ctx = ctx;
+    if (ko.tables) P->tab = *ko.tables;
+    else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
+
+    // ---- canonicalise
+    std::vector<int32_t> layout(n);
+    for (int q = 0; q < n; ++q) layout[q] = q;
+    for (int64_t i = 0; i < c->n_gates; ++i) {
+        const qk_gate& g = c->gates[i];
+        const int ar = kind_arity(g.kind);
+        if (ar == 0 || (int)g.nq != ar) { delete P; return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " has a bad kind or qubit count"); }
+        for (int j = 0; j < ar; ++j) {
+            if (g.q[j] >= (uint32_t)n) { delete P; return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " qubit out of range"); }
+            for (int l = 0; l < j; ++l)
+                if (g.q[l] == g.q[j]) { delete P; return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " repeats a qubit"); }
+        }
+        if (g.flags != 0) { delete P; return fail(QK_EINVAL, "kernelize: gate flags must be 0"); }
+        if (ko.absorb_swaps && g.kind == QK_SWAP) {
+            std::swap(layout[g.q[0]], layout[g.q[1]]);
+            continue;
+        }
+        CGate cg{};
+        cg.kind = g.kind;
+        cg.nq = ar;
+        for (int j = 0; j < ar; ++j) cg.q[j] = layout[g.q[j]];
+        cg.p[0] = g.p[0]; cg.p[1] = g.p[1]; cg.p[2] = g.p[2];
+        cg.src = i;
+        P->gates.push_back(cg);
+    }
+    P->final_layout = layout;
+    const int64_t m = (int64_t)P->gates.size();
+    const std::vector<CGate>& G = P->gates;
+
+    // ---- enumerate feasible segments (early exit is exact: see header)
+    const uint64_t lowmask = (1ull << ko.ell) - 1;
+    std::vector<int64_t> seg_off(m + 1, 0);
+    std::vector<uint64_t> seg_mask;
+    std::vector<int64_t> seg_fused, seg_lds;
+    for (int64_t i = 0; i < m; ++i) {
+        seg_off[i] = (int64_t)seg_mask.size();
+        uint64_t mask = 0;
+        int64_t s = P->tab.lds_alpha_ps;
+        for (int64_t j = i; j >= 0; --j) {
+            for (int t = 0; t < G[j].nq; ++t) mask |= 1ull << G[j].q[t];
+            s += P->tab.lds_gate_ps[gate_class(G[j].kind)];
+            const int k = popcount64(mask);
+            const bool fok = ko.allow_fused && k <= ko.k_max;
+            const bool lok = ko.allow_lds && popcount64(mask | lowmask) <= ko.m_max;
+            if (!fok && !lok) break;
+            seg_mask.push_back(mask);
+            seg_fused.push_back(fok ? P->tab.fused_ps[k] : kInf);
+            seg_lds.push_back(lok ? s : kInf);
+        }
+    }
+    seg_off[m] = (int64_t)seg_mask.size();
+
+    // ---- learned costs replace the analytic ones for every feasible entry
+    if (ko.cost_model == QK_COST_LEARNED) {
+        if (!learned_available(ctx, ko.dtype)) {
+            P->learned_fallback = true;
+        } else {
+            std::vector<float> feats;
+            std::vector<int64_t*> dst;
+            feats.reserve(seg_mask.size() * 2 * kNumFeatures);
+            float f[kNumFeatures];
+            for (int64_t i = 0; i < m; ++i) {
+                for (int64_t e = seg_off[i]; e < seg_off[i + 1]; ++e) {
+                    const int64_t j = i - (e - seg_off[i]);
+                    if (seg_fused[e] < kInf) {
+                        segment_features(&G[j], (int)(i - j + 1), n, QK_KERNEL_FUSED, ko.dtype, f);
+                        feats.insert(feats.end(), f, f + kNumFeatures);
+                        dst.push_back(&seg_fused[e]);
+                    }
+                    if (seg_lds[e] < kInf) {
+                        segment_features(&G[j], (int)(i - j + 1), n, QK_KERNEL_LDS, ko.dtype, f);
+                        feats.insert(feats.end(), f, f + kNumFeatures);
+                        dst.push_back(&seg_lds[e]);
+                    }
+                }
+            }
+            std::vector<float> pred(dst.size());
+            int rc = dst.empty() ? QK_OK
+                                 : learned_predict(ctx, ko.dtype, feats.data(), (int64_t)dst.size(), pred.data());
+            if (rc != QK_OK) {
+                P->learned_fallback = true;
+            } else {
+                const double amps = std::ldexp(1.0, n);
+                for (size_t t = 0; t < dst.size(); ++t) {
+                    // quantise once: predicted log(ps per amplitude) -> int64 ps
+                    double ps = std::exp((double)pred[t]) * amps;
+                    ps = std::min(std::max(ps, 1.0), 1e15);
+                    *dst[t] = (int64_t)std::llround(ps);
+                }
+                P->learned_used = true;
+            }
+        }
+    }
+
+    // ---- OrderedKernelize
+    std::vector<int64_t> best_c(m + 1, kInf), best_n(m + 1, 0), back_j(m + 1, -1);
+    std::vector<int> back_t(m + 1, 0);
+    std::vector<int64_t> back_cost(m + 1, 0);
+    best_c[0] = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t e = seg_off[i]; e < seg_off[i + 1]; ++e) {
+            const int64_t j = i - (e - seg_off[i]);
+            int64_t cst; int typ;
+            if (seg_fused[e] <= seg_lds[e]) { cst = seg_fused[e]; typ = QK_KERNEL_FUSED; }
+            else { cst = seg_lds[e]; typ = QK_KERNEL_LDS; }
+            if (cst >= kInf || best_c[j] >= kInf) continue;
+            const int64_t cc = best_c[j] + cst, cn = best_n[j] + 1;
+            // strict improvement only: on a tie the larger j (visited first) stays
+            if (cc < best_c[i + 1] || (cc == best_c[i + 1] && cn < best_n[i + 1])) {
+                best_c[i + 1] = cc;
+                best_n[i + 1] = cn;
+                back_j[i + 1] = j;
+                back_t[i + 1] = typ;
+                back_cost[i + 1] = cst;
+            }
+        }
+        if (best_c[i + 1] >= kInf) { delete P; return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " fits no kernel type"); }
+    }
+    P->total_cost = best_c[m];
+    std::vector<int64_t> cuts;
+    for (int64_t i = m; i > 0; i = back_j[i]) cuts.push_back(i);
+    std::reverse(cuts.begin(), cuts.end());
+
+    // ---- plan build
+    const int m_exec = std::min(n, mblk);
+    int64_t j = 0;
+    for (int64_t i : cuts) {
+        PKernel K{};
+        K.type = back_t[i];
+        K.cost = back_cost[i];
+        K.g0 = j;
+        K.g1 = i;
+        uint64_t mask = 0;
+        for (int64_t t = j; t < i; ++t)
+            for (int u = 0; u < G[t].nq; ++u) mask |= 1ull << G[t].q[u];
+        K.mask = mask;
+        K.k = popcount64(mask);
+        const int ell = (K.type == QK_KERNEL_LDS) ? ko.ell : 1;
+        fill_desc(K.desc, active_set(mask, std::min(ell, n), m_exec, n), n);
+        K.op_off = (int)P->ops.size();
+        if (K.type == QK_KERNEL_FUSED) {
+            // kernel qubits in ascending order give the matrix index bits
+            int kq[8], kb[8], nk = 0;
+            for (int q = 0; q < n; ++q)
+                if ((mask >> q) & 1) { kq[nk] = q; kb[nk] = block_bit(K.desc, q); ++nk; }
+            const int dim = 1 << nk;
+            std::vector<cd> U((size_t)dim * dim, cd(0.0, 0.0));
+            for (int r = 0; r < dim; ++r) U[(size_t)r * dim + r] = 1.0;
+            for (int64_t t = j; t < i; ++t) {
+                int loc[2];
+                for (int u = 0; u < G[t].nq; ++u)
+                    loc[u] = (int)(std::find(kq, kq + nk, G[t].q[u]) - kq);
+                left_multiply(U, nk, G[t], loc);
+            }
+            Op op{};
+            op.code = OP_DENSEK;
+            op.k = (uint8_t)nk;
+            for (int u = 0; u < nk; ++u) op.b[u] = (uint8_t)kb[u];
+            op.coef = (uint32_t)P->coefs.size();
+            P->coefs.insert(P->coefs.end(), U.begin(), U.end());
+            P->ops.push_back(op);
+        } else {
+            for (int64_t t = j; t < i; ++t) {
+                const CGate& g = G[t];
+                Op op{};
+                op.b[0] = (uint8_t)block_bit(K.desc, g.q[0]);
+                if (g.nq == 2) op.b[1] = (uint8_t)block_bit(K.desc, g.q[1]);
+                op.coef = (uint32_t)P->coefs.size();
+                cd U[16];
+                qk_gate rec{};
+                rec.kind = g.kind; rec.nq = g.nq;
+                rec.p[0] = g.p[0]; rec.p[1] = g.p[1]; rec.p[2] = g.p[2];
+                gate_unitary(rec, U);
+                switch (g.kind) {
+                case QK_X: op.code = OP_X; break;
+                case QK_CX: op.code = OP_CX; break;
+                case QK_CZ: op.code = OP_CZ; break;
+                case QK_SWAP: op.code = OP_SWAP; break;
+                case QK_CP: op.code = OP_CPHASE; P->coefs.push_back(U[15]); break;
+                case QK_RZZ:
+                    op.code = OP_DIAG2;
+                    for (int r = 0; r < 4; ++r) P->coefs.push_back(U[r * 5]);
+                    break;
+                case QK_Z: case QK_S: case QK_T: case QK_RZ: case QK_P:
+                    op.code = OP_DIAG1;
+                    P->coefs.push_back(U[0]);
+                    P->coefs.push_back(U[3]);
+                    break;
+                default:
+                    op.code = OP_DENSE1;
+                    for (int r = 0; r < 4; ++r) P->coefs.push_back(U[r]);
+                    break;
+                }
+                P->ops.push_back(op);
+            }
+        }
+        K.n_ops = (int)P->ops.size() - K.op_off;
+        K.desc.n_ops = K.n_ops;
+        P->kernels.push_back(K);
+        j = i;
+    }
+    *out = P;
+    return QK_OK;
+}
+
+}  // namespace qk

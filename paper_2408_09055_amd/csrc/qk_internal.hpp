@@ -1,0 +1,115 @@
+// Internal declarations shared by the host planner, the executor and the
+// HIP kernels of libqk.  Not part of the public ABI (include/qk.h is).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qk.h"
+
+namespace qk {
+
+using cd = std::complex<double>;
+
+constexpr int kMaxQubits = 34;
+constexpr int kMaxBlockQubits = 14;
+constexpr int kMaxFusedQubits = 7;
+
+// ---------------------------------------------------------------- errors
+int fail(int code, const std::string& msg);   // sets the thread-local message
+int hip_fail(int hip_err, const char* what);  // maps a HIP error to QK_EDEVICE
+
+// ---------------------------------------------------------------- gates
+int kind_arity(uint32_t kind);
+int gate_class(uint32_t kind);                // 0..6, see qk.h
+bool kind_is_diagonal(uint32_t kind);
+// Row-major 2^k x 2^k matrix, index bit j <-> j-th listed qubit.
+void gate_unitary(const qk_gate& g, cd* U);
+
+// ---------------------------------------------------------------- device ops
+// One operation of a staged-block kernel.  Bits are block-local bit indices
+// (block bit j <-> the j-th smallest active physical qubit).
+enum OpCode : uint8_t {
+    OP_DENSE1 = 0,  // 2x2 matrix on bit b0: coef[0..3] row-major
+    OP_DIAG1 = 1,   // diag(coef[0], coef[1]) on bit b0
+    OP_X = 2,       // swap the halves of bit b0
+    OP_CX = 3,      // control b0, target b1
+    OP_CZ = 4,      // negate where b0 and b1 are set
+    OP_CPHASE = 5,  // multiply by coef[0] where b0 and b1 are set
+    OP_DIAG2 = 6,   // diag(coef[0..3]) indexed by bit(b0) + 2 bit(b1)
+    OP_SWAP = 7,    // exchange bits b0 and b1
+    OP_DENSEK = 8,  // 2^k x 2^k matrix on bits b[0..k-1] (sorted ascending)
+};
+
+struct Op {
+    uint8_t code;
+    uint8_t k;       // OP_DENSEK: number of bits
+    uint8_t b[7];    // block bits (b[0], b[1] for one/two-bit ops)
+    uint8_t pad;
+    uint32_t coef;   // offset of the first coefficient in the plan's table
+};
+static_assert(sizeof(Op) == 16, "Op layout");
+
+// Descriptor of one staged-block launch (passed by value).
+struct BlockDesc {
+    uint64_t nblocks;   // 2^(n - m)
+    int32_t n, m;       // state qubits, block qubits
+    int32_t ell0;       // act[j] == j for j < ell0 (contiguous low run)
+    int32_t n_ops;
+    uint8_t act[16];    // block bit j -> physical qubit, ascending
+};
+
+// Descriptor of one out-of-place permutation launch.
+struct PermDesc {
+    uint64_t nblocks;   // 2^(n - m)
+    int32_t n, m;
+    int32_t lo_src;     // src run: act_src[j] == j for j < lo_src
+    int32_t lo_dst;     // dst run: act_dst[j] == j for j < lo_dst
+    uint8_t act_src[16];   // ascending source-active qubits
+    uint8_t act_dst[16];   // ascending destination-active qubits (= perm of act_src)
+    uint8_t src_of_dst[16];// dest block bit j takes source block bit src_of_dst[j]
+    uint8_t perm[40];      // source bit b -> destination bit perm[b]
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return a hipError_t value (0 = ok).
+int launch_block(int dtype, void* psi, const BlockDesc& d, const Op* ops,
+                 const void* coef, void* stream);
+int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream);
+int launch_fill_basis(int dtype, void* psi, uint64_t N, uint64_t x, void* stream);
+// Reductions: partial buffer must hold at least reduce_partials() doubles x 2.
+int reduce_partials();
+int launch_norm2(int dtype, const void* psi, uint64_t N, double* partials, double* result, void* stream);
+int launch_overlap(int dtype, const void* psi, uint64_t offset, uint64_t count,
+                   const double* ref, double* partials, double* result, void* stream);
+int launch_gather(int dtype, const void* psi, const uint64_t* idx, uint64_t cnt,
+                  double* out, void* stream);
+size_t block_lds_bytes(int dtype, int m, int ell0);
+
+}  // namespace qk
+
+// ---------------------------------------------------------------- handles
+struct qk_ctx {
+    void* stream = nullptr;
+    bool host_only = false;
+    int device = -1;
+    // analytic tables keyed by (n, dtype); calibrated or set by the caller
+    std::vector<std::pair<int, qk_cost_tables>> tables;  // key = n*2 + dtype
+    // scratch
+    double* d_partials = nullptr;   // reduction partials (+ result)
+    void* d_stage = nullptr;        // staging buffer for host data
+    size_t stage_bytes = 0;
+    double* h_pinned = nullptr;     // small pinned host buffer for results
+};
+
+struct qk_state {
+    qk_ctx* ctx = nullptr;
+    int n = 0;
+    int dtype = 0;
+    void* psi = nullptr;
+    bool owned = false;
+    void* tmp = nullptr;            // permutation scratch (same size)
+    std::vector<int32_t> layout;    // layout[q] = physical bit of logical q
+};

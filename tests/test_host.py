@@ -1,0 +1,157 @@
+"""Host-side tests of libqk (no GPU): the C ABI exports every declared
+symbol, and the native planner (canonicalisation + OrderedKernelize) returns
+exactly the oracle's partition for the same cost tables."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+qk = pytest.importorskip("paper_2408_09055_amd")
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "qk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 30
+    lib = ctypes.CDLL(qk.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_defaults():
+    assert "gfx950" in qk.version()
+    ko = qk.kopts()
+    assert (ko.k_max, ko.m_max, ko.ell, ko.absorb_swaps) == (5, 12, 3, 1)
+
+
+@pytest.fixture(scope="module")
+def hctx():
+    return qk.Context(host_only=True)
+
+
+def _oracle_plan(circ, opts, tab):
+    gates, P = oracle.canonicalize(circ, absorb_swaps=opts.absorb_swaps)
+    cost, ks = oracle.ordered_kernelize(gates, opts, tab)
+    return gates, P, cost, ks
+
+
+def _native_plan(ctx, circ, opts, tab, dtype=qk.QK_C64):
+    ko = qk.kopts(dtype=dtype, k_max=opts.k_max, m_max=opts.m_max, ell=opts.ell,
+                  absorb_swaps=int(opts.absorb_swaps), allow_fused=int(opts.allow_fused),
+                  allow_lds=int(opts.allow_lds), block_qubits=max(opts.m_max, opts.k_max + 1),
+                  tables=(tab.fused, tab.alpha, tab.gate))
+    return qk.kernelize(ctx, circ, ko)
+
+
+def _rand_tables(rng, scale):
+    t = oracle.CostTables()
+    t.fused = [0] + sorted(int(x) for x in rng.integers(1, scale, 7))
+    t.alpha = int(rng.integers(0, scale))
+    t.gate = [int(x) for x in rng.integers(0, scale // 4 + 1, oracle.NUM_CLASSES)]
+    return t
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_native_dp_equals_oracle_random(seed, hctx):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 14))
+    circ = W.random_circuit(n, int(rng.integers(1, 120)), rng)
+    k_max = int(rng.integers(1, 8))
+    m_max = int(rng.integers(max(2, k_max), 15))
+    opts = oracle.KOpts(k_max=k_max, m_max=m_max, ell=int(rng.integers(1, m_max + 1)),
+                        allow_fused=bool(rng.integers(0, 2)) or True, allow_lds=bool(rng.integers(0, 2)),
+                        absorb_swaps=bool(rng.integers(0, 2)))
+    if opts.k_max < 2 and not opts.allow_lds:
+        opts.k_max = 2
+    tab = _rand_tables(rng, int(rng.choice([10, 1000, 10 ** 9])))
+    try:
+        gates, P, cost, ks = _oracle_plan(circ, opts, tab)
+    except ValueError:
+        # some gate fits neither kernel type: the library must refuse too
+        _expect(qk.QK_EINVAL, _native_plan, hctx, circ, opts, tab)
+        return
+    plan = _native_plan(hctx, circ, opts, tab)
+    assert plan.total_cost() == cost
+    assert [k.as_tuple() for k in plan.kernels()] == ks
+    assert plan.final_layout() == P
+    assert [plan.gate_source(i) for i in range(plan.num_gates())] == [g[2] for g in gates]
+    for k in plan.kernels():
+        mask = 0
+        for (_, qs, _) in gates[k.gate_begin:k.gate_end]:
+            for q in qs:
+                mask |= 1 << q
+        assert k.qubit_mask == mask and k.k == bin(mask).count("1")
+
+
+@pytest.mark.parametrize("name", ["qft20", "qft32", "rl28", "ghz32", "hea16"])
+def test_native_dp_equals_oracle_workloads(name, hctx):
+    circ = {"qft20": lambda: W.qft(20), "qft32": lambda: W.qft(32),
+            "rl28": lambda: W.random_layered(28, 20, 2), "ghz32": lambda: W.ghz(32),
+            "hea16": lambda: W.hea(16, 8, np.random.default_rng(4))}[name]()
+    rng = np.random.default_rng(len(name))
+    for opts in (oracle.KOpts(k_max=5, m_max=12, ell=3), oracle.KOpts(k_max=7, m_max=13, ell=4),
+                 oracle.KOpts(k_max=3, m_max=10, ell=1, allow_lds=False)):
+        tab = _rand_tables(rng, 10 ** 6)
+        gates, P, cost, ks = _oracle_plan(circ, opts, tab)
+        plan = _native_plan(hctx, circ, opts, tab)
+        assert plan.total_cost() == cost
+        assert [k.as_tuple() for k in plan.kernels()] == ks
+
+
+def test_default_tables_give_valid_plan(hctx):
+    circ = W.random_layered(24, 6, 9)
+    plan = qk.kernelize(hctx, circ, qk.kopts())
+    ks = plan.kernels()
+    assert ks[0].gate_begin == 0 and ks[-1].gate_end == plan.num_gates()
+    for a, b in zip(ks[:-1], ks[1:]):
+        assert a.gate_end == b.gate_begin
+    assert sum(k.cost_ps for k in ks) == plan.total_cost()
+
+
+def test_learned_request_without_weights_falls_back(hctx):
+    circ = W.qft(12)
+    a = qk.kernelize(hctx, circ, qk.kopts(cost_model=qk.QK_COST_ANALYTIC))
+    b = qk.kernelize(hctx, circ, qk.kopts(cost_model=qk.QK_COST_LEARNED))
+    assert [k.as_tuple() for k in a.kernels()] == [k.as_tuple() for k in b.kernels()]
+
+
+# ---------------------------------------------------------------- error paths
+def _expect(code, fn, *a):
+    with pytest.raises(qk.QkError) as ei:
+        fn(*a)
+    assert ei.value.code == code, str(ei.value)
+
+
+def test_error_paths(hctx):
+    bad_q = W.from_list(4, [W.gate(W.H, [4])])
+    _expect(qk.QK_EINVAL, qk.kernelize, hctx, bad_q, qk.kopts())
+    rep = W.from_list(4, [W.gate(W.CX, [1, 1])])
+    _expect(qk.QK_EINVAL, qk.kernelize, hctx, rep, qk.kopts())
+    wrong_nq = W.Circuit(4, np.array([(W.CX, 1, [0, 1, 0], 0, [0, 0, 0])], dtype=W.GATE_DTYPE))
+    _expect(qk.QK_EINVAL, qk.kernelize, hctx, wrong_nq, qk.kopts())
+    _expect(qk.QK_EINVAL, qk.kernelize, hctx, W.qft(3), qk.kopts(k_max=9))
+    _expect(qk.QK_EINVAL, qk.kernelize, hctx, W.Circuit(40, np.zeros(0, W.GATE_DTYPE)), qk.kopts())
+    _expect(qk.QK_EINVAL, qk.kernelize, hctx, W.qft(16), qk.kopts(dtype=qk.QK_C128, m_max=14))
+    # host-only contexts refuse device work
+    _expect(qk.QK_EDEVICE, qk.sv_alloc, hctx, 10)
+    plan = qk.kernelize(hctx, W.qft(4), qk.kopts())
+    assert len(plan) >= 1
+
+
+def test_empty_and_swap_only_circuits(hctx):
+    e = qk.kernelize(hctx, W.Circuit(5, np.zeros(0, W.GATE_DTYPE)), qk.kopts())
+    assert len(e) == 0 and e.total_cost() == 0
+    s = qk.kernelize(hctx, W.from_list(3, [W.gate(W.SWAP, [0, 2])]), qk.kopts())
+    assert len(s) == 0 and s.final_layout() == [2, 1, 0]
