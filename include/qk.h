@@ -124,6 +124,9 @@ int sv_init_basis(qk_state* st, uint64_t x);
 int sv_upload(qk_state* st, const void* host);
 /* Copy 2^n amplitudes to host.  QK_ESTATE unless the layout is logical. */
 int sv_download(qk_state* st, void* host);
+/* Copy all 2^n amplitudes to host in physical order, whatever the layout
+ * (checkpointing a state mid-plan together with sv_layout). */
+int sv_download_physical(qk_state* st, void* host);
 /* Copy amplitudes [offset, offset+count) (logical order) to host. */
 int sv_download_range(qk_state* st, uint64_t offset, uint64_t count, void* host);
 /* Bring the state back to logical order with one permutation pass (a no-op
@@ -172,7 +175,8 @@ typedef struct qk_kopts {
     int32_t cost_model;    /* QK_COST_ANALYTIC or QK_COST_LEARNED */
     int32_t k_max;         /* fused kernels: 1..7 qubits */
     int32_t m_max;         /* LDS kernels: active set bound, ell..14 */
-    int32_t ell;           /* lowest qubits forced into every LDS kernel, 1..m_max */
+    int32_t ell;           /* lowest qubits forced into every LDS kernel, 1..m_max;
+                              0 = 128-byte runs (4 for complex64, 3 for complex128) */
     int32_t absorb_swaps;  /* relabel SWAP gates into the layout instead of running them */
     int32_t allow_fused;
     int32_t allow_lds;
@@ -183,7 +187,7 @@ typedef struct qk_kopts {
                                       context's tables for (n, dtype) */
 } qk_kopts;
 
-/* Defaults: complex64, analytic, k_max 5, m_max 12, ell 3, swaps absorbed,
+/* Defaults: complex64, analytic, k_max 5, m_max 12, ell 0 (auto), swaps absorbed,
  * both kernel types, block_qubits 0, tables NULL. */
 void qk_kopts_default(qk_kopts* ko);
 

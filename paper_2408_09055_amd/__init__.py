@@ -3,7 +3,7 @@
 Thin ctypes binding over ``libqk.so`` (declared in ``include/qk.h``).  Every
 step of the simulation runs in the library's HIP kernels; this module only
 marshals arguments.  Importing it fails loudly when the library has not been
-built (``python -m paper_2408_09055_amd.build``).
+built (``python paper_2408_09055_amd/build.py``).
 
 PyTorch provides device memory and the stream: ``State.from_torch`` wraps a
 ``torch.complex64``/``complex128`` CUDA tensor, and contexts bind to
@@ -21,8 +21,13 @@ LIB_PATH = os.path.join(_HERE, "libqk.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"libqk.so not found at {LIB_PATH}: build it with `python -m paper_2408_09055_amd.build` "
+        f"libqk.so not found at {LIB_PATH}: build it with `python paper_2408_09055_amd/build.py` "
         "(there is no fallback implementation)")
+
+# libqk links libamdhip64.so.7.  Importing torch first makes the process use
+# torch's HIP runtime for both (one runtime per process); loading libqk first
+# would bring in a second runtime that cannot see the device torch holds.
+import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -79,6 +84,7 @@ _SIGS = {
     "sv_wrap": [_P, _P, ctypes.c_int, ctypes.c_int, _PP], "sv_free": [_P],
     "sv_device_ptr": [_P, _PP], "sv_info": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
     "sv_layout": [_P, _P], "sv_init_basis": [_P, _u64], "sv_upload": [_P, _P], "sv_download": [_P, _P],
+    "sv_download_physical": [_P, _P],
     "sv_download_range": [_P, _u64, _u64, _P], "sv_restore": [_P], "sv_permute": [_P, _P],
     "sv_norm2": [_P, _dbl_p], "sv_overlap_host": [_P, _P, _u64, _u64, _P],
     "sv_gather": [_P, _P, _u64, _P],
@@ -93,7 +99,11 @@ _SIGS = {
     "execute_plan": [_P, _P, _P],
 }
 for _name, _args in _SIGS.items():
-    _f = getattr(_lib, _name)
+    try:
+        _f = getattr(_lib, _name)
+    except AttributeError as _e:
+        raise ImportError(f"{LIB_PATH} lacks {_name}: it is older than the sources, rebuild it with "
+                          "`python paper_2408_09055_amd/build.py`") from _e
     _f.argtypes = _args
     _f.restype = ctypes.c_int
 _lib.qk_last_error.restype = ctypes.c_char_p
@@ -248,6 +258,11 @@ class State:
     def download(self) -> np.ndarray:
         out = np.empty(1 << self.n, self.np_dtype)
         _check(_lib.sv_download(self.h, out.ctypes.data))
+        return out
+
+    def download_physical(self) -> np.ndarray:
+        out = np.empty(1 << self.n, self.np_dtype)
+        _check(_lib.sv_download_physical(self.h, out.ctypes.data))
         return out
 
     def download_range(self, offset: int, count: int) -> np.ndarray:

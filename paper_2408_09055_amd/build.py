@@ -1,6 +1,6 @@
 """Build libqk.so (HIP for gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2408_09055_amd.build
+Usage: python paper_2408_09055_amd/build.py   (runs without importing the package)
 """
 from __future__ import annotations
 

@@ -149,7 +149,7 @@ void qk_kopts_default(qk_kopts* ko)
     ko->cost_model = QK_COST_ANALYTIC;
     ko->k_max = 5;
     ko->m_max = 12;
-    ko->ell = 3;
+    ko->ell = 0;
     ko->absorb_swaps = 1;
     ko->allow_fused = 1;
     ko->allow_lds = 1;
@@ -318,6 +318,15 @@ int sv_download_range(qk_state* st, uint64_t offset, uint64_t count, void* host)
                                   (hipStream_t)st->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "sv_download");
     return sync_stream(st->ctx, "sv_download");
+}
+
+int sv_download_physical(qk_state* st, void* host)
+{
+    if (!st || !host) return fail(QK_EINVAL, "sv_download_physical: null argument");
+    hipError_t e = hipMemcpyAsync(host, st->psi, amp_bytes(st->dtype) << st->n, hipMemcpyDeviceToHost,
+                                  (hipStream_t)st->ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "sv_download_physical");
+    return sync_stream(st->ctx, "sv_download_physical");
 }
 
 int sv_download(qk_state* st, void* host)
@@ -525,7 +534,8 @@ int apply_kernel(qk_ctx* ctx, const qk_plan* p, int64_t i, qk_state* st)
     // single stage: every kernel runs on the layout the plan started from
     if (!is_identity(st->layout)) return fail(QK_ESTATE, "apply_kernel: state layout differs from the plan's");
     const PKernel& K = p->kernels[i];
-    int e = launch_block(p->dtype, st->psi, K.desc, (const Op*)p->d_ops + K.op_off, p->d_coef, ctx->stream);
+    const int fused_k = K.type == QK_KERNEL_FUSED ? K.k : 0;
+    int e = launch_block(p->dtype, fused_k, st->psi, K.desc, (const Op*)p->d_ops + K.op_off, p->d_coef, ctx->stream);
     if (e) return hip_fail(e, "apply_kernel launch");
     return QK_OK;
 }

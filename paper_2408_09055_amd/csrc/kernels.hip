@@ -16,6 +16,8 @@
 //                 reductions with compensated sums and a fixed-order tree.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "qk_internal.hpp"
 
 namespace qk {
@@ -101,6 +103,7 @@ __device__ void op_dense1(C* sm, int m, int j, const C* __restrict__ u)
 {
     const C u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
     const uint32_t half = 1u << (m - 1);
+#pragma unroll 4
     for (uint32_t p = threadIdx.x; p < half; p += kNT) {
         const uint32_t r0 = ins0(p, j), r1 = r0 | (1u << j);
         const C a = sm[r0], b = sm[r1];
@@ -113,6 +116,7 @@ template <typename C>
 __device__ void op_diag1(C* sm, int m, int j, const C* __restrict__ u)
 {
     const C d1 = u[1], d0 = u[0];
+#pragma unroll 4
     for (uint32_t r = threadIdx.x; r < (1u << m); r += kNT)
         sm[r] = cmul(sm[r], ((r >> j) & 1u) ? d1 : d0);
 }
@@ -120,6 +124,7 @@ __device__ void op_diag1(C* sm, int m, int j, const C* __restrict__ u)
 template <typename C>
 __device__ void op_x(C* sm, int m, int j)
 {
+#pragma unroll 4
     for (uint32_t p = threadIdx.x; p < (1u << (m - 1)); p += kNT) {
         const uint32_t r0 = ins0(p, j), r1 = r0 | (1u << j);
         const C a = sm[r0];
@@ -138,6 +143,7 @@ __device__ __forceinline__ uint32_t ins00(uint32_t p, int a, int b)
 template <typename C>
 __device__ void op_cx(C* sm, int m, int c, int t)
 {
+#pragma unroll 4
     for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
         const uint32_t r0 = ins00(p, c, t) | (1u << c), r1 = r0 | (1u << t);
         const C a = sm[r0];
@@ -149,6 +155,7 @@ __device__ void op_cx(C* sm, int m, int c, int t)
 template <typename C>
 __device__ void op_cz(C* sm, int m, int a, int b)
 {
+#pragma unroll 4
     for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
         const uint32_t r = ins00(p, a, b) | (1u << a) | (1u << b);
         C v = sm[r];
@@ -162,6 +169,7 @@ template <typename C>
 __device__ void op_cphase(C* sm, int m, int a, int b, const C* __restrict__ u)
 {
     const C ph = u[0];
+#pragma unroll 4
     for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
         const uint32_t r = ins00(p, a, b) | (1u << a) | (1u << b);
         sm[r] = cmul(sm[r], ph);
@@ -172,6 +180,7 @@ template <typename C>
 __device__ void op_diag2(C* sm, int m, int a, int b, const C* __restrict__ u)
 {
     const C d0 = u[0], d1 = u[1], d2 = u[2], d3 = u[3];
+#pragma unroll 4
     for (uint32_t r = threadIdx.x; r < (1u << m); r += kNT) {
         const uint32_t s = ((r >> a) & 1u) | (((r >> b) & 1u) << 1);
         const C d = s == 0 ? d0 : s == 1 ? d1 : s == 2 ? d2 : d3;
@@ -182,6 +191,7 @@ __device__ void op_diag2(C* sm, int m, int a, int b, const C* __restrict__ u)
 template <typename C>
 __device__ void op_swap(C* sm, int m, int a, int b)
 {
+#pragma unroll 4
     for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
         const uint32_t base = ins00(p, a, b);
         const uint32_t r0 = base | (1u << a), r1 = base | (1u << b);
@@ -271,69 +281,133 @@ __device__ void op_densek_rows(C* sm, int m, const uint8_t* bits, const C* __res
     }
 }
 
-template <typename C>
-__device__ void op_densek(C* sm, int m, const Op& op, const C* __restrict__ U)
+// ----------------------------------------------------------- staged block kernel
+// Compile-time loop: f(integral_constant<int, I>) for I = 0..N-1.  Register
+// arrays indexed only through it keep constant indices from the start, so
+// they stay in VGPRs instead of being demoted to scratch.
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
 {
-    switch (op.k) {
-    case 1: op_densek_group<C, 1>(sm, m, op.b, U); break;
-    case 2: op_densek_group<C, 2>(sm, m, op.b, U); break;
-    case 3: op_densek_group<C, 3>(sm, m, op.b, U); break;
-    case 4: op_densek_group<C, 4>(sm, m, op.b, U); break;
-    case 5: op_densek_group<C, 5>(sm, m, op.b, U); break;
-    case 6: op_densek_rows<C, 6>(sm, m, op.b, U); break;
-    case 7: op_densek_rows<C, 7>(sm, m, op.b, U); break;
-    default: break;
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
     }
 }
 
-// ----------------------------------------------------------- staged block kernel
+// 16-byte register vector (a plain clang vector, which scalar replacement of
+// aggregates handles; HIP's uint4 is a union-based struct).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Maximum 16-byte chunks a thread moves per block: 2^m amplitudes / (16 B
+// chunks) / kNT threads, with m <= 13 (c64) or 12 (c128) -> 64 KiB per block.
+constexpr int kMaxChunks = 16;
+
 template <typename C>
-__global__ __launch_bounds__(kNT) void k_block(C* __restrict__ psi, BlockDesc d,
-                                               const Op* __restrict__ ops,
-                                               const C* __restrict__ coef)
+__device__ __forceinline__ uint64_t chunk_addr(uint64_t base, const SplitTab& tab, uint32_t r, int ell0, int nhi)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ SplitTab tab;
-    C* sm = reinterpret_cast<C*>(smem);
+    return base + split_off(tab, r >> ell0, nhi) + (r & ((1u << ell0) - 1u));
+}
+
+__device__ __forceinline__ uint64_t block_base(uint64_t blk, const uint8_t* act, int m)
+{
+    uint64_t base = blk;
+    for (int j = 0; j < m; ++j) base = ins0_64(base, act[j]);
+    return base;
+}
+
+// Persistent grid: each workgroup walks blocks blk, blk + G, ...; the next
+// block's loads are issued into registers before the current block's
+// operations run, so HBM latency overlaps LDS work.  `body(sm, m)` applies
+// the kernel's operations to the block in LDS and ends with a barrier.
+template <typename C, typename Body>
+__device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc& d, C* sm, SplitTab& tab, Body body)
+{
     const int m = d.m, ell0 = d.ell0, nhi = m - ell0;
     const int tid = threadIdx.x;
     build_split(tab, d.act + ell0, nhi, tid, kNT);
     constexpr int CH = 16 / sizeof(C);          // amplitudes per 16-byte access
     const uint32_t nch = (1u << m) / CH;
-    const uint32_t lomask = (1u << ell0) - 1u;
-    for (uint64_t blk = blockIdx.x; blk < d.nblocks; blk += gridDim.x) {
-        uint64_t base = blk;
-        for (int j = 0; j < m; ++j) base = ins0_64(base, d.act[j]);
+    __syncthreads();
+
+    uint64_t blk = blockIdx.x;
+    if (blk >= d.nblocks) return;
+    u32x4 buf[kMaxChunks];
+    uint64_t base = block_base(blk, d.act, m);
+    auto load_all = [&](uint64_t b0) {
+        static_for<0, kMaxChunks>([&](auto I) {
+            const uint32_t c = tid + (uint32_t)I.value * kNT;
+            if (c < nch) buf[I.value] = *reinterpret_cast<const u32x4*>(&psi[chunk_addr<C>(b0, tab, c * CH, ell0, nhi)]);
+        });
+    };
+    load_all(base);
+    for (;;) {
+        static_for<0, kMaxChunks>([&](auto I) {
+            const uint32_t c = tid + (uint32_t)I.value * kNT;
+            if (c < nch) *reinterpret_cast<u32x4*>(&sm[c * CH]) = buf[I.value];
+        });
         __syncthreads();
-        for (uint32_t c = tid; c < nch; c += kNT) {
-            const uint32_t r = c * CH;
-            const uint64_t a = base + split_off(tab, r >> ell0, nhi) + (r & lomask);
-            *reinterpret_cast<uint4*>(&sm[r]) = *reinterpret_cast<const uint4*>(&psi[a]);
-        }
-        __syncthreads();
+        const uint64_t next = blk + gridDim.x;
+        const uint64_t nbase = next < d.nblocks ? block_base(next, d.act, m) : 0;
+        if (next < d.nblocks) load_all(nbase);
+        body(sm, m);
+        static_for<0, kMaxChunks>([&](auto I) {
+            const uint32_t c = tid + (uint32_t)I.value * kNT;
+            if (c < nch)
+                *reinterpret_cast<u32x4*>(&psi[chunk_addr<C>(base, tab, c * CH, ell0, nhi)]) =
+                    *reinterpret_cast<const u32x4*>(&sm[c * CH]);
+        });
+        if (next >= d.nblocks) break;
+        blk = next;
+        base = nbase;
+        __syncthreads();   // all LDS reads of this block done before the next fill
+    }
+}
+
+// LDS gate-sequence kernel: the kernel's gates one by one on the staged block.
+template <typename C>
+__global__ __launch_bounds__(kNT) void k_block_seq(C* __restrict__ psi, BlockDesc d,
+                                                   const Op* __restrict__ ops,
+                                                   const C* __restrict__ coef)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ SplitTab tab;
+    C* sm = reinterpret_cast<C*>(smem);
+    block_loop(psi, d, sm, tab, [&](C* s, int m) {
         for (int o = 0; o < d.n_ops; ++o) {
             const Op op = ops[o];
             const C* u = coef + op.coef;
             switch (op.code) {
-            case OP_DENSE1: op_dense1(sm, m, op.b[0], u); break;
-            case OP_DIAG1: op_diag1(sm, m, op.b[0], u); break;
-            case OP_X: op_x(sm, m, op.b[0]); break;
-            case OP_CX: op_cx(sm, m, op.b[0], op.b[1]); break;
-            case OP_CZ: op_cz(sm, m, op.b[0], op.b[1]); break;
-            case OP_CPHASE: op_cphase(sm, m, op.b[0], op.b[1], u); break;
-            case OP_DIAG2: op_diag2(sm, m, op.b[0], op.b[1], u); break;
-            case OP_SWAP: op_swap(sm, m, op.b[0], op.b[1]); break;
-            case OP_DENSEK: op_densek(sm, m, op, u); break;
+            case OP_DENSE1: op_dense1(s, m, op.b[0], u); break;
+            case OP_DIAG1: op_diag1(s, m, op.b[0], u); break;
+            case OP_X: op_x(s, m, op.b[0]); break;
+            case OP_CX: op_cx(s, m, op.b[0], op.b[1]); break;
+            case OP_CZ: op_cz(s, m, op.b[0], op.b[1]); break;
+            case OP_CPHASE: op_cphase(s, m, op.b[0], op.b[1], u); break;
+            case OP_DIAG2: op_diag2(s, m, op.b[0], op.b[1], u); break;
+            case OP_SWAP: op_swap(s, m, op.b[0], op.b[1]); break;
             default: break;
             }
             __syncthreads();
         }
-        for (uint32_t c = tid; c < nch; c += kNT) {
-            const uint32_t r = c * CH;
-            const uint64_t a = base + split_off(tab, r >> ell0, nhi) + (r & lomask);
-            *reinterpret_cast<uint4*>(&psi[a]) = *reinterpret_cast<const uint4*>(&sm[r]);
-        }
-    }
+    });
+}
+
+// Fused kernel: one dense 2^K x 2^K product on the staged block.
+template <typename C, int K>
+__global__ __launch_bounds__(kNT) void k_block_dense(C* __restrict__ psi, BlockDesc d,
+                                                     const Op* __restrict__ ops,
+                                                     const C* __restrict__ coef)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ SplitTab tab;
+    C* sm = reinterpret_cast<C*>(smem);
+    const Op op = ops[0];
+    const C* U = coef + op.coef;
+    block_loop(psi, d, sm, tab, [&](C* s, int m) {
+        if constexpr (K <= 5) op_densek_group<C, K>(s, m, op.b, U);
+        else op_densek_rows<C, K>(s, m, op.b, U);
+        __syncthreads();
+    });
 }
 
 // ----------------------------------------------------------- permutation pass
@@ -493,36 +567,79 @@ size_t block_lds_bytes(int dtype, int m, int /*ell0*/)
     return (size_t)(dtype == QK_C128 ? 16 : 8) << m;
 }
 
-// Dynamic LDS of up to 64 KiB plus the static tables exceeds the default
-// per-launch limit, so raise it once per kernel instantiation.
-template <typename F>
-void allow_lds(F* f)
+// Per-kernel launch facts, cached by kernel address: the dynamic-LDS limit is
+// raised once (64 KiB of block plus the static tables exceeds the default),
+// and the number of resident workgroups on the device is queried once per
+// (kernel, LDS size).
+struct KernelFacts {
+    const void* f;
+    size_t lds;
+    int occ;
+};
+
+uint64_t resident_groups(const void* f, size_t lds)
 {
-    static bool done = false;
-    if (!done) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  96 * 1024);
-        done = true;
+    static int cus = 0;
+    static KernelFacts cache[64];
+    static int ncache = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 256;
+    }
+    for (int i = 0; i < ncache; ++i)
+        if (cache[i].f == f && cache[i].lds == lds) return (uint64_t)cache[i].occ * cus;
+    bool seen = false;
+    for (int i = 0; i < ncache; ++i) seen |= cache[i].f == f;
+    if (!seen) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, kNT, lds) != hipSuccess || occ <= 0) occ = 1;
+    if (ncache < 64) cache[ncache++] = KernelFacts{f, lds, occ};
+    return (uint64_t)occ * cus;
+}
+
+template <typename C, typename F>
+int launch_one(F* f, C* psi, const BlockDesc& d, const Op* ops, const void* coef, size_t lds, hipStream_t s)
+{
+    const uint64_t res = resident_groups(reinterpret_cast<const void*>(f), lds);
+    const dim3 grid((uint32_t)std::min<uint64_t>(d.nblocks, res)), block(kNT);
+    hipLaunchKernelGGL(f, grid, block, lds, s, psi, d, ops, (const C*)coef);
+    return (int)hipGetLastError();
+}
+
+template <typename C>
+int launch_typed(int fused_k, void* psi, const BlockDesc& d, const Op* ops, const void* coef, size_t lds,
+                 hipStream_t s)
+{
+    C* p = (C*)psi;
+    switch (fused_k) {
+    case 0: return launch_one<C>(k_block_seq<C>, p, d, ops, coef, lds, s);
+    case 1: return launch_one<C>(k_block_dense<C, 1>, p, d, ops, coef, lds, s);
+    case 2: return launch_one<C>(k_block_dense<C, 2>, p, d, ops, coef, lds, s);
+    case 3: return launch_one<C>(k_block_dense<C, 3>, p, d, ops, coef, lds, s);
+    case 4: return launch_one<C>(k_block_dense<C, 4>, p, d, ops, coef, lds, s);
+    case 5: return launch_one<C>(k_block_dense<C, 5>, p, d, ops, coef, lds, s);
+    case 6: return launch_one<C>(k_block_dense<C, 6>, p, d, ops, coef, lds, s);
+    case 7: return launch_one<C>(k_block_dense<C, 7>, p, d, ops, coef, lds, s);
+    default: return (int)hipErrorInvalidValue;
     }
 }
 
-int launch_block(int dtype, void* psi, const BlockDesc& d, const Op* ops, const void* coef, void* stream)
+int launch_block(int dtype, int fused_k, void* psi, const BlockDesc& d, const Op* ops, const void* coef,
+                 void* stream)
 {
     const size_t lds = block_lds_bytes(dtype, d.m, d.ell0);
-    if (dtype == QK_C128) allow_lds(k_block<double2>); else allow_lds(k_block<float2>);
-    const dim3 grid(grid_for(d.nblocks)), block(kNT);
     hipStream_t s = (hipStream_t)stream;
-    if (dtype == QK_C128)
-        hipLaunchKernelGGL(k_block<double2>, grid, block, lds, s, (double2*)psi, d, ops, (const double2*)coef);
-    else
-        hipLaunchKernelGGL(k_block<float2>, grid, block, lds, s, (float2*)psi, d, ops, (const float2*)coef);
-    return (int)hipGetLastError();
+    if (dtype == QK_C128) return launch_typed<double2>(fused_k, psi, d, ops, coef, lds, s);
+    return launch_typed<float2>(fused_k, psi, d, ops, coef, lds, s);
 }
 
 int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream)
 {
     const size_t lds = (size_t)(dtype == QK_C128 ? 16 : 8) << d.m;
-    if (dtype == QK_C128) allow_lds(k_permute<double2>); else allow_lds(k_permute<float2>);
+    if (dtype == QK_C128) (void)resident_groups(reinterpret_cast<const void*>(k_permute<double2>), lds);
+    else (void)resident_groups(reinterpret_cast<const void*>(k_permute<float2>), lds);
     const dim3 grid(grid_for(d.nblocks)), block(kNT);
     hipStream_t s = (hipStream_t)stream;
     if (dtype == QK_C128)

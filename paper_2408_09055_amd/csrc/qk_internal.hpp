@@ -75,7 +75,8 @@ struct PermDesc {
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return a hipError_t value (0 = ok).
-int launch_block(int dtype, void* psi, const BlockDesc& d, const Op* ops,
+// fused_k = 0: LDS gate sequence (ops[0..n_ops)); 1..7: one dense product.
+int launch_block(int dtype, int fused_k, void* psi, const BlockDesc& d, const Op* ops,
                  const void* coef, void* stream);
 int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream);
 int launch_fill_basis(int dtype, void* psi, uint64_t N, uint64_t x, void* stream);

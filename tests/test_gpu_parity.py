@@ -205,17 +205,8 @@ def test_permutation_pass_bit_exact(ctx, dtype):
 
 
 def _raw_download(st):
-    """Device bytes in physical order (torch copy; no layout check)."""
-    import ctypes
-    import torch
-    nbytes = (1 << st.n) * (8 if st.dtype == qk.QK_C64 else 16)
-    out = np.empty(1 << st.n, st.np_dtype)
-    torch.cuda.synchronize()
-    hip = ctypes.CDLL("libamdhip64.so")
-    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-    rc = hip.hipMemcpy(out.ctypes.data, ctypes.c_void_p(st.device_ptr()), nbytes, 2)
-    assert rc == 0
-    return out
+    """Device amplitudes in physical order (no layout check)."""
+    return st.download_physical()
 
 
 def test_swap_absorption_matches_executed_swaps(ctx):
