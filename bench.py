@@ -58,7 +58,8 @@ def run_gpu(args):
         cm = qk.QK_COST_ANALYTIC if model == "analytic" else qk.QK_COST_LEARNED
         for name, circ, _ in circuits:
             t0 = time.perf_counter()
-            plans[(model, name)] = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, cost_model=cm))
+            plans[(model, name)] = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, cost_model=cm, k_max=args.k_max,
+                                                                    m_max=args.m_max, ell=args.ell))
             kern_s[(model, name)] = time.perf_counter() - t0
 
     amp_bytes = 8
@@ -153,6 +154,9 @@ def main():
     ap.add_argument("--qubits", type=int, default=32)
     ap.add_argument("--cost", default="analytic", choices=["analytic", "learned", "both"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--k-max", type=int, default=None)
+    ap.add_argument("--m-max", type=int, default=None)
+    ap.add_argument("--ell", type=int, default=None)
     ap.add_argument("--cpu-sample-qubits", type=int, default=26)
     ap.add_argument("--cpu-sample-gates", type=int, default=24)
     args = ap.parse_args()

@@ -174,9 +174,10 @@ typedef struct qk_kopts {
     int32_t dtype;         /* QK_C64 or QK_C128: the state the plan runs on */
     int32_t cost_model;    /* QK_COST_ANALYTIC or QK_COST_LEARNED */
     int32_t k_max;         /* fused kernels: 1..7 qubits */
-    int32_t m_max;         /* LDS kernels: active set bound, ell..14 */
+    int32_t m_max;         /* LDS kernels: active set bound, ell..14;
+                              0 = 13 for complex64, 12 for complex128 (64 KiB blocks) */
     int32_t ell;           /* lowest qubits forced into every LDS kernel, 1..m_max;
-                              0 = 128-byte runs (4 for complex64, 3 for complex128) */
+                              0 = 1 KiB runs (7 for complex64, 6 for complex128) */
     int32_t absorb_swaps;  /* relabel SWAP gates into the layout instead of running them */
     int32_t allow_fused;
     int32_t allow_lds;
@@ -187,7 +188,7 @@ typedef struct qk_kopts {
                                       context's tables for (n, dtype) */
 } qk_kopts;
 
-/* Defaults: complex64, analytic, k_max 5, m_max 12, ell 0 (auto), swaps absorbed,
+/* Defaults: complex64, analytic, k_max 5, m_max 0 (auto), ell 0 (auto), swaps absorbed,
  * both kernel types, block_qubits 0, tables NULL. */
 void qk_kopts_default(qk_kopts* ko);
 

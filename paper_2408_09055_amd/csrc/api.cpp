@@ -148,7 +148,7 @@ void qk_kopts_default(qk_kopts* ko)
     ko->dtype = QK_C64;
     ko->cost_model = QK_COST_ANALYTIC;
     ko->k_max = 5;
-    ko->m_max = 12;
+    ko->m_max = 0;
     ko->ell = 0;
     ko->absorb_swaps = 1;
     ko->allow_fused = 1;

@@ -69,32 +69,14 @@ __device__ __forceinline__ C czero()
     return r;
 }
 
-// Split offset tables: an index h over `nb` bits maps to
-// tab_lo[h & lomask] + tab_hi[h >> nlo]; each table has at most 128 entries.
-struct SplitTab {
-    uint64_t lo[128];
-    uint64_t hi[128];
-};
-
-__device__ __forceinline__ void build_split(SplitTab& t, const uint8_t* qubits, int nb, int tid, int nt)
+// Scatter the bits of a block-local index r onto physical qubit positions:
+// bit j of r goes to bit act[j] of the amplitude index.
+__device__ __forceinline__ uint64_t deposit(uint32_t r, const uint8_t* act, int m)
 {
-    const int nlo = nb / 2, nhi = nb - nlo;
-    for (int h = tid; h < (1 << nlo); h += nt) {
-        uint64_t o = 0;
-        for (int j = 0; j < nlo; ++j) if ((h >> j) & 1) o |= 1ull << qubits[j];
-        t.lo[h] = o;
-    }
-    for (int h = tid; h < (1 << nhi); h += nt) {
-        uint64_t o = 0;
-        for (int j = 0; j < nhi; ++j) if ((h >> j) & 1) o |= 1ull << qubits[nlo + j];
-        t.hi[h] = o;
-    }
-}
-
-__device__ __forceinline__ uint64_t split_off(const SplitTab& t, uint32_t h, int nb)
-{
-    const int nlo = nb / 2;
-    return t.lo[h & ((1u << nlo) - 1u)] + t.hi[h >> nlo];
+    uint64_t o = 0;
+    for (int j = 0; j < m; ++j)
+        if ((r >> j) & 1u) o |= 1ull << act[j];
+    return o;
 }
 
 // ----------------------------------------------------------- block operations
@@ -302,12 +284,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // chunks) / kNT threads, with m <= 13 (c64) or 12 (c128) -> 64 KiB per block.
 constexpr int kMaxChunks = 16;
 
-template <typename C>
-__device__ __forceinline__ uint64_t chunk_addr(uint64_t base, const SplitTab& tab, uint32_t r, int ell0, int nhi)
-{
-    return base + split_off(tab, r >> ell0, nhi) + (r & ((1u << ell0) - 1u));
-}
-
 __device__ __forceinline__ uint64_t block_base(uint64_t blk, const uint8_t* act, int m)
 {
     uint64_t base = blk;
@@ -319,24 +295,33 @@ __device__ __forceinline__ uint64_t block_base(uint64_t blk, const uint8_t* act,
 // block's loads are issued into registers before the current block's
 // operations run, so HBM latency overlaps LDS work.  `body(sm, m)` applies
 // the kernel's operations to the block in LDS and ends with a barrier.
+//
+// Thread t moves the 16-byte chunks c = t + i * kNT (i < kMaxChunks) of the
+// block.  The chunk's block-local index r = c * CH splits into disjoint bit
+// fields owned by t and by i, so its amplitude offset is
+// deposit(t part) + deposit(i part): one per-thread value plus a value that is
+// uniform across the workgroup.
 template <typename C, typename Body>
-__device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc& d, C* sm, SplitTab& tab, Body body)
+__device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc& d, C* sm, Body body)
 {
-    const int m = d.m, ell0 = d.ell0, nhi = m - ell0;
+    const int m = d.m;
     const int tid = threadIdx.x;
-    build_split(tab, d.act + ell0, nhi, tid, kNT);
     constexpr int CH = 16 / sizeof(C);          // amplitudes per 16-byte access
     const uint32_t nch = (1u << m) / CH;
-    __syncthreads();
+    const uint64_t off_t = deposit((uint32_t)tid * CH, d.act, m);
+    uint64_t off_i[kMaxChunks];
+    static_for<0, kMaxChunks>([&](auto I) {
+        off_i[I.value] = deposit((uint32_t)I.value * kNT * CH, d.act, m);
+    });
 
     uint64_t blk = blockIdx.x;
     if (blk >= d.nblocks) return;
     u32x4 buf[kMaxChunks];
-    uint64_t base = block_base(blk, d.act, m);
+    uint64_t base = block_base(blk, d.act, m) + off_t;
     auto load_all = [&](uint64_t b0) {
         static_for<0, kMaxChunks>([&](auto I) {
             const uint32_t c = tid + (uint32_t)I.value * kNT;
-            if (c < nch) buf[I.value] = *reinterpret_cast<const u32x4*>(&psi[chunk_addr<C>(b0, tab, c * CH, ell0, nhi)]);
+            if (c < nch) buf[I.value] = *reinterpret_cast<const u32x4*>(&psi[b0 + off_i[I.value]]);
         });
     };
     load_all(base);
@@ -347,14 +332,13 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
         });
         __syncthreads();
         const uint64_t next = blk + gridDim.x;
-        const uint64_t nbase = next < d.nblocks ? block_base(next, d.act, m) : 0;
+        const uint64_t nbase = next < d.nblocks ? block_base(next, d.act, m) + off_t : 0;
         if (next < d.nblocks) load_all(nbase);
         body(sm, m);
         static_for<0, kMaxChunks>([&](auto I) {
             const uint32_t c = tid + (uint32_t)I.value * kNT;
             if (c < nch)
-                *reinterpret_cast<u32x4*>(&psi[chunk_addr<C>(base, tab, c * CH, ell0, nhi)]) =
-                    *reinterpret_cast<const u32x4*>(&sm[c * CH]);
+                *reinterpret_cast<u32x4*>(&psi[base + off_i[I.value]]) = *reinterpret_cast<const u32x4*>(&sm[c * CH]);
         });
         if (next >= d.nblocks) break;
         blk = next;
@@ -370,9 +354,8 @@ __global__ __launch_bounds__(kNT) void k_block_seq(C* __restrict__ psi, BlockDes
                                                    const C* __restrict__ coef)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ SplitTab tab;
     C* sm = reinterpret_cast<C*>(smem);
-    block_loop(psi, d, sm, tab, [&](C* s, int m) {
+    block_loop(psi, d, sm, [&](C* s, int m) {
         for (int o = 0; o < d.n_ops; ++o) {
             const Op op = ops[o];
             const C* u = coef + op.coef;
@@ -399,11 +382,10 @@ __global__ __launch_bounds__(kNT) void k_block_dense(C* __restrict__ psi, BlockD
                                                      const C* __restrict__ coef)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ SplitTab tab;
     C* sm = reinterpret_cast<C*>(smem);
     const Op op = ops[0];
     const C* U = coef + op.coef;
-    block_loop(psi, d, sm, tab, [&](C* s, int m) {
+    block_loop(psi, d, sm, [&](C* s, int m) {
         if constexpr (K <= 5) op_densek_group<C, K>(s, m, op.b, U);
         else op_densek_rows<C, K>(s, m, op.b, U);
         __syncthreads();
@@ -411,17 +393,16 @@ __global__ __launch_bounds__(kNT) void k_block_dense(C* __restrict__ psi, BlockD
 }
 
 // ----------------------------------------------------------- permutation pass
+// Tile = the 2^m amplitudes with fixed source bits outside act_src.  Reads
+// use the source run (lo_src low bits contiguous), writes the destination run.
+// Same persistent, register-prefetched structure as block_loop.
 template <typename C>
 __global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* __restrict__ dst, PermDesc d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ SplitTab tsrc, tdst;
     __shared__ uint16_t rlo[128], rhi[128];   // dest-local index -> source-local index
     C* sm = reinterpret_cast<C*>(smem);
     const int m = d.m, tid = threadIdx.x;
-    const int nhs = m - d.lo_src, nhd = m - d.lo_dst;
-    build_split(tsrc, d.act_src + d.lo_src, nhs, tid, kNT);
-    build_split(tdst, d.act_dst + d.lo_dst, nhd, tid, kNT);
     const int nlo = m / 2, nhi = m - nlo;
     for (int h = tid; h < (1 << nlo); h += kNT) {
         uint32_t r = 0;
@@ -435,30 +416,56 @@ __global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* _
     }
     constexpr int CH = 16 / sizeof(C);
     const uint32_t nch = (1u << m) / CH;
-    const uint32_t ms = (1u << d.lo_src) - 1u, md = (1u << d.lo_dst) - 1u;
-    for (uint64_t blk = blockIdx.x; blk < d.nblocks; blk += gridDim.x) {
-        uint64_t sb = blk;
-        for (int j = 0; j < m; ++j) sb = ins0_64(sb, d.act_src[j]);
+    const uint64_t soff_t = deposit((uint32_t)tid * CH, d.act_src, m);
+    const uint64_t doff_t = deposit((uint32_t)tid * CH, d.act_dst, m);
+    uint64_t soff_i[kMaxChunks], doff_i[kMaxChunks];
+    static_for<0, kMaxChunks>([&](auto I) {
+        soff_i[I.value] = deposit((uint32_t)I.value * kNT * CH, d.act_src, m);
+        doff_i[I.value] = deposit((uint32_t)I.value * kNT * CH, d.act_dst, m);
+    });
+    auto dest_base = [&](uint64_t sb) {
         uint64_t db = 0;
         for (int b = 0; b < d.n; ++b) if ((sb >> b) & 1) db |= 1ull << d.perm[b];
+        return db;
+    };
+    __syncthreads();
+    uint64_t blk = blockIdx.x;
+    if (blk >= d.nblocks) return;
+    u32x4 buf[kMaxChunks];
+    uint64_t sb = block_base(blk, d.act_src, m);
+    auto load_all = [&](uint64_t b0) {
+        static_for<0, kMaxChunks>([&](auto I) {
+            const uint32_t c = tid + (uint32_t)I.value * kNT;
+            if (c < nch) buf[I.value] = *reinterpret_cast<const u32x4*>(&src[b0 + soff_t + soff_i[I.value]]);
+        });
+    };
+    load_all(sb);
+    for (;;) {
+        static_for<0, kMaxChunks>([&](auto I) {
+            const uint32_t c = tid + (uint32_t)I.value * kNT;
+            if (c < nch) *reinterpret_cast<u32x4*>(&sm[c * CH]) = buf[I.value];
+        });
         __syncthreads();
-        for (uint32_t c = tid; c < nch; c += kNT) {
-            const uint32_t r = c * CH;
-            const uint64_t a = sb + split_off(tsrc, r >> d.lo_src, nhs) + (r & ms);
-            *reinterpret_cast<uint4*>(&sm[r]) = *reinterpret_cast<const uint4*>(&src[a]);
-        }
-        __syncthreads();
-        for (uint32_t c = tid; c < nch; c += kNT) {
-            const uint32_t s = c * CH;
-            union { C v[CH]; uint4 w; } u;
+        const uint64_t db = dest_base(sb);
+        const uint64_t next = blk + gridDim.x;
+        const uint64_t nsb = next < d.nblocks ? block_base(next, d.act_src, m) : 0;
+        if (next < d.nblocks) load_all(nsb);
+        static_for<0, kMaxChunks>([&](auto I) {
+            const uint32_t c = tid + (uint32_t)I.value * kNT;
+            if (c < nch) {
+                union { C v[CH]; u32x4 w; } u;
 #pragma unroll
-            for (int e = 0; e < CH; ++e) {
-                const uint32_t se = s + e;
-                u.v[e] = sm[rlo[se & ((1u << nlo) - 1u)] | rhi[se >> nlo]];
+                for (int e = 0; e < CH; ++e) {
+                    const uint32_t se = c * CH + e;
+                    u.v[e] = sm[rlo[se & ((1u << nlo) - 1u)] | rhi[se >> nlo]];
+                }
+                *reinterpret_cast<u32x4*>(&dst[db + doff_t + doff_i[I.value]]) = u.w;
             }
-            const uint64_t a = db + split_off(tdst, s >> d.lo_dst, nhd) + (s & md);
-            *reinterpret_cast<uint4*>(&dst[a]) = u.w;
-        }
+        });
+        if (next >= d.nblocks) break;
+        blk = next;
+        sb = nsb;
+        __syncthreads();
     }
 }
 
@@ -638,14 +645,16 @@ int launch_block(int dtype, int fused_k, void* psi, const BlockDesc& d, const Op
 int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream)
 {
     const size_t lds = (size_t)(dtype == QK_C128 ? 16 : 8) << d.m;
-    if (dtype == QK_C128) (void)resident_groups(reinterpret_cast<const void*>(k_permute<double2>), lds);
-    else (void)resident_groups(reinterpret_cast<const void*>(k_permute<float2>), lds);
-    const dim3 grid(grid_for(d.nblocks)), block(kNT);
     hipStream_t s = (hipStream_t)stream;
-    if (dtype == QK_C128)
-        hipLaunchKernelGGL(k_permute<double2>, grid, block, lds, s, (const double2*)src, (double2*)dst, d);
-    else
-        hipLaunchKernelGGL(k_permute<float2>, grid, block, lds, s, (const float2*)src, (float2*)dst, d);
+    if (dtype == QK_C128) {
+        const uint64_t res = resident_groups(reinterpret_cast<const void*>(k_permute<double2>), lds);
+        hipLaunchKernelGGL(k_permute<double2>, dim3((uint32_t)std::min<uint64_t>(d.nblocks, res)), dim3(kNT), lds, s,
+                           (const double2*)src, (double2*)dst, d);
+    } else {
+        const uint64_t res = resident_groups(reinterpret_cast<const void*>(k_permute<float2>), lds);
+        hipLaunchKernelGGL(k_permute<float2>, dim3((uint32_t)std::min<uint64_t>(d.nblocks, res)), dim3(kNT), lds, s,
+                           (const float2*)src, (float2*)dst, d);
+    }
     return (int)hipGetLastError();
 }
 

@@ -177,8 +177,10 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
     if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) return fail(QK_EINVAL, "kernelize: bad gate array");
     if (ko.dtype != QK_C64 && ko.dtype != QK_C128) return fail(QK_EINVAL, "kernelize: bad dtype");
     if (ko.k_max < 1 || ko.k_max > kMaxFusedQubits) return fail(QK_EINVAL, "kernelize: k_max must be 1..7");
-    // ell = 0 selects 128-byte runs: 16 complex64 or 8 complex128 amplitudes
-    if (ko.ell == 0) ko.ell = ko.dtype == QK_C64 ? 4 : 3;
+    // 0 selects the defaults: blocks of 64 KiB (2^13 complex64 or 2^12
+    // complex128 amplitudes) whose low run is 1 KiB (7 or 6 low qubits)
+    if (ko.m_max == 0) ko.m_max = ko.dtype == QK_C64 ? 13 : 12;
+    if (ko.ell == 0) ko.ell = ko.dtype == QK_C64 ? 7 : 6;
     if (ko.ell < 1 || ko.ell > ko.m_max) return fail(QK_EINVAL, "kernelize: ell must be 1..m_max");
     if (ko.m_max < 2 || ko.m_max > kMaxBlockQubits) return fail(QK_EINVAL, "kernelize: m_max must be 2..14");
     if (!ko.allow_fused && !ko.allow_lds) return fail(QK_EINVAL, "kernelize: no kernel type allowed");

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_defaults():
     assert "gfx950" in qk.version()
     ko = qk.kopts()
-    assert (ko.k_max, ko.m_max, ko.ell, ko.absorb_swaps) == (5, 12, 0, 1)
+    assert (ko.k_max, ko.m_max, ko.ell, ko.absorb_swaps) == (5, 0, 0, 1)
 
 
 @pytest.fixture(scope="module")
