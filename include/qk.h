@@ -183,7 +183,7 @@ typedef struct qk_kopts {
     int32_t allow_lds;
     int32_t block_qubits;  /* amplitudes per staged block = 2^block_qubits
                               (>= m_max and >= k_max; 0 = m_max) */
-    int32_t learned_flags; /* out: 1 if a learned request fell back to analytic */
+    int32_t reserved;      /* must be 0 */
     const qk_cost_tables* tables;  /* explicit analytic tables, or NULL for the
                                       context's tables for (n, dtype) */
 } qk_kopts;
@@ -219,6 +219,10 @@ int plan_num_gates(const qk_plan* p, int64_t* out);
 int plan_gate_source(const qk_plan* p, int64_t i, int64_t* out);
 /* Layout after the last kernel: perm[q] = physical bit of logical qubit q. */
 int plan_final_layout(const qk_plan* p, int32_t* perm);
+/* Which cost model priced the plan: learned_used = 1 if the learned model's
+ * predictions were used, learned_fallback = 1 if the learned model was
+ * requested but no weights were loaded (analytic costs were used instead). */
+int plan_cost_model(const qk_plan* p, int* learned_used, int* learned_fallback);
 int plan_free(qk_plan* p);
 
 /* ---- execution (Execute on one GPU) ------------------------------------- */
@@ -235,6 +239,76 @@ int plan_finish(qk_ctx* ctx, const qk_plan* p, qk_state* st);
 int simulate(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_state* st);
 /* Enqueue all kernels of p and plan_finish, without re-planning. */
 int execute_plan(qk_ctx* ctx, const qk_plan* p, qk_state* st);
+
+/* ---- cost models -----------------------------------------------------------
+ * Analytic tables are kept per (n_qubits, dtype) in the context; kernelize uses
+ * them when qk_kopts.tables is NULL, and a built-in bandwidth model otherwise. */
+int qk_ctx_set_tables(qk_ctx* ctx, int n_qubits, int dtype, const qk_cost_tables* t);
+/* Tables kernelize would use for (n, dtype); *is_default = 1 when they are the
+ * built-in model rather than calibrated or set ones (is_default may be NULL). */
+int qk_ctx_get_tables(qk_ctx* ctx, int n_qubits, int dtype, qk_cost_tables* out, int* is_default);
+/* Measure the analytic constants on the device following the paper's
+ * experimental setup: fused kernels timed per qubit count k = 1..7 (three
+ * qubit placements averaged), an empty LDS kernel for alpha, and each gate
+ * class inside an LDS kernel (16 gates, alpha subtracted).  Allocates and
+ * frees a temporary 2^n state; stores the tables in the context and copies
+ * them to out (may be NULL).  n must be 14..34; reps = timed repetitions. */
+int costmodel_calibrate(qk_ctx* ctx, int n_qubits, int dtype, int reps, qk_cost_tables* out);
+
+/* A plan with exactly one kernel of the given type (QK_KERNEL_FUSED/LDS)
+ * covering the whole circuit; QK_EINVAL if infeasible for that type.  Used to
+ * time candidate kernels for the learned model. */
+int kernelize_single(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, int type, qk_plan** out);
+#define QK_NUM_FEATURES 20
+/* Feature vector of kernel i (QK_NUM_FEATURES floats): k, gate count,
+ * class histogram (7), min/max/mean physical qubit, qubits below 6, diagonal
+ * gates, fused one-hot, LDS one-hot, n, complex128 flag, k * fused,
+ * gate count * LDS. */
+int plan_kernel_features(const qk_plan* p, int64_t i, float* out);
+/* Launch kernel i of p on st once untimed, then reps times between HIP events
+ * on the context's stream; *median_ms = median duration.  The state's
+ * contents are changed (the kernel is applied reps + 1 times). */
+int time_kernel(qk_ctx* ctx, const qk_plan* p, int64_t i, qk_state* st, int reps, double* median_ms);
+
+/* Learned model: MLP with QK_NUM_FEATURES inputs, two hidden ReLU layers of 64
+ * and one output, FP32, predicting log(picoseconds per amplitude); trained
+ * on the device by libqk's own forward, backward and Adam kernels. */
+typedef struct qk_train_opts {
+    int32_t epochs;      /* default 200 */
+    int32_t batch;       /* default 256 */
+    float lr;            /* Adam step size, default 1e-3 */
+    float val_frac;      /* held-out fraction, default 0.2 */
+    uint64_t seed;       /* shuffling and initialisation */
+} qk_train_opts;
+typedef struct qk_train_report {
+    float train_mse, val_mse;     /* on standardised targets */
+    double train_mape, val_mape;  /* mean |predicted - measured| / measured time */
+    int64_t n_train, n_val;
+} qk_train_report;
+/* Train on count rows (feats: count x QK_NUM_FEATURES, targets: log ps per
+ * amplitude) and install the model for dtype in the context.  opts may be
+ * NULL for defaults. */
+int costmodel_train(qk_ctx* ctx, int dtype, const float* feats, const float* targets, int64_t count,
+                    const qk_train_opts* opts, qk_train_report* report);
+/* Text file with the standardisation, parameters and an FNV-1a checksum;
+ * load rejects a malformed or corrupted file with QK_EINVAL (the context then
+ * keeps whatever model it had). */
+int costmodel_save(qk_ctx* ctx, int dtype, const char* path);
+int costmodel_load(qk_ctx* ctx, int dtype, const char* path);
+int costmodel_unload(qk_ctx* ctx, int dtype);
+int costmodel_loaded(qk_ctx* ctx, int dtype, int* out);
+/* Predicted log(ps per amplitude) for cnt feature rows (device forward pass). */
+int costmodel_predict(qk_ctx* ctx, int dtype, const float* feats, int64_t cnt, float* out);
+/* Raw network pieces, for checking the device gradients: parameter count, and
+ * one forward (+ backward when t != NULL) pass of B rows with the flat
+ * parameter vector params (W1[20][64], b1[64], W2[64][64], b2[64], W3[64],
+ * b3); y, loss and grads may each be NULL. */
+int mlp_num_params(void);
+int mlp_forward_backward(qk_ctx* ctx, const float* params, const float* x, const float* t, int64_t B,
+                         float* y, float* loss, float* grads);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected at step),
+ * updating params, m and v in place (host arrays of mlp_num_params floats). */
+int mlp_adam_step(qk_ctx* ctx, float* params, const float* grads, float* m, float* v, float lr, int step);
 
 #ifdef __cplusplus
 }

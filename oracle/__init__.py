@@ -354,6 +354,34 @@ def ordered_kernelize(gates, opts: KOpts, tab: CostTables):
     return best[m][0], kernels
 
 
+def ordered_kernelize_fn(gates, cost_fn):
+    """OrderedKernelize with an arbitrary segment cost: cost_fn(segment) ->
+    (cost, type), cost INF when infeasible.  Same recurrence and tie order as
+    ``ordered_kernelize``; used with the learned model's costs."""
+    m = len(gates)
+    best = [(0, 0)] + [(INF, 0)] * m
+    back = [None] * (m + 1)
+    for i in range(m):
+        for j in range(i, -1, -1):
+            c, t = cost_fn(gates[j:i + 1])
+            if c >= INF:
+                continue
+            cand = (best[j][0] + c, best[j][1] + 1)
+            if cand < best[i + 1]:
+                best[i + 1] = cand
+                back[i + 1] = (j, t, c)
+        if back[i + 1] is None:
+            raise ValueError(f"gate {i} fits no kernel type")
+    kernels = []
+    i = m
+    while i > 0:
+        j, t, c = back[i]
+        kernels.append((j, i, t, c))
+        i = j
+    kernels.reverse()
+    return best[m][0], kernels
+
+
 def brute_force_kernelize(gates, opts: KOpts, tab: CostTables):
     """Enumerate all 2^(|C|-1) contiguous partitions and take the minimum
     under the same total order, compared back to front."""

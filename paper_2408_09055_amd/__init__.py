@@ -63,7 +63,7 @@ class qk_kopts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("cost_model", ctypes.c_int32), ("k_max", ctypes.c_int32),
                 ("m_max", ctypes.c_int32), ("ell", ctypes.c_int32), ("absorb_swaps", ctypes.c_int32),
                 ("allow_fused", ctypes.c_int32), ("allow_lds", ctypes.c_int32),
-                ("block_qubits", ctypes.c_int32), ("learned_flags", ctypes.c_int32),
+                ("block_qubits", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tables", ctypes.POINTER(qk_cost_tables))]
 
 
@@ -71,6 +71,25 @@ class qk_kernel_info(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("k", ctypes.c_int32), ("gate_begin", ctypes.c_int64),
                 ("gate_end", ctypes.c_int64), ("qubit_mask", ctypes.c_uint64), ("cost_ps", ctypes.c_int64),
                 ("block_qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32)]
+
+
+class qk_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("val_frac", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class qk_train_report(ctypes.Structure):
+    _fields_ = [("train_mse", ctypes.c_float), ("val_mse", ctypes.c_float), ("train_mape", ctypes.c_double),
+                ("val_mape", ctypes.c_double), ("n_train", ctypes.c_int64), ("n_val", ctypes.c_int64)]
+
+
+NUM_FEATURES = 20
+DATA_DIR = os.path.join(_HERE, "data")
+
+
+def costmodel_path(dtype: int) -> str:
+    """Default location of the trained cost model for a dtype."""
+    return os.path.join(DATA_DIR, f"costmodel_gfx950_{'c64' if dtype == 0 else 'c128'}.txt")
 
 
 _P = ctypes.c_void_p
@@ -97,6 +116,19 @@ _SIGS = {
     "apply_kernel": [_P, _P, _i64, _P], "plan_finish": [_P, _P, _P],
     "simulate": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _P],
     "execute_plan": [_P, _P, _P],
+    "plan_cost_model": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+    "qk_ctx_set_tables": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qk_cost_tables)],
+    "qk_ctx_get_tables": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qk_cost_tables), ctypes.POINTER(ctypes.c_int)],
+    "costmodel_calibrate": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qk_cost_tables)],
+    "kernelize_single": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), ctypes.c_int, _PP],
+    "plan_kernel_features": [_P, _i64, _P],
+    "time_kernel": [_P, _P, _i64, _P, ctypes.c_int, _dbl_p],
+    "costmodel_train": [_P, ctypes.c_int, _P, _P, _i64, ctypes.POINTER(qk_train_opts), ctypes.POINTER(qk_train_report)],
+    "costmodel_save": [_P, ctypes.c_int, ctypes.c_char_p], "costmodel_load": [_P, ctypes.c_int, ctypes.c_char_p],
+    "costmodel_unload": [_P, ctypes.c_int], "costmodel_loaded": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "costmodel_predict": [_P, ctypes.c_int, _P, _i64, _P],
+    "mlp_forward_backward": [_P, _P, _P, _P, _i64, _P, _P, _P],
+    "mlp_adam_step": [_P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int],
 }
 for _name, _args in _SIGS.items():
     try:
@@ -111,6 +143,8 @@ _lib.qk_last_error.argtypes = []
 _lib.qk_version.restype = ctypes.c_char_p
 _lib.qk_kopts_default.restype = None
 _lib.qk_kopts_default.argtypes = [ctypes.POINTER(qk_kopts)]
+_lib.mlp_num_params.restype = ctypes.c_int
+_lib.mlp_num_params.argtypes = []
 
 
 def lib():
@@ -142,6 +176,11 @@ def kopts(dtype=QK_C64, cost_model=QK_COST_ANALYTIC, k_max=None, m_max=None, ell
         ko._tables_keep = t
         ko.tables = ctypes.pointer(t)
     return ko
+
+
+def tables_tuple(t: qk_cost_tables):
+    return ([int(t.fused_ps[k]) for k in range(8)], int(t.lds_alpha_ps),
+            [int(t.lds_gate_ps[c]) for c in range(NUM_CLASSES)])
 
 
 def make_tables(fused, alpha, gate) -> qk_cost_tables:
@@ -193,6 +232,57 @@ class Context:
 
     def sync(self):
         _check(_lib.qk_sync(self.h))
+
+    def set_tables(self, n: int, dtype: int, tables):
+        t = tables if isinstance(tables, qk_cost_tables) else make_tables(*tables)
+        _check(_lib.qk_ctx_set_tables(self.h, n, dtype, ctypes.byref(t)))
+
+    def get_tables(self, n: int, dtype: int):
+        t = qk_cost_tables()
+        d = ctypes.c_int()
+        _check(_lib.qk_ctx_get_tables(self.h, n, dtype, ctypes.byref(t), ctypes.byref(d)))
+        return tables_tuple(t), bool(d.value)
+
+    def calibrate(self, n: int, dtype: int, reps: int = 3):
+        """Measure the analytic cost constants for (n, dtype) on the device."""
+        t = qk_cost_tables()
+        _check(_lib.costmodel_calibrate(self.h, n, dtype, reps, ctypes.byref(t)))
+        return tables_tuple(t)
+
+    def load_costmodel(self, dtype: int, path: str | None = None) -> bool:
+        p = path or costmodel_path(dtype)
+        if not os.path.exists(p):
+            return False
+        _check(_lib.costmodel_load(self.h, dtype, p.encode()))
+        return True
+
+    def save_costmodel(self, dtype: int, path: str):
+        _check(_lib.costmodel_save(self.h, dtype, path.encode()))
+
+    def unload_costmodel(self, dtype: int):
+        _check(_lib.costmodel_unload(self.h, dtype))
+
+    def costmodel_loaded(self, dtype: int) -> bool:
+        v = ctypes.c_int()
+        _check(_lib.costmodel_loaded(self.h, dtype, ctypes.byref(v)))
+        return bool(v.value)
+
+    def predict(self, dtype: int, feats: np.ndarray) -> np.ndarray:
+        f = np.ascontiguousarray(feats, np.float32).reshape(-1, NUM_FEATURES)
+        out = np.zeros(f.shape[0], np.float32)
+        _check(_lib.costmodel_predict(self.h, dtype, f.ctypes.data, f.shape[0], out.ctypes.data))
+        return out
+
+    def train_costmodel(self, dtype: int, feats: np.ndarray, targets: np.ndarray, epochs=200, batch=256,
+                        lr=1e-3, val_frac=0.2, seed=3) -> dict:
+        f = np.ascontiguousarray(feats, np.float32).reshape(-1, NUM_FEATURES)
+        t = np.ascontiguousarray(targets, np.float32)
+        o = qk_train_opts(epochs, batch, lr, val_frac, seed)
+        r = qk_train_report()
+        _check(_lib.costmodel_train(self.h, dtype, f.ctypes.data, t.ctypes.data, f.shape[0], ctypes.byref(o),
+                                    ctypes.byref(r)))
+        return {"train_mse": r.train_mse, "val_mse": r.val_mse, "train_mape": r.train_mape,
+                "val_mape": r.val_mape, "n_train": r.n_train, "n_val": r.n_val}
 
 
 class State:
@@ -361,6 +451,16 @@ class Plan:
         _check(_lib.plan_gate_source(self.h, i, ctypes.byref(v)))
         return v.value
 
+    def features(self, i: int) -> np.ndarray:
+        out = np.zeros(NUM_FEATURES, np.float32)
+        _check(_lib.plan_kernel_features(self.h, i, out.ctypes.data))
+        return out
+
+    def cost_model(self):
+        u, f = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.plan_cost_model(self.h, ctypes.byref(u), ctypes.byref(f)))
+        return {"learned_used": bool(u.value), "learned_fallback": bool(f.value)}
+
     def final_layout(self) -> list:
         out = np.zeros(self.n, np.int32)
         _check(_lib.plan_final_layout(self.h, out.ctypes.data))
@@ -395,3 +495,47 @@ def execute_plan(ctx: Context, plan: Plan, state: State):
 def simulate(ctx: Context, circuit, state: State, ko: qk_kopts | None = None):
     c = _circuit_struct(circuit)
     _check(_lib.simulate(ctx.h, ctypes.byref(c), ctypes.byref(ko) if ko is not None else None, state.h))
+
+
+def kernelize_single(ctx: Context, circuit, ko: qk_kopts | None, ktype: int) -> Plan:
+    c = _circuit_struct(circuit)
+    h = ctypes.c_void_p()
+    _check(_lib.kernelize_single(ctx.h, ctypes.byref(c), ctypes.byref(ko) if ko is not None else None, ktype,
+                                 ctypes.byref(h)))
+    return Plan(ctx, h, circuit.n_qubits)
+
+
+def time_kernel(ctx: Context, plan: Plan, i: int, state: State, reps: int = 3) -> float:
+    v = ctypes.c_double()
+    _check(_lib.time_kernel(ctx.h, plan.h, i, state.h, reps, ctypes.byref(v)))
+    return v.value
+
+
+def mlp_num_params() -> int:
+    return int(_lib.mlp_num_params())
+
+
+def mlp_forward_backward(ctx: Context, params: np.ndarray, x: np.ndarray, t: np.ndarray | None = None):
+    """One device pass of the cost-model network: returns (y, loss, grads)."""
+    p = np.ascontiguousarray(params, np.float32)
+    assert p.size == mlp_num_params()
+    xx = np.ascontiguousarray(x, np.float32).reshape(-1, NUM_FEATURES)
+    B = xx.shape[0]
+    y = np.zeros(B, np.float32)
+    loss = np.zeros(1, np.float32)
+    grads = np.zeros(p.size, np.float32)
+    tt = None if t is None else np.ascontiguousarray(t, np.float32)
+    _check(_lib.mlp_forward_backward(ctx.h, p.ctypes.data, xx.ctypes.data,
+                                     None if tt is None else tt.ctypes.data, B, y.ctypes.data,
+                                     loss.ctypes.data, grads.ctypes.data))
+    return y, (float(loss[0]) if tt is not None else None), (grads if tt is not None else None)
+
+
+def mlp_adam_step(ctx: Context, params, grads, m, v, lr: float, step: int):
+    """One device Adam step; returns updated (params, m, v) copies."""
+    p = np.array(params, np.float32)
+    g = np.ascontiguousarray(grads, np.float32)
+    mm = np.array(m, np.float32)
+    vv = np.array(v, np.float32)
+    _check(_lib.mlp_adam_step(ctx.h, p.ctypes.data, g.ctypes.data, mm.ctypes.data, vv.ctypes.data, lr, step))
+    return p, mm, vv

@@ -13,10 +13,14 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "planner.cpp", "gates.cpp", "costmodel.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "planner.cpp", "gates.cpp", "costmodel.cpp", "kernels.hip", "mlp.hip"]
 
-# Packed FP32 instructions are disabled for all device code.
-DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 instructions are disabled for all device code.  Common-code
+# sinking is disabled because it merges the per-bit variants of register
+# operations into pointer selects, which demotes the register arrays of the
+# register-blocked kernel to scratch memory.
+DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-simplifycfg-sink-common=false"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 
 

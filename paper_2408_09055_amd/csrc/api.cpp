@@ -197,6 +197,8 @@ int qk_ctx_free(qk_ctx* ctx)
         if (ctx->d_partials) (void)hipFree(ctx->d_partials);
         if (ctx->d_stage) (void)hipFree(ctx->d_stage);
         if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+        for (int d = 0; d < 2; ++d)
+            if (ctx->mlp[d].d_params) (void)hipFree(ctx->mlp[d].d_params);
     }
     delete ctx;
     return QK_OK;
@@ -421,19 +423,19 @@ int sv_gather(qk_state* st, const uint64_t* idx, uint64_t cnt, double* out)
 }
 
 // ---------------------------------------------------------------- plans
-int kernelize(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_plan** out)
+}  // extern "C"
+
+namespace qk {
+
+// Upload a plan's operation and coefficient tables on the context's stream
+// (skipped for host-only contexts).  Frees the plan on failure.
+int upload_plan(qk_ctx* ctx, qk_plan* P)
 {
-    if (!ctx) return fail(QK_EINVAL, "kernelize: null context");
-    qk_plan* P = nullptr;
-    int rc = build_plan(ctx, c, ko, &P);
-    if (rc) return rc;
     if (!ctx->host_only && !P->ops.empty()) {
         const size_t ob = P->ops.size() * sizeof(Op);
         const size_t cb = std::max<size_t>(P->coefs.size(), 1) * amp_bytes(P->dtype);
-        if (hipMalloc(&P->d_ops, ob) != hipSuccess || hipMalloc(&P->d_coef, cb) != hipSuccess) {
-            plan_free(P);
+        if (hipMalloc(&P->d_ops, ob) != hipSuccess || hipMalloc(&P->d_coef, cb) != hipSuccess)
             return fail(QK_ENOMEM, "kernelize: plan upload allocation failed");
-        }
         // the device copy of the coefficients is rounded once to the dtype
         std::vector<char>* hb = new std::vector<char>(cb);
         if (P->dtype == QK_C128) {
@@ -445,15 +447,35 @@ int kernelize(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_plan** ou
                 f[2 * i + 1] = (float)P->coefs[i].imag();
             }
         }
+        if (!P->phases.empty()) {
+            if (hipMalloc(&P->d_phases, P->phases.size() * sizeof(Phase)) != hipSuccess)
+                return fail(QK_ENOMEM, "kernelize: plan upload allocation failed");
+            hipError_t e0 = hipMemcpyAsync(P->d_phases, P->phases.data(), P->phases.size() * sizeof(Phase),
+                                           hipMemcpyHostToDevice, (hipStream_t)ctx->stream);
+            if (e0 != hipSuccess) return hip_fail(e0, "kernelize: plan upload");
+        }
         hipError_t e1 = hipMemcpyAsync(P->d_ops, P->ops.data(), ob, hipMemcpyHostToDevice, (hipStream_t)ctx->stream);
         hipError_t e2 = hipMemcpyAsync(P->d_coef, hb->data(), cb, hipMemcpyHostToDevice, (hipStream_t)ctx->stream);
         hipError_t e3 = hipStreamSynchronize((hipStream_t)ctx->stream);
         delete hb;
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-            plan_free(P);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
             return hip_fail(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3, "kernelize: plan upload");
-        }
     }
+    return QK_OK;
+}
+
+}  // namespace qk
+
+extern "C" {
+
+int kernelize(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_plan** out)
+{
+    if (!ctx) return fail(QK_EINVAL, "kernelize: null context");
+    qk_plan* P = nullptr;
+    int rc = build_plan(ctx, c, ko, &P);
+    if (rc) return rc;
+    rc = upload_plan(ctx, P);
+    if (rc) { plan_free(P); return rc; }
     *out = P;
     return QK_OK;
 }
@@ -478,6 +500,14 @@ int plan_kernel_info(const qk_plan* p, int64_t i, qk_kernel_info* out)
     out->cost_ps = K.cost;
     out->block_qubits = K.desc.m;
     out->n_ops = K.n_ops;
+    return QK_OK;
+}
+
+int plan_cost_model(const qk_plan* p, int* learned_used, int* learned_fallback)
+{
+    if (!p) return fail(QK_EINVAL, "plan_cost_model: null plan");
+    if (learned_used) *learned_used = p->learned_used ? 1 : 0;
+    if (learned_fallback) *learned_fallback = p->learned_fallback ? 1 : 0;
     return QK_OK;
 }
 
@@ -513,10 +543,11 @@ int plan_final_layout(const qk_plan* p, int32_t* perm)
 int plan_free(qk_plan* p)
 {
     if (!p) return QK_OK;
-    if (p->ctx && !p->ctx->host_only && (p->d_ops || p->d_coef)) {
+    if (p->ctx && !p->ctx->host_only && (p->d_ops || p->d_coef || p->d_phases)) {
         (void)hipStreamSynchronize((hipStream_t)p->ctx->stream);
         if (p->d_ops) (void)hipFree(p->d_ops);
         if (p->d_coef) (void)hipFree(p->d_coef);
+        if (p->d_phases) (void)hipFree(p->d_phases);
     }
     delete p;
     return QK_OK;
@@ -534,8 +565,14 @@ int apply_kernel(qk_ctx* ctx, const qk_plan* p, int64_t i, qk_state* st)
     // single stage: every kernel runs on the layout the plan started from
     if (!is_identity(st->layout)) return fail(QK_ESTATE, "apply_kernel: state layout differs from the plan's");
     const PKernel& K = p->kernels[i];
-    const int fused_k = K.type == QK_KERNEL_FUSED ? K.k : 0;
-    int e = launch_block(p->dtype, fused_k, st->psi, K.desc, (const Op*)p->d_ops + K.op_off, p->d_coef, ctx->stream);
+    int e;
+    if (K.rb) {
+        e = launch_block_rb(p->dtype, st->psi, K.rbd, (const Phase*)p->d_phases + K.ph_off,
+                            (const Op*)p->d_ops + K.rbop_off, p->d_coef, ctx->stream);
+    } else {
+        const int fused_k = K.type == QK_KERNEL_FUSED ? K.k : 0;
+        e = launch_block(p->dtype, fused_k, st->psi, K.desc, (const Op*)p->d_ops + K.op_off, p->d_coef, ctx->stream);
+    }
     if (e) return hip_fail(e, "apply_kernel launch");
     return QK_OK;
 }

@@ -392,6 +392,314 @@ __global__ __launch_bounds__(kNT) void k_block_dense(C* __restrict__ psi, BlockD
     });
 }
 
+// ----------------------------------------------------------- register-blocked kernel
+// Each thread holds kRbAmps = 16 amplitudes v[rho]; register bit k of rho is
+// block bit reg[k] of the current phase, the thread index supplies the other
+// block bits in ascending order.  Operations on register bits run in
+// registers with compile-time indices (dispatch on the bit position); a phase
+// change writes the block to LDS in the old layout and reads it back in the
+// new one.  Loads and stores use the I/O layout: 16-byte chunks along the
+// contiguous low run, as in block_loop.
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Lambdas that index register arrays must be inlined, or the array escapes
+// to scratch memory.
+#define QK_AI __attribute__((always_inline))
+
+// Plain complex value for register arrays (HIP's float2/double2 wrap a union,
+// which keeps arrays of them out of registers).
+template <typename R>
+struct Cx {
+    R x, y;
+};
+
+template <typename C>
+using CxOf = Cx<typename Real<C>::T>;
+
+template <typename C>
+__device__ __forceinline__ CxOf<C> ld_coef(const C* __restrict__ p)
+{
+    const C c = *p;
+    return CxOf<C>{c.x, c.y};
+}
+
+__host__ __device__ constexpr int cins0(int p, int k) { return ((p >> k) << (k + 1)) | (p & ((1 << k) - 1)); }
+
+template <typename F>
+__device__ __forceinline__ void dispatch1(int k, F&& f)
+{
+    switch (k) {
+    case 0: f(IC<0>{}); break;
+    case 1: f(IC<1>{}); break;
+    case 2: f(IC<2>{}); break;
+    default: f(IC<3>{}); break;
+    }
+}
+
+template <typename F>
+__device__ __forceinline__ void dispatch2(int a, int b, F&& f)
+{
+    switch (a * 4 + b) {
+    case 1: f(IC<0>{}, IC<1>{}); break;
+    case 2: f(IC<0>{}, IC<2>{}); break;
+    case 3: f(IC<0>{}, IC<3>{}); break;
+    case 4: f(IC<1>{}, IC<0>{}); break;
+    case 6: f(IC<1>{}, IC<2>{}); break;
+    case 7: f(IC<1>{}, IC<3>{}); break;
+    case 8: f(IC<2>{}, IC<0>{}); break;
+    case 9: f(IC<2>{}, IC<1>{}); break;
+    case 11: f(IC<2>{}, IC<3>{}); break;
+    case 12: f(IC<3>{}, IC<0>{}); break;
+    case 13: f(IC<3>{}, IC<1>{}); break;
+    case 14: f(IC<3>{}, IC<2>{}); break;
+    default: break;
+    }
+}
+
+// 2x2 on register bit K: pairs (i0, i0 | 2^K)
+template <int K, typename C, typename V>
+__device__ __forceinline__ void rb_dense1(V (&v)[kRbAmps], const C* __restrict__ u)
+{
+    const V u00 = ld_coef(u), u01 = ld_coef(u + 1), u10 = ld_coef(u + 2), u11 = ld_coef(u + 3);
+    static_for<0, kRbAmps / 2>([&](auto P) QK_AI {
+        constexpr int i0 = cins0(P.value, K), i1 = i0 | (1 << K);
+        const V a = v[i0], b = v[i1];
+        v[i0] = cmadd(u01, b, cmul(u00, a));
+        v[i1] = cmadd(u11, b, cmul(u10, a));
+    });
+}
+
+template <int K, typename C, typename V>
+__device__ __forceinline__ void rb_diag1(V (&v)[kRbAmps], const C* __restrict__ u)
+{
+    const V d0 = ld_coef(u), d1 = ld_coef(u + 1);
+    static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], ((I.value >> K) & 1) ? d1 : d0); });
+}
+
+template <int K, typename V>
+__device__ __forceinline__ void rb_x(V (&v)[kRbAmps])
+{
+    static_for<0, kRbAmps / 2>([&](auto P) QK_AI {
+        constexpr int i0 = cins0(P.value, K), i1 = i0 | (1 << K);
+        const V a = v[i0];
+        v[i0] = v[i1];
+        v[i1] = a;
+    });
+}
+
+// quads over two distinct register bits A, B: base has zeros at A and B
+template <int A, int B>
+__host__ __device__ constexpr int cins00(int p)
+{
+    return A < B ? cins0(cins0(p, A), B) : cins0(cins0(p, B), A);
+}
+
+template <int KC, int KT, typename V>
+__device__ __forceinline__ void rb_cx(V (&v)[kRbAmps])
+{
+    static_for<0, kRbAmps / 4>([&](auto P) QK_AI {
+        constexpr int i0 = cins00<KC, KT>(P.value) | (1 << KC), i1 = i0 | (1 << KT);
+        const V a = v[i0];
+        v[i0] = v[i1];
+        v[i1] = a;
+    });
+}
+
+template <int KA, int KB, typename V>
+__device__ __forceinline__ void rb_cz(V (&v)[kRbAmps])
+{
+    static_for<0, kRbAmps / 4>([&](auto P) QK_AI {
+        constexpr int i = cins00<KA, KB>(P.value) | (1 << KA) | (1 << KB);
+        v[i].x = -v[i].x;
+        v[i].y = -v[i].y;
+    });
+}
+
+template <int KA, int KB, typename C, typename V>
+__device__ __forceinline__ void rb_cphase(V (&v)[kRbAmps], const C* __restrict__ u)
+{
+    const V ph = ld_coef(u);
+    static_for<0, kRbAmps / 4>([&](auto P) QK_AI {
+        constexpr int i = cins00<KA, KB>(P.value) | (1 << KA) | (1 << KB);
+        v[i] = cmul(v[i], ph);
+    });
+}
+
+template <int KA, int KB, typename C, typename V>
+__device__ __forceinline__ void rb_diag2(V (&v)[kRbAmps], const C* __restrict__ u)
+{
+    const V d0 = ld_coef(u), d1 = ld_coef(u + 1), d2 = ld_coef(u + 2), d3 = ld_coef(u + 3);
+    static_for<0, kRbAmps>([&](auto I) QK_AI {
+        constexpr int s = ((I.value >> KA) & 1) | (((I.value >> KB) & 1) << 1);
+        v[I.value] = cmul(v[I.value], s == 0 ? d0 : s == 1 ? d1 : s == 2 ? d2 : d3);
+    });
+}
+
+template <int KA, int KB, typename V>
+__device__ __forceinline__ void rb_swap(V (&v)[kRbAmps])
+{
+    static_for<0, kRbAmps / 4>([&](auto P) QK_AI {
+        constexpr int base = cins00<KA, KB>(P.value);
+        constexpr int i0 = base | (1 << KA), i1 = base | (1 << KB);
+        const V a = v[i0];
+        v[i0] = v[i1];
+        v[i1] = a;
+    });
+}
+
+// 2^K x 2^K matrix on register bits 0..K-1 (row-major U, index bit j <-> bit j)
+template <int K, typename C, typename V>
+__device__ __forceinline__ void rb_densek(V (&v)[kRbAmps], const C* __restrict__ U)
+{
+    constexpr int D = 1 << K;
+    static_for<0, kRbAmps / D>([&](auto G) QK_AI {
+        V in[D];
+        static_for<0, D>([&](auto R) QK_AI { in[R.value] = v[G.value * D + R.value]; });
+        static_for<0, D>([&](auto R) QK_AI {
+            V acc{0, 0};
+            static_for<0, D>([&](auto Cc) QK_AI { acc = cmadd(ld_coef(U + R.value * D + Cc.value), in[Cc.value], acc); });
+            v[G.value * D + R.value] = acc;
+        });
+    });
+}
+
+template <typename C, typename V>
+__device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* __restrict__ coef)
+{
+    const C* u = coef + op.coef;
+    switch (op.code) {
+    case OP_DENSE1: dispatch1(op.b[0], [&](auto K) QK_AI { rb_dense1<K.value>(v, u); }); break;
+    case OP_DIAG1: dispatch1(op.b[0], [&](auto K) QK_AI { rb_diag1<K.value>(v, u); }); break;
+    case OP_X: dispatch1(op.b[0], [&](auto K) QK_AI { rb_x<K.value>(v); }); break;
+    case OP_CX: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_cx<A.value, B.value>(v); }); break;
+    case OP_CZ: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_cz<A.value, B.value>(v); }); break;
+    case OP_CPHASE: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_cphase<A.value, B.value>(v, u); }); break;
+    case OP_DIAG2: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_diag2<A.value, B.value>(v, u); }); break;
+    case OP_SWAP: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_swap<A.value, B.value>(v); }); break;
+    case OP_DENSEK:
+        switch (op.k) {
+        case 1: rb_densek<1>(v, u); break;
+        case 2: rb_densek<2>(v, u); break;
+        case 3: rb_densek<3>(v, u); break;
+        default: rb_densek<4>(v, u); break;
+        }
+        break;
+    default: break;
+    }
+}
+
+// LDS index swizzle: XOR the low 5 bits with higher bits so that lanes whose
+// block index differs only in high bits land in different banks.
+__device__ __forceinline__ uint32_t lds_swz(uint32_t i) { return i ^ (((i >> 5) ^ (i >> 10)) & 31u); }
+
+// Block index of this thread's rho = 0 under register bits reg: the thread
+// index bits go, in order, to the block bits outside reg (ascending).
+__device__ __forceinline__ uint32_t thr_deposit(uint32_t t, const uint8_t* reg, int m)
+{
+    const uint32_t rm = (1u << reg[0]) | (1u << reg[1]) | (1u << reg[2]) | (1u << reg[3]);
+    uint32_t out = 0;
+    int j = 0;
+    for (int q = 0; q < m; ++q) {
+        if ((rm >> q) & 1u) continue;
+        out |= ((t >> j) & 1u) << q;
+        ++j;
+    }
+    return out;
+}
+
+template <int RHO>
+__device__ __forceinline__ uint32_t reg_deposit(const uint8_t* reg)
+{
+    return ((RHO & 1) ? (1u << reg[0]) : 0u) | ((RHO & 2) ? (1u << reg[1]) : 0u) |
+           ((RHO & 4) ? (1u << reg[2]) : 0u) | ((RHO & 8) ? (1u << reg[3]) : 0u);
+}
+
+template <typename V>
+__device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint8_t* from, const uint8_t* to, int m)
+{
+    __syncthreads();   // earlier readers of the LDS block are done
+    const uint32_t tf = thr_deposit(threadIdx.x, from, m);
+    static_for<0, kRbAmps>([&](auto R) QK_AI { sm[lds_swz(tf | reg_deposit<R.value>(from))] = v[R.value]; });
+    __syncthreads();
+    const uint32_t tt = thr_deposit(threadIdx.x, to, m);
+    static_for<0, kRbAmps>([&](auto R) QK_AI { v[R.value] = sm[lds_swz(tt | reg_deposit<R.value>(to))]; });
+}
+
+__device__ __forceinline__ bool same_reg(const uint8_t* a, const uint8_t* b)
+{
+    return a[0] == b[0] && a[1] == b[1] && a[2] == b[2] && a[3] == b[3];
+}
+
+template <typename C, int NT>
+__global__ __launch_bounds__(NT) void k_block_rb(C* __restrict__ psi, RbDesc d, const Phase* __restrict__ phases,
+                                                 const Op* __restrict__ ops, const C* __restrict__ coef)
+{
+    using V = CxOf<C>;
+    using R = typename Real<C>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* sm = reinterpret_cast<V*>(smem);
+    constexpr int CH = 16 / sizeof(C);              // amplitudes per 16-byte chunk
+    constexpr int NCH = kRbAmps / CH;               // chunks per thread
+    const int m = d.b.m;
+    const int tid = threadIdx.x;
+    // chunk i of thread t covers block index (t + NT i) * CH (+ e): the thread
+    // part and the chunk part occupy disjoint bit fields
+    const uint64_t off_t = deposit((uint32_t)tid * CH, d.b.act, m);
+    uint64_t off_i[NCH];
+    static_for<0, NCH>([&](auto I) QK_AI { off_i[I.value] = deposit((uint32_t)I.value * NT * CH, d.b.act, m); });
+    uint64_t blk = blockIdx.x;
+    if (blk >= d.b.nblocks) return;
+    u32x4 w[NCH];
+    uint64_t base = block_base(blk, d.b.act, m) + off_t;
+    auto load_all = [&](uint64_t b0) {
+        static_for<0, NCH>([&](auto I) QK_AI { w[I.value] = *reinterpret_cast<const u32x4*>(&psi[b0 + off_i[I.value]]); });
+    };
+    load_all(base);
+    for (;;) {
+        V v[kRbAmps];
+        static_for<0, NCH>([&](auto I) QK_AI {
+            const u32x4 x = w[I.value];
+            if constexpr (CH == 2) {
+                v[2 * I.value] = V{__uint_as_float(x.x), __uint_as_float(x.y)};
+                v[2 * I.value + 1] = V{__uint_as_float(x.z), __uint_as_float(x.w)};
+            } else {
+                v[I.value] = V{__builtin_bit_cast(R, (uint64_t)x.x | ((uint64_t)x.y << 32)),
+                               __builtin_bit_cast(R, (uint64_t)x.z | ((uint64_t)x.w << 32))};
+            }
+        });
+        const uint64_t next = blk + gridDim.x;
+        const uint64_t nbase = next < d.b.nblocks ? block_base(next, d.b.act, m) + off_t : 0;
+        if (next < d.b.nblocks) load_all(nbase);
+        uint8_t cur[4] = {d.io_reg[0], d.io_reg[1], d.io_reg[2], d.io_reg[3]};
+        for (int p = 0; p < d.n_phases; ++p) {
+            const Phase ph = phases[p];
+            if (!same_reg(cur, ph.reg) && d.uses_lds) {
+                rb_transition(sm, v, cur, ph.reg, m);
+                cur[0] = ph.reg[0]; cur[1] = ph.reg[1]; cur[2] = ph.reg[2]; cur[3] = ph.reg[3];
+            }
+            for (int o = ph.op_begin; o < ph.op_end; ++o) rb_apply(v, ops[o], coef);
+        }
+        if (!same_reg(cur, d.io_reg) && d.uses_lds) rb_transition(sm, v, cur, d.io_reg, m);
+        static_for<0, NCH>([&](auto I) QK_AI {
+            u32x4 x;
+            if constexpr (CH == 2) {
+                const V a = v[2 * I.value], b = v[2 * I.value + 1];
+                x.x = __float_as_uint(a.x); x.y = __float_as_uint(a.y);
+                x.z = __float_as_uint(b.x); x.w = __float_as_uint(b.y);
+            } else {
+                const V a = v[I.value];
+                const uint64_t re = __builtin_bit_cast(uint64_t, a.x), im = __builtin_bit_cast(uint64_t, a.y);
+                x.x = (uint32_t)re; x.y = (uint32_t)(re >> 32); x.z = (uint32_t)im; x.w = (uint32_t)(im >> 32);
+            }
+            *reinterpret_cast<u32x4*>(&psi[base + off_i[I.value]]) = x;
+        });
+        if (next >= d.b.nblocks) break;
+        blk = next;
+        base = nbase;
+    }
+}
+
 // ----------------------------------------------------------- permutation pass
 // Tile = the 2^m amplitudes with fixed source bits outside act_src.  Reads
 // use the source run (lo_src low bits contiguous), writes the destination run.
@@ -584,7 +892,7 @@ struct KernelFacts {
     int occ;
 };
 
-uint64_t resident_groups(const void* f, size_t lds)
+uint64_t resident_groups(const void* f, size_t lds, int threads = kNT)
 {
     static int cus = 0;
     static KernelFacts cache[64];
@@ -601,7 +909,7 @@ uint64_t resident_groups(const void* f, size_t lds)
     for (int i = 0; i < ncache; ++i) seen |= cache[i].f == f;
     if (!seen) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, kNT, lds) != hipSuccess || occ <= 0) occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, threads, lds) != hipSuccess || occ <= 0) occ = 1;
     if (ncache < 64) cache[ncache++] = KernelFacts{f, lds, occ};
     return (uint64_t)occ * cus;
 }
@@ -640,6 +948,48 @@ int launch_block(int dtype, int fused_k, void* psi, const BlockDesc& d, const Op
     hipStream_t s = (hipStream_t)stream;
     if (dtype == QK_C128) return launch_typed<double2>(fused_k, psi, d, ops, coef, lds, s);
     return launch_typed<float2>(fused_k, psi, d, ops, coef, lds, s);
+}
+
+int rb_threads(int dtype, int m)
+{
+    if (dtype == QK_C64) return m == 12 ? 256 : m == 13 ? 512 : 0;
+    return m == 12 ? 256 : 0;
+}
+
+void rb_io_reg(int dtype, int threads, uint8_t* reg)
+{
+    const int lt = threads == 512 ? 9 : 8;
+    if (dtype == QK_C64) {
+        reg[0] = 0;
+        reg[1] = (uint8_t)(lt + 1); reg[2] = (uint8_t)(lt + 2); reg[3] = (uint8_t)(lt + 3);
+    } else {
+        reg[0] = (uint8_t)lt; reg[1] = (uint8_t)(lt + 1); reg[2] = (uint8_t)(lt + 2); reg[3] = (uint8_t)(lt + 3);
+    }
+}
+
+template <typename C, int NT>
+int launch_rb_typed(void* psi, const RbDesc& d, const Phase* phases, const Op* ops, const void* coef, hipStream_t s)
+{
+    const size_t lds = d.uses_lds ? ((size_t)sizeof(C) << d.b.m) : 0;
+    auto f = k_block_rb<C, NT>;
+    const uint64_t res = resident_groups(reinterpret_cast<const void*>(f), lds, NT);
+    const dim3 grid((uint32_t)std::min<uint64_t>(d.b.nblocks, res)), block(NT);
+    hipLaunchKernelGGL(f, grid, block, lds, s, (C*)psi, d, phases, ops, (const C*)coef);
+    return (int)hipGetLastError();
+}
+
+int launch_block_rb(int dtype, void* psi, const RbDesc& d, const Phase* phases, const Op* ops, const void* coef,
+                    void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int nt = rb_threads(dtype, d.b.m);
+    if (dtype == QK_C64) {
+        if (nt == 512) return launch_rb_typed<float2, 512>(psi, d, phases, ops, coef, s);
+        if (nt == 256) return launch_rb_typed<float2, 256>(psi, d, phases, ops, coef, s);
+    } else if (nt == 256) {
+        return launch_rb_typed<double2, 256>(psi, d, phases, ops, coef, s);
+    }
+    return (int)hipErrorInvalidValue;
 }
 
 int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream)

@@ -23,7 +23,11 @@ struct PKernel {
     uint64_t mask;     // physical qubits of the gates
     int64_t cost;      // DP cost (ps)
     BlockDesc desc;    // staged-block launch
-    int op_off, n_ops; // slice of the plan's op table
+    int op_off, n_ops; // slice of the plan's op table (block-bit form)
+    bool rb;           // runs on the register-blocked kernel
+    RbDesc rbd;        // its launch descriptor
+    int ph_off;        // slice of the plan's phase table
+    int rbop_off;      // slice of the op table in register-position form
 };
 
 // Feature vector of a candidate kernel for the learned cost model.
@@ -52,9 +56,11 @@ struct qk_plan {
     std::vector<qk::PKernel> kernels;
     std::vector<int32_t> final_layout;   // logical q -> physical bit
     std::vector<qk::Op> ops;
+    std::vector<qk::Phase> phases;
     std::vector<qk::cd> coefs;           // FP64 master copy
     int64_t total_cost = 0;
     qk_ctx* ctx = nullptr;
     void* d_ops = nullptr;
     void* d_coef = nullptr;
+    void* d_phases = nullptr;
 };

@@ -167,51 +167,47 @@ void segment_features(const CGate* g, int count, int n, int type, int dtype, flo
 }
 
 // ------------------------------------------------------------------ kernelize
-int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan** out)
+namespace {
+
+// Validate options, resolve defaults; returns QK_OK or an error.
+int resolve_opts(const qk_kopts* ko_in, int n, qk_kopts& ko, int& mblk)
 {
-    if (!c || !out) return fail(QK_EINVAL, "kernelize: null argument");
-    qk_kopts ko;
     if (ko_in) ko = *ko_in; else qk_kopts_default(&ko);
-    const int n = c->n_qubits;
     if (n < 1 || n > kMaxQubits) return fail(QK_EINVAL, "kernelize: n_qubits out of range 1..34");
-    if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) return fail(QK_EINVAL, "kernelize: bad gate array");
     if (ko.dtype != QK_C64 && ko.dtype != QK_C128) return fail(QK_EINVAL, "kernelize: bad dtype");
     if (ko.k_max < 1 || ko.k_max > kMaxFusedQubits) return fail(QK_EINVAL, "kernelize: k_max must be 1..7");
     // 0 selects the defaults: blocks of 64 KiB (2^13 complex64 or 2^12
     // complex128 amplitudes) whose low run is 1 KiB (7 or 6 low qubits)
     if (ko.m_max == 0) ko.m_max = ko.dtype == QK_C64 ? 13 : 12;
     if (ko.ell == 0) ko.ell = ko.dtype == QK_C64 ? 7 : 6;
-    if (ko.ell < 1 || ko.ell > ko.m_max) return fail(QK_EINVAL, "kernelize: ell must be 1..m_max");
     if (ko.m_max < 2 || ko.m_max > kMaxBlockQubits) return fail(QK_EINVAL, "kernelize: m_max must be 2..14");
+    if (ko.ell < 1 || ko.ell > ko.m_max) return fail(QK_EINVAL, "kernelize: ell must be 1..m_max");
     if (!ko.allow_fused && !ko.allow_lds) return fail(QK_EINVAL, "kernelize: no kernel type allowed");
-    int mblk = ko.block_qubits ? ko.block_qubits : ko.m_max;
+    mblk = ko.block_qubits ? ko.block_qubits : ko.m_max;
     if (mblk < ko.m_max || mblk <= ko.k_max || mblk > kMaxBlockQubits)
         return fail(QK_EINVAL, "kernelize: block_qubits must be >= m_max, > k_max and <= 14");
     const int64_t bytes_per_amp = ko.dtype == QK_C128 ? 16 : 8;
-    if (((int64_t)bytes_per_amp << std::min(mblk, n)) > 64 * 1024)
+    if ((bytes_per_amp << std::min(mblk, n)) > 64 * 1024)
         return fail(QK_EINVAL, "kernelize: block of 2^block_qubits amplitudes exceeds 64 KiB of LDS");
+    return QK_OK;
+}
 
-    qk_plan* P = new qk_plan();
-    P->n = n;
-    P->dtype = ko.dtype;
-    P->ko = ko;
-    P->ctx = ctx;
-    if (ko.tables) P->tab = *ko.tables;
-    else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
-
-    // ---- canonicalise
+// Canonicalise c into P->gates / P->final_layout (SWAP absorption).
+int canonicalize(const qk_circuit* c, const qk_kopts& ko, qk_plan* P)
+{
+    const int n = c->n_qubits;
     std::vector<int32_t> layout(n);
     for (int q = 0; q < n; ++q) layout[q] = q;
     for (int64_t i = 0; i < c->n_gates; ++i) {
         const qk_gate& g = c->gates[i];
         const int ar = kind_arity(g.kind);
-        if (ar == 0 || (int)g.nq != ar) { delete P; return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " has a bad kind or qubit count"); }
+        if (ar == 0 || (int)g.nq != ar) return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " has a bad kind or qubit count");
         for (int j = 0; j < ar; ++j) {
-            if (g.q[j] >= (uint32_t)n) { delete P; return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " qubit out of range"); }
+            if (g.q[j] >= (uint32_t)n) return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " qubit out of range");
             for (int l = 0; l < j; ++l)
-                if (g.q[l] == g.q[j]) { delete P; return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " repeats a qubit"); }
+                if (g.q[l] == g.q[j]) return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " repeats a qubit");
         }
-        if (g.flags != 0) { delete P; return fail(QK_EINVAL, "kernelize: gate flags must be 0"); }
+        if (g.flags != 0) return fail(QK_EINVAL, "kernelize: gate flags must be 0");
         if (ko.absorb_swaps && g.kind == QK_SWAP) {
             std::swap(layout[g.q[0]], layout[g.q[1]]);
             continue;
@@ -225,16 +221,245 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
         P->gates.push_back(cg);
     }
     P->final_layout = layout;
+    return QK_OK;
+}
+
+bool op_two_bits(const Op& op)
+{
+    return op.code == OP_CX || op.code == OP_CZ || op.code == OP_CPHASE || op.code == OP_DIAG2 || op.code == OP_SWAP;
+}
+
+int reg_pos(const uint8_t* reg, int bit)
+{
+    for (int k = 0; k < kRbBits; ++k)
+        if (reg[k] == bit) return k;
+    return -1;
+}
+
+// Register-blocked form of kernel K: phases of at most kRbBits block bits.
+// A fused kernel of k <= 4 qubits is one phase whose first k register bits
+// are the kernel bits; an LDS kernel is split greedily, each new phase taking
+// the bits of as many upcoming operations as fit in four.
+void build_rb(qk_plan* P, PKernel& K)
+{
+    const int m = K.desc.m;
+    const int nt = rb_threads(P->dtype, m);
+    if (!nt) return;
+    if (K.type == QK_KERNEL_FUSED && K.k > kRbBits) return;
+    if (K.n_ops > 60000) return;
+    RbDesc& d = K.rbd;
+    std::memset(&d, 0, sizeof(d));
+    d.b = K.desc;
+    rb_io_reg(P->dtype, nt, d.io_reg);
+    K.ph_off = (int)P->phases.size();
+    K.rbop_off = (int)P->ops.size();
+    std::vector<Phase> ph;
+    std::vector<Op> lops;
+    auto has = [](const uint8_t* reg, int nreg, int b) {
+        for (int t = 0; t < nreg; ++t)
+            if (reg[t] == b) return true;
+        return false;
+    };
+    // complete reg[0..nreg) to four bits: first from `prefer`, then the lowest
+    auto fill = [&](uint8_t* reg, int nreg, const uint8_t* prefer) {
+        for (int k = 0; k < kRbBits && nreg < kRbBits; ++k)
+            if (!has(reg, nreg, prefer[k])) reg[nreg++] = prefer[k];
+        for (int b = 0; b < m && nreg < kRbBits; ++b)
+            if (!has(reg, nreg, b)) reg[nreg++] = (uint8_t)b;
+    };
+    if (K.type == QK_KERNEL_FUSED) {
+        const Op& src = P->ops[K.op_off];
+        Phase p{};
+        int nreg = 0;
+        for (int u = 0; u < src.k; ++u) p.reg[nreg++] = src.b[u];
+        fill(p.reg, nreg, d.io_reg);
+        Op o = src;
+        for (int u = 0; u < src.k; ++u) o.b[u] = (uint8_t)u;
+        lops.push_back(o);
+        p.op_begin = 0;
+        p.op_end = 1;
+        ph.push_back(p);
+    } else {
+        uint8_t cur[4];
+        std::memcpy(cur, d.io_reg, 4);
+        bool open = false;
+        for (int o = 0; o < K.n_ops; ++o) {
+            Op op = P->ops[K.op_off + o];
+            const int nb = op_two_bits(op) ? 2 : 1;
+            bool fits = reg_pos(cur, op.b[0]) >= 0 && (nb == 1 || reg_pos(cur, op.b[1]) >= 0);
+            if (!fits) {
+                // bits of this and the following operations while four suffice
+                uint8_t set[4];
+                int ns = 0;
+                for (int o2 = o; o2 < K.n_ops; ++o2) {
+                    const Op& q = P->ops[K.op_off + o2];
+                    uint8_t nbits[2] = {q.b[0], q.b[1]};
+                    const int qn = op_two_bits(q) ? 2 : 1;
+                    uint8_t tmp[4];
+                    std::memcpy(tmp, set, 4);
+                    int nt2 = ns;
+                    for (int t = 0; t < qn; ++t) {
+                        bool dup = false;
+                        for (int u = 0; u < nt2; ++u) dup |= tmp[u] == nbits[t];
+                        if (!dup) {
+                            if (nt2 == kRbBits) { nt2 = kRbBits + 1; break; }
+                            tmp[nt2++] = nbits[t];
+                        }
+                    }
+                    if (nt2 > kRbBits) break;
+                    std::memcpy(set, tmp, 4);
+                    ns = nt2;
+                }
+                fill(set, ns, cur);
+                std::sort(set, set + kRbBits);
+                if (open) ph.back().op_end = (uint16_t)lops.size();
+                Phase p{};
+                std::memcpy(p.reg, set, 4);
+                p.op_begin = (uint16_t)lops.size();
+                ph.push_back(p);
+                std::memcpy(cur, set, 4);
+                open = true;
+            } else if (!open) {
+                Phase p{};
+                std::memcpy(p.reg, cur, 4);
+                p.op_begin = (uint16_t)lops.size();
+                ph.push_back(p);
+                open = true;
+            }
+            Op lo = op;
+            lo.b[0] = (uint8_t)reg_pos(cur, op.b[0]);
+            if (nb == 2) lo.b[1] = (uint8_t)reg_pos(cur, op.b[1]);
+            lops.push_back(lo);
+        }
+        if (open) ph.back().op_end = (uint16_t)lops.size();
+    }
+    // does some phase leave the load/store layout (then the kernel needs LDS)?
+    uint8_t cur[4];
+    std::memcpy(cur, d.io_reg, 4);
+    int uses = 0;
+    for (const Phase& p : ph) {
+        if (std::memcmp(cur, p.reg, 4) != 0) { uses = 1; std::memcpy(cur, p.reg, 4); }
+    }
+    if (std::memcmp(cur, d.io_reg, 4) != 0) uses = 1;
+    d.uses_lds = uses;
+    d.n_phases = (int)ph.size();
+    P->phases.insert(P->phases.end(), ph.begin(), ph.end());
+    P->ops.insert(P->ops.end(), lops.begin(), lops.end());
+    K.rb = true;
+}
+
+// Append the kernel covering canonical gates [j, i) with the given type.
+void emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m_exec)
+{
+    const std::vector<CGate>& G = P->gates;
+    const int n = P->n;
+    PKernel K{};
+    K.type = type;
+    K.cost = cost;
+    K.g0 = j;
+    K.g1 = i;
+    uint64_t mask = 0;
+    for (int64_t t = j; t < i; ++t)
+        for (int u = 0; u < G[t].nq; ++u) mask |= 1ull << G[t].q[u];
+    K.mask = mask;
+    K.k = popcount64(mask);
+    const int ell = (K.type == QK_KERNEL_LDS) ? P->ko.ell : 1;
+    fill_desc(K.desc, active_set(mask, std::min(ell, n), m_exec, n), n);
+    K.op_off = (int)P->ops.size();
+    if (K.type == QK_KERNEL_FUSED) {
+        // kernel qubits in ascending order give the matrix index bits
+        int kq[8], kb[8], nk = 0;
+        for (int q = 0; q < n; ++q)
+            if ((mask >> q) & 1) { kq[nk] = q; kb[nk] = block_bit(K.desc, q); ++nk; }
+        const int dim = 1 << nk;
+        std::vector<cd> U((size_t)dim * dim, cd(0.0, 0.0));
+        for (int r = 0; r < dim; ++r) U[(size_t)r * dim + r] = 1.0;
+        for (int64_t t = j; t < i; ++t) {
+            int loc[2];
+            for (int u = 0; u < G[t].nq; ++u)
+                loc[u] = (int)(std::find(kq, kq + nk, G[t].q[u]) - kq);
+            left_multiply(U, nk, G[t], loc);
+        }
+        Op op{};
+        op.code = OP_DENSEK;
+        op.k = (uint8_t)nk;
+        for (int u = 0; u < nk; ++u) op.b[u] = (uint8_t)kb[u];
+        op.coef = (uint32_t)P->coefs.size();
+        P->coefs.insert(P->coefs.end(), U.begin(), U.end());
+        P->ops.push_back(op);
+    } else {
+        for (int64_t t = j; t < i; ++t) {
+            const CGate& g = G[t];
+            Op op{};
+            op.b[0] = (uint8_t)block_bit(K.desc, g.q[0]);
+            if (g.nq == 2) op.b[1] = (uint8_t)block_bit(K.desc, g.q[1]);
+            op.coef = (uint32_t)P->coefs.size();
+            cd U[16];
+            qk_gate rec{};
+            rec.kind = g.kind; rec.nq = g.nq;
+            rec.p[0] = g.p[0]; rec.p[1] = g.p[1]; rec.p[2] = g.p[2];
+            gate_unitary(rec, U);
+            switch (g.kind) {
+            case QK_X: op.code = OP_X; break;
+            case QK_CX: op.code = OP_CX; break;
+            case QK_CZ: op.code = OP_CZ; break;
+            case QK_SWAP: op.code = OP_SWAP; break;
+            case QK_CP: op.code = OP_CPHASE; P->coefs.push_back(U[15]); break;
+            case QK_RZZ:
+                op.code = OP_DIAG2;
+                for (int r = 0; r < 4; ++r) P->coefs.push_back(U[r * 5]);
+                break;
+            case QK_Z: case QK_S: case QK_T: case QK_RZ: case QK_P:
+                op.code = OP_DIAG1;
+                P->coefs.push_back(U[0]);
+                P->coefs.push_back(U[3]);
+                break;
+            default:
+                op.code = OP_DENSE1;
+                for (int r = 0; r < 4; ++r) P->coefs.push_back(U[r]);
+                break;
+            }
+            P->ops.push_back(op);
+        }
+    }
+    K.n_ops = (int)P->ops.size() - K.op_off;
+    K.desc.n_ops = K.n_ops;
+    K.rb = false;
+    build_rb(P, K);
+    P->kernels.push_back(K);
+}
+
+}  // namespace
+
+int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan** out)
+{
+    if (!c || !out) return fail(QK_EINVAL, "kernelize: null argument");
+    const int n = c->n_qubits;
+    qk_kopts ko;
+    int mblk = 0;
+    int rc = resolve_opts(ko_in, n, ko, mblk);
+    if (rc) return rc;
+    if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) return fail(QK_EINVAL, "kernelize: bad gate array");
+
+    qk_plan* P = new qk_plan();
+    P->n = n;
+    P->dtype = ko.dtype;
+    P->ko = ko;
+    P->ctx = ctx;
+    if (ko.tables) P->tab = *ko.tables;
+    else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
+
+    rc = canonicalize(c, ko, P);
+    if (rc) { delete P; return rc; }
     const int64_t m = (int64_t)P->gates.size();
     const std::vector<CGate>& G = P->gates;
 
     // ---- enumerate feasible segments (early exit is exact: see header)
     const uint64_t lowmask = (1ull << ko.ell) - 1;
     std::vector<int64_t> seg_off(m + 1, 0);
-    std::vector<uint64_t> seg_mask;
     std::vector<int64_t> seg_fused, seg_lds;
     for (int64_t i = 0; i < m; ++i) {
-        seg_off[i] = (int64_t)seg_mask.size();
+        seg_off[i] = (int64_t)seg_fused.size();
         uint64_t mask = 0;
         int64_t s = P->tab.lds_alpha_ps;
         for (int64_t j = i; j >= 0; --j) {
@@ -244,12 +469,11 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
             const bool fok = ko.allow_fused && k <= ko.k_max;
             const bool lok = ko.allow_lds && popcount64(mask | lowmask) <= ko.m_max;
             if (!fok && !lok) break;
-            seg_mask.push_back(mask);
             seg_fused.push_back(fok ? P->tab.fused_ps[k] : kInf);
             seg_lds.push_back(lok ? s : kInf);
         }
     }
-    seg_off[m] = (int64_t)seg_mask.size();
+    seg_off[m] = (int64_t)seg_fused.size();
 
     // ---- learned costs replace the analytic ones for every feasible entry
     if (ko.cost_model == QK_COST_LEARNED) {
@@ -258,7 +482,7 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
         } else {
             std::vector<float> feats;
             std::vector<int64_t*> dst;
-            feats.reserve(seg_mask.size() * 2 * kNumFeatures);
+            feats.reserve(seg_fused.size() * 2 * kNumFeatures);
             float f[kNumFeatures];
             for (int64_t i = 0; i < m; ++i) {
                 for (int64_t e = seg_off[i]; e < seg_off[i + 1]; ++e) {
@@ -276,9 +500,9 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
                 }
             }
             std::vector<float> pred(dst.size());
-            int rc = dst.empty() ? QK_OK
-                                 : learned_predict(ctx, ko.dtype, feats.data(), (int64_t)dst.size(), pred.data());
-            if (rc != QK_OK) {
+            int prc = dst.empty() ? QK_OK
+                                  : learned_predict(ctx, ko.dtype, feats.data(), (int64_t)dst.size(), pred.data());
+            if (prc != QK_OK) {
                 P->learned_fallback = true;
             } else {
                 const double amps = std::ldexp(1.0, n);
@@ -326,80 +550,54 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
     const int m_exec = std::min(n, mblk);
     int64_t j = 0;
     for (int64_t i : cuts) {
-        PKernel K{};
-        K.type = back_t[i];
-        K.cost = back_cost[i];
-        K.g0 = j;
-        K.g1 = i;
-        uint64_t mask = 0;
-        for (int64_t t = j; t < i; ++t)
-            for (int u = 0; u < G[t].nq; ++u) mask |= 1ull << G[t].q[u];
-        K.mask = mask;
-        K.k = popcount64(mask);
-        const int ell = (K.type == QK_KERNEL_LDS) ? ko.ell : 1;
-        fill_desc(K.desc, active_set(mask, std::min(ell, n), m_exec, n), n);
-        K.op_off = (int)P->ops.size();
-        if (K.type == QK_KERNEL_FUSED) {
-            // kernel qubits in ascending order give the matrix index bits
-            int kq[8], kb[8], nk = 0;
-            for (int q = 0; q < n; ++q)
-                if ((mask >> q) & 1) { kq[nk] = q; kb[nk] = block_bit(K.desc, q); ++nk; }
-            const int dim = 1 << nk;
-            std::vector<cd> U((size_t)dim * dim, cd(0.0, 0.0));
-            for (int r = 0; r < dim; ++r) U[(size_t)r * dim + r] = 1.0;
-            for (int64_t t = j; t < i; ++t) {
-                int loc[2];
-                for (int u = 0; u < G[t].nq; ++u)
-                    loc[u] = (int)(std::find(kq, kq + nk, G[t].q[u]) - kq);
-                left_multiply(U, nk, G[t], loc);
-            }
-            Op op{};
-            op.code = OP_DENSEK;
-            op.k = (uint8_t)nk;
-            for (int u = 0; u < nk; ++u) op.b[u] = (uint8_t)kb[u];
-            op.coef = (uint32_t)P->coefs.size();
-            P->coefs.insert(P->coefs.end(), U.begin(), U.end());
-            P->ops.push_back(op);
-        } else {
-            for (int64_t t = j; t < i; ++t) {
-                const CGate& g = G[t];
-                Op op{};
-                op.b[0] = (uint8_t)block_bit(K.desc, g.q[0]);
-                if (g.nq == 2) op.b[1] = (uint8_t)block_bit(K.desc, g.q[1]);
-                op.coef = (uint32_t)P->coefs.size();
-                cd U[16];
-                qk_gate rec{};
-                rec.kind = g.kind; rec.nq = g.nq;
-                rec.p[0] = g.p[0]; rec.p[1] = g.p[1]; rec.p[2] = g.p[2];
-                gate_unitary(rec, U);
-                switch (g.kind) {
-                case QK_X: op.code = OP_X; break;
-                case QK_CX: op.code = OP_CX; break;
-                case QK_CZ: op.code = OP_CZ; break;
-                case QK_SWAP: op.code = OP_SWAP; break;
-                case QK_CP: op.code = OP_CPHASE; P->coefs.push_back(U[15]); break;
-                case QK_RZZ:
-                    op.code = OP_DIAG2;
-                    for (int r = 0; r < 4; ++r) P->coefs.push_back(U[r * 5]);
-                    break;
-                case QK_Z: case QK_S: case QK_T: case QK_RZ: case QK_P:
-                    op.code = OP_DIAG1;
-                    P->coefs.push_back(U[0]);
-                    P->coefs.push_back(U[3]);
-                    break;
-                default:
-                    op.code = OP_DENSE1;
-                    for (int r = 0; r < 4; ++r) P->coefs.push_back(U[r]);
-                    break;
-                }
-                P->ops.push_back(op);
-            }
-        }
-        K.n_ops = (int)P->ops.size() - K.op_off;
-        K.desc.n_ops = K.n_ops;
-        P->kernels.push_back(K);
+        emit_kernel(P, j, i, back_t[i], back_cost[i], m_exec);
         j = i;
     }
+    *out = P;
+    return QK_OK;
+}
+
+// One kernel of the given type over the whole (canonicalised) circuit;
+// QK_EINVAL if it is not feasible for that type.  Its cost is the analytic one.
+int build_single(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, int type, qk_plan** out)
+{
+    if (!c || !out) return fail(QK_EINVAL, "kernelize_single: null argument");
+    const int n = c->n_qubits;
+    qk_kopts ko;
+    int mblk = 0;
+    int rc = resolve_opts(ko_in, n, ko, mblk);
+    if (rc) return rc;
+    if (type != QK_KERNEL_FUSED && type != QK_KERNEL_LDS) return fail(QK_EINVAL, "kernelize_single: bad type");
+    if (c->n_gates < 1 || !c->gates) return fail(QK_EINVAL, "kernelize_single: needs at least one gate");
+    qk_plan* P = new qk_plan();
+    P->n = n;
+    P->dtype = ko.dtype;
+    P->ko = ko;
+    P->ctx = ctx;
+    if (ko.tables) P->tab = *ko.tables;
+    else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
+    rc = canonicalize(c, ko, P);
+    if (rc) { delete P; return rc; }
+    const int64_t m = (int64_t)P->gates.size();
+    if (m == 0) { delete P; return fail(QK_EINVAL, "kernelize_single: no gate left after SWAP absorption"); }
+    uint64_t mask = 0;
+    int64_t s = P->tab.lds_alpha_ps;
+    for (const CGate& g : P->gates) {
+        for (int t = 0; t < g.nq; ++t) mask |= 1ull << g.q[t];
+        s += P->tab.lds_gate_ps[gate_class(g.kind)];
+    }
+    const int k = popcount64(mask);
+    const uint64_t lowmask = (1ull << ko.ell) - 1;
+    int64_t cost;
+    if (type == QK_KERNEL_FUSED) {
+        if (k > ko.k_max) { delete P; return fail(QK_EINVAL, "kernelize_single: too many qubits for a fused kernel"); }
+        cost = P->tab.fused_ps[k];
+    } else {
+        if (popcount64(mask | lowmask) > ko.m_max) { delete P; return fail(QK_EINVAL, "kernelize_single: too many qubits for an LDS kernel"); }
+        cost = s;
+    }
+    P->total_cost = cost;
+    emit_kernel(P, 0, m, type, cost, std::min(n, mblk));
     *out = P;
     return QK_OK;
 }

@@ -73,11 +73,41 @@ struct PermDesc {
     uint8_t perm[40];      // source bit b -> destination bit perm[b]
 };
 
+// Register-blocked execution of a staged block: every thread keeps
+// kRbAmps = 16 amplitudes in registers (kRbBits = 4 block bits); a phase is a
+// choice of those 4 bits plus the operations that act only on them.  Moving
+// between phases transposes the block through LDS.
+constexpr int kRbBits = 4;
+constexpr int kRbAmps = 1 << kRbBits;
+
+struct Phase {
+    uint8_t reg[4];      // block bits held in registers: register bit k <-> reg[k]
+    uint16_t op_begin;   // operations [op_begin, op_end) of the kernel's slice,
+    uint16_t op_end;     // with bits given as register positions 0..3
+};
+static_assert(sizeof(Phase) == 8, "Phase layout");
+
+struct RbDesc {
+    BlockDesc b;         // block geometry (act, ell0, m, nblocks)
+    int32_t n_phases;
+    int32_t uses_lds;    // 1 if some phase differs from the I/O layout
+    uint8_t io_reg[4];   // register bits of the HBM load/store layout
+    int32_t pad;
+};
+
+// Threads per workgroup of the register-blocked kernel for a block of 2^m
+// amplitudes (2^m / 16), or 0 when m has no register-blocked variant.
+int rb_threads(int dtype, int m);
+// Register bits of the load/store layout for that thread count.
+void rb_io_reg(int dtype, int threads, uint8_t* reg);
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return a hipError_t value (0 = ok).
 // fused_k = 0: LDS gate sequence (ops[0..n_ops)); 1..7: one dense product.
 int launch_block(int dtype, int fused_k, void* psi, const BlockDesc& d, const Op* ops,
                  const void* coef, void* stream);
+int launch_block_rb(int dtype, void* psi, const RbDesc& d, const Phase* phases, const Op* ops, const void* coef,
+                    void* stream);
 int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream);
 int launch_fill_basis(int dtype, void* psi, uint64_t N, uint64_t x, void* stream);
 // Reductions: partial buffer must hold at least reduce_partials() doubles x 2.
@@ -92,6 +122,17 @@ size_t block_lds_bytes(int dtype, int m, int ell0);
 }  // namespace qk
 
 // ---------------------------------------------------------------- handles
+// Learned cost model of one dtype: standardisation + flat FP32 parameters.
+struct MlpModel {
+    bool loaded = false;
+    float x_mean[20] = {0};
+    float x_std[20] = {0};
+    float y_mean = 0.f;
+    float y_std = 1.f;
+    std::vector<float> params;
+    float* d_params = nullptr;   // device copy (owned by the context)
+};
+
 struct qk_ctx {
     void* stream = nullptr;
     bool host_only = false;
@@ -103,6 +144,7 @@ struct qk_ctx {
     void* d_stage = nullptr;        // staging buffer for host data
     size_t stage_bytes = 0;
     double* h_pinned = nullptr;     // small pinned host buffer for results
+    MlpModel mlp[2];                // learned cost model per dtype
 };
 
 struct qk_state {
