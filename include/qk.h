@@ -310,6 +310,36 @@ int mlp_forward_backward(qk_ctx* ctx, const float* params, const float* x, const
  * updating params, m and v in place (host arrays of mlp_num_params floats). */
 int mlp_adam_step(qk_ctx* ctx, float* params, const float* grads, float* m, float* v, float lr, int step);
 
+/* ---- batched execution ---------------------------------------------------
+ * Many circuits of uneven size in one persistent launch (an addition to the
+ * paper's method).  Each circuit is kernelized on the host with kos[i] (or,
+ * when kos is NULL, the options tuned for its qubit count, else defaults);
+ * workgroups then take (circuit, kernel, block) items from a device queue,
+ * and kernel s of a circuit starts a block only after all blocks of its
+ * kernel s-1 are done.  A circuit whose state is a single staged block runs
+ * all its kernels in one item.  States must be distinct, share one dtype and
+ * be in logical order; they are in logical order on return.  latency_ms[i]
+ * (may be NULL) receives the time from the launch start to circuit i's
+ * completion, from the device wall clock. */
+typedef struct qk_batch_stats {
+    double total_ms;          /* launch duration (HIP events) */
+    int64_t items;            /* queue items (block-kernels) */
+    int32_t whole_circuits;   /* circuits run as a single item */
+    int32_t errors;           /* dependency waits that hit their limit (0) */
+} qk_batch_stats;
+int simulate_batch(qk_ctx* ctx, const qk_circuit* circuits, qk_state* const* states, int64_t count,
+                   const qk_kopts* kos, double* latency_ms, qk_batch_stats* stats);
+
+/* Autotuner: for every n in [n_lo, n_hi] (4..26) time batches of 8 copies of
+ * a layered RY/RZ/CX-ring circuit under a grid of (k_max, block qubits, ell)
+ * and keep the fastest options in the context (used by simulate_batch when
+ * kos is NULL).  Writes a text cache to cache_path when it is not NULL. */
+int qk_autotune(qk_ctx* ctx, int dtype, int n_lo, int n_hi, int reps, const char* cache_path);
+int qk_autotune_load(qk_ctx* ctx, int dtype, const char* path);
+int qk_set_tuned(qk_ctx* ctx, int dtype, int n_qubits, const qk_kopts* ko);
+/* Tuned options for (dtype, n); *found = 0 and defaults when none. */
+int qk_get_tuned(qk_ctx* ctx, int dtype, int n_qubits, qk_kopts* out, int* found);
+
 #ifdef __cplusplus
 }
 #endif

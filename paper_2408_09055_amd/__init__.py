@@ -83,6 +83,11 @@ class qk_train_report(ctypes.Structure):
                 ("val_mape", ctypes.c_double), ("n_train", ctypes.c_int64), ("n_val", ctypes.c_int64)]
 
 
+class qk_batch_stats(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double), ("items", ctypes.c_int64), ("whole_circuits", ctypes.c_int32),
+                ("errors", ctypes.c_int32)]
+
+
 NUM_FEATURES = 20
 DATA_DIR = os.path.join(_HERE, "data")
 
@@ -129,6 +134,11 @@ _SIGS = {
     "costmodel_predict": [_P, ctypes.c_int, _P, _i64, _P],
     "mlp_forward_backward": [_P, _P, _P, _P, _i64, _P, _P, _P],
     "mlp_adam_step": [_P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int],
+    "simulate_batch": [_P, _P, _P, _i64, _P, _P, ctypes.POINTER(qk_batch_stats)],
+    "qk_autotune": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p],
+    "qk_autotune_load": [_P, ctypes.c_int, ctypes.c_char_p],
+    "qk_set_tuned": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qk_kopts)],
+    "qk_get_tuned": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qk_kopts), ctypes.POINTER(ctypes.c_int)],
 }
 for _name, _args in _SIGS.items():
     try:
@@ -539,3 +549,43 @@ def mlp_adam_step(ctx: Context, params, grads, m, v, lr: float, step: int):
     vv = np.array(v, np.float32)
     _check(_lib.mlp_adam_step(ctx.h, p.ctypes.data, g.ctypes.data, mm.ctypes.data, vv.ctypes.data, lr, step))
     return p, mm, vv
+
+
+def simulate_batch(ctx: Context, circuits, states, kos=None):
+    """Run many circuits in one persistent launch.  Returns (stats dict,
+    per-circuit latency in ms from the device clock)."""
+    n = len(circuits)
+    assert len(states) == n and n > 0
+    cstructs = (qk_circuit * n)()
+    keep = []
+    for i, c in enumerate(circuits):
+        cs = _circuit_struct(c)
+        keep.append(cs)
+        ctypes.memmove(ctypes.byref(cstructs, i * ctypes.sizeof(qk_circuit)), ctypes.byref(cs),
+                       ctypes.sizeof(qk_circuit))
+    sptr = (ctypes.c_void_p * n)(*[s.h.value if isinstance(s.h, ctypes.c_void_p) else s.h for s in states])
+    karr = None
+    if kos is not None:
+        karr = (qk_kopts * n)(*kos)
+    lat = np.zeros(n, np.float64)
+    st = qk_batch_stats()
+    _check(_lib.simulate_batch(ctx.h, ctypes.cast(cstructs, ctypes.c_void_p), ctypes.cast(sptr, ctypes.c_void_p), n,
+                               ctypes.cast(karr, ctypes.c_void_p) if karr is not None else None,
+                               lat.ctypes.data, ctypes.byref(st)))
+    return ({"total_ms": st.total_ms, "items": st.items, "whole_circuits": st.whole_circuits,
+             "errors": st.errors}, lat)
+
+
+def autotune(ctx: Context, dtype: int, n_lo: int, n_hi: int, reps: int = 3, cache_path: str | None = None):
+    _check(_lib.qk_autotune(ctx.h, dtype, n_lo, n_hi, reps, cache_path.encode() if cache_path else None))
+
+
+def autotune_load(ctx: Context, dtype: int, path: str):
+    _check(_lib.qk_autotune_load(ctx.h, dtype, path.encode()))
+
+
+def get_tuned(ctx: Context, dtype: int, n: int):
+    ko = qk_kopts()
+    f = ctypes.c_int()
+    _check(_lib.qk_get_tuned(ctx.h, dtype, n, ctypes.byref(ko), ctypes.byref(f)))
+    return ko, bool(f.value)

@@ -392,6 +392,132 @@ __global__ __launch_bounds__(kNT) void k_block_dense(C* __restrict__ psi, BlockD
     });
 }
 
+// ----------------------------------------------------------- MFMA fused kernel
+// A fused kernel on K bits views the staged block as the complex matrix
+// X[r][c] (r: the K kernel bits, c: the other m - K block bits) and computes
+// Y = U X as the real product
+//     [Yr; Yi] = [[Ur, -Ui], [Ui, Ur]] [Xr; Xi]      (2D x 2D times 2D x N)
+// with D = 2^K, N = 2^(m-K), on 16x16x4 matrix-core tiles (FP32 for complex64,
+// FP64 for complex128).  Lane layout of the 16x16x4 instruction (wave64):
+// A lane l = A[l % 16][l / 16], B lane l = B[l / 16][l % 16], accumulator
+// register v of lane l = C[4 (l / 16) + v][l % 16].
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct MfmaAcc;
+template <> struct MfmaAcc<float> { using T = mf4; };
+template <> struct MfmaAcc<double> { using T = md4; };
+
+__device__ __forceinline__ mf4 mfma16(float a, float b, mf4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ md4 mfma16(double a, double b, md4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Element (i, k) of the real expansion of U (D x D complex, row-major).
+template <typename C>
+__device__ __forceinline__ typename Real<C>::T uexp(const C* __restrict__ U, int D, int i, int k)
+{
+    const C u = U[(i & (D - 1)) * D + (k & (D - 1))];
+    const bool lo_i = i < D, lo_k = k < D;
+    return lo_i == lo_k ? u.x : (lo_i ? -u.y : u.y);
+}
+
+template <typename C, int K>
+__global__ __launch_bounds__(kNT) void k_block_mfma(C* __restrict__ psi, BlockDesc d, const Op* __restrict__ ops,
+                                                    const C* __restrict__ coef)
+{
+    using R = typename Real<C>::T;
+    using Acc = typename MfmaAcc<R>::T;
+    constexpr int D = 1 << K, M2 = 2 * D;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t rowtab[D];
+    C* sm = reinterpret_cast<C*>(smem);
+    R* smr = reinterpret_cast<R*>(smem);
+    const Op op = ops[0];
+    const C* __restrict__ U = coef + op.coef;
+    const int m = d.m;
+    const int N = 1 << (m - K);
+    // rows: deposit over the kernel bits; columns: over the remaining bits
+    uint8_t ob[16];
+    {
+        int j = 0;
+        for (int b = 0; b < m; ++b) {
+            bool kb = false;
+            for (int u = 0; u < K; ++u) kb |= op.b[u] == b;
+            if (!kb) ob[j++] = (uint8_t)b;
+        }
+    }
+    for (int r = threadIdx.x; r < D; r += kNT) {
+        uint32_t o = 0;
+        for (int u = 0; u < K; ++u) if ((r >> u) & 1) o |= 1u << op.b[u];
+        rowtab[r] = o;
+    }
+    // wave tiling of the 16x16 output tiles: TM x TN tiles, 4 waves
+    const int TM = M2 / 16, TN = N / 16;
+    const int RM = TM < 4 ? TM : 4;
+    const int RN = (TM * TN / 4) / RM;
+    const int WN = TN / RN;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int tm0 = (wave / WN) * RM, tn0 = (wave % WN) * RN;
+    const int lr = lane % 16, lk = lane / 16;
+    block_loop(psi, d, sm, [&](C*, int) {
+        // column offsets of this lane's B columns (RN tiles, col = 16 tn + lr)
+        constexpr int MAXRN = 16;
+        uint32_t coff[MAXRN];
+#pragma unroll
+        for (int t = 0; t < MAXRN; ++t) {
+            coff[t] = 0;
+            if (t < RN) {
+                const uint32_t c = 16 * (tn0 + t) + lr;
+                uint32_t o = 0;
+                for (int j = 0; j < m - K; ++j) if ((c >> j) & 1) o |= 1u << ob[j];
+                coff[t] = o;
+            }
+        }
+        Acc acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+        for (int s4 = 0; s4 < M2; s4 += 4) {
+            const int k = s4 + lk;                       // this lane's k row
+            const uint32_t roff = rowtab[k & (D - 1)];
+            const int part = k >= D ? 1 : 0;
+            R bfr[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                bfr[t] = t < RN ? smr[2 * (roff + coff[t]) + part] : R(0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                if (a >= RM) break;
+                const R afr = uexp(U, D, 16 * (tm0 + a) + lr, k);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < RN) acc[a][t] = mfma16(afr, bfr[t], acc[a][t]);
+            }
+        }
+        __syncthreads();   // every wave has read its X columns before any Y is written
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            if (a >= RM) break;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t >= RN) break;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * (tm0 + a) + 4 * lk + v;
+                    smr[2 * (rowtab[i & (D - 1)] + coff[t]) + (i >= D ? 1 : 0)] = acc[a][t][v];
+                }
+            }
+        }
+        __syncthreads();
+    });
+}
+
 // ----------------------------------------------------------- register-blocked kernel
 // Each thread holds kRbAmps = 16 amplitudes v[rho]; register bit k of rho is
 // block bit reg[k] of the current phase, the thread index supplies the other
@@ -700,6 +826,135 @@ __global__ __launch_bounds__(NT) void k_block_rb(C* __restrict__ psi, RbDesc d, 
     }
 }
 
+// ----------------------------------------------------------- batched execution
+// One persistent launch runs many circuits.  Workgroups take queue positions
+// from an atomic counter; a position names (circuit, kernel, block).  Kernel
+// s of a circuit may start a block only after all blocks of kernels 0..s-1
+// are done (per-circuit counter, released and acquired at agent scope, since
+// the eight XCDs have separate L2 caches).  Queue order puts every kernel's
+// blocks after the previous kernel's, and all workgroups are resident, so a
+// waited-on block is always held by a running workgroup; every wait is also
+// bounded by a spin limit, after which the item is skipped and an error is
+// counted.  A circuit whose state is a single block runs all its kernels in
+// one item.  Operations run on the LDS-staged block (any block size).
+template <typename C>
+__device__ void batch_ops(C* sm, int m, const Op* __restrict__ ops, int n_ops, int fused_k, const C* __restrict__ coef)
+{
+    for (int o = 0; o < n_ops; ++o) {
+        const Op op = ops[o];
+        const C* u = coef + op.coef;
+        switch (op.code) {
+        case OP_DENSE1: op_dense1(sm, m, op.b[0], u); break;
+        case OP_DIAG1: op_diag1(sm, m, op.b[0], u); break;
+        case OP_X: op_x(sm, m, op.b[0]); break;
+        case OP_CX: op_cx(sm, m, op.b[0], op.b[1]); break;
+        case OP_CZ: op_cz(sm, m, op.b[0], op.b[1]); break;
+        case OP_CPHASE: op_cphase(sm, m, op.b[0], op.b[1], u); break;
+        case OP_DIAG2: op_diag2(sm, m, op.b[0], op.b[1], u); break;
+        case OP_SWAP: op_swap(sm, m, op.b[0], op.b[1]); break;
+        case OP_DENSEK:
+            switch (op.k) {
+            case 1: op_densek_group<C, 1>(sm, m, op.b, u); break;
+            case 2: op_densek_group<C, 2>(sm, m, op.b, u); break;
+            case 3: op_densek_group<C, 3>(sm, m, op.b, u); break;
+            case 4: op_densek_rows<C, 4>(sm, m, op.b, u); break;
+            case 5: op_densek_rows<C, 5>(sm, m, op.b, u); break;
+            case 6: op_densek_rows<C, 6>(sm, m, op.b, u); break;
+            default: op_densek_rows<C, 7>(sm, m, op.b, u); break;
+            }
+            break;
+        default: break;
+        }
+        __syncthreads();
+    }
+    (void)fused_k;
+}
+
+template <typename C>
+__device__ void batch_block_io(C* __restrict__ psi, const BlockDesc& d, uint64_t blk, C* sm, bool load)
+{
+    constexpr int CH = 16 / sizeof(C);
+    const int m = d.m;
+    const uint32_t nch = (1u << m) / CH;
+    const uint64_t base = block_base(blk, d.act, m);
+    for (uint32_t c = threadIdx.x; c < nch; c += kNT) {
+        const uint64_t a = base + deposit(c * CH, d.act, m);
+        if (load) *reinterpret_cast<u32x4*>(&sm[c * CH]) = *reinterpret_cast<const u32x4*>(&psi[a]);
+        else *reinterpret_cast<u32x4*>(&psi[a]) = *reinterpret_cast<const u32x4*>(&sm[c * CH]);
+    }
+}
+
+template <typename C>
+__global__ __launch_bounds__(kNT) void k_batch(BatchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_skip;
+    C* sm = reinterpret_cast<C*>(smem);
+    const C* coef = reinterpret_cast<const C*>(a.coef);
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        // launch start: the first workgroup's clock
+        __hip_atomic_store(a.t_start, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = __hip_atomic_fetch_add(a.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint64_t item = s_item;
+        if (item >= a.total_items) break;
+        // segment holding this queue position (binary search on item_begin)
+        uint32_t lo = 0, hi = a.n_segs - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (a.seg[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+        }
+        const BatchSeg sg = a.seg[lo];
+        const BatchCirc ci = a.circ[sg.circ];
+        const uint64_t blk = item - sg.item_begin;
+        if (threadIdx.x == 0) {
+            uint32_t skip = 0;
+            if (!ci.whole && sg.kern > 0) {
+                const uint32_t need = sg.kern * ci.nblocks;
+                uint32_t spins = 0;
+                while (__hip_atomic_load(a.done + sg.circ, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (++spins > a.spin_limit) { skip = 1; break; }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            s_skip = skip;
+        }
+        __syncthreads();
+        // every wave sees the producers' writes
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        C* psi = reinterpret_cast<C*>(ci.psi);
+        if (!s_skip) {
+            const uint32_t k0 = ci.whole ? 0 : sg.kern, k1 = ci.whole ? ci.n_kernels : sg.kern + 1;
+            const BatchKern& first = a.kern[ci.kern_off + k0];
+            batch_block_io(psi, first.d, blk, sm, true);
+            __syncthreads();
+            for (uint32_t k = k0; k < k1; ++k) {
+                const BatchKern& kk = a.kern[ci.kern_off + k];
+                batch_ops(sm, kk.d.m, a.ops + kk.op_off, kk.d.n_ops, kk.fused_k, coef);
+            }
+            batch_block_io(psi, first.d, blk, sm, false);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_skip) __hip_atomic_fetch_add(a.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t add = ci.whole ? ci.n_kernels * ci.nblocks : 1u;
+            const uint32_t prev = __hip_atomic_fetch_add(a.done + sg.circ, add, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev + add == ci.n_kernels * ci.nblocks)
+                __hip_atomic_store(a.t_done + sg.circ, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t value)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
 // ----------------------------------------------------------- permutation pass
 // Tile = the 2^m amplitudes with fixed source bits outside act_src.  Reads
 // use the source run (lo_src low bits contiguous), writes the destination run.
@@ -923,6 +1178,19 @@ int launch_one(F* f, C* psi, const BlockDesc& d, const Op* ops, const void* coef
     return (int)hipGetLastError();
 }
 
+// The matrix-core tiling needs 16 | 2^(m-K) columns, 4 waves over whole
+// tiles and at most 4 x 4 tiles per wave.
+bool mfma_ok(int K, int m)
+{
+    if (m - K < 4) return false;
+    const int TM = (2 << K) / 16, TN = (1 << (m - K)) / 16;
+    if ((TM * TN) % 4) return false;
+    const int RM = TM < 4 ? TM : 4;
+    const int RN = (TM * TN / 4) / RM;
+    return RN >= 1 && RN <= 4 && RM * RN * 4 == TM * TN && TN % RN == 0 && TM % RM == 0 &&
+           (TM / RM) * (TN / RN) == 4;
+}
+
 template <typename C>
 int launch_typed(int fused_k, void* psi, const BlockDesc& d, const Op* ops, const void* coef, size_t lds,
                  hipStream_t s)
@@ -934,9 +1202,12 @@ int launch_typed(int fused_k, void* psi, const BlockDesc& d, const Op* ops, cons
     case 2: return launch_one<C>(k_block_dense<C, 2>, p, d, ops, coef, lds, s);
     case 3: return launch_one<C>(k_block_dense<C, 3>, p, d, ops, coef, lds, s);
     case 4: return launch_one<C>(k_block_dense<C, 4>, p, d, ops, coef, lds, s);
-    case 5: return launch_one<C>(k_block_dense<C, 5>, p, d, ops, coef, lds, s);
-    case 6: return launch_one<C>(k_block_dense<C, 6>, p, d, ops, coef, lds, s);
-    case 7: return launch_one<C>(k_block_dense<C, 7>, p, d, ops, coef, lds, s);
+    case 5: return mfma_ok(5, d.m) ? launch_one<C>(k_block_mfma<C, 5>, p, d, ops, coef, lds, s)
+                                   : launch_one<C>(k_block_dense<C, 5>, p, d, ops, coef, lds, s);
+    case 6: return mfma_ok(6, d.m) ? launch_one<C>(k_block_mfma<C, 6>, p, d, ops, coef, lds, s)
+                                   : launch_one<C>(k_block_dense<C, 6>, p, d, ops, coef, lds, s);
+    case 7: return mfma_ok(7, d.m) ? launch_one<C>(k_block_mfma<C, 7>, p, d, ops, coef, lds, s)
+                                   : launch_one<C>(k_block_dense<C, 7>, p, d, ops, coef, lds, s);
     default: return (int)hipErrorInvalidValue;
     }
 }
@@ -1059,6 +1330,27 @@ int launch_gather(int dtype, const void* psi, const uint64_t* idx, uint64_t cnt,
     else
         hipLaunchKernelGGL(k_gather<float2>, dim3((uint32_t)blocks), dim3(kNT), 0, s, (const float2*)psi, idx, cnt,
                            (double2*)out);
+    return (int)hipGetLastError();
+}
+
+int launch_batch(int dtype, const BatchArgs& a, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const size_t lds = 64 * 1024;
+    const void* f = dtype == QK_C128 ? reinterpret_cast<const void*>(k_batch<double2>)
+                                     : reinterpret_cast<const void*>(k_batch<float2>);
+    const uint64_t res = resident_groups(f, lds);
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res, a.total_items));
+    if (dtype == QK_C128) hipLaunchKernelGGL(k_batch<double2>, dim3(grid), dim3(kNT), lds, s, a);
+    else hipLaunchKernelGGL(k_batch<float2>, dim3(grid), dim3(kNT), lds, s, a);
+    return (int)hipGetLastError();
+}
+
+int launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, void* stream)
+{
+    if (count == 0) return 0;
+    const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, p, count, value);
     return (int)hipGetLastError();
 }
 

@@ -1,0 +1,90 @@
+"""Batched persistent execution: every circuit of a batch matches the FP64
+oracle (or the single-circuit path), the dependency waits never expire, and
+the autotuner's cache round-trips."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+qk = pytest.importorskip("paper_2408_09055_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = qk.Context()
+    yield c
+    c.close()
+
+
+def _bar(dtype):
+    return 1e-12 if dtype == qk.QK_C128 else 1e-6
+
+
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_small_batch_vs_oracle(ctx, dtype):
+    circs = W.hea_batch(24, seed=40 + dtype, n_lo=4, n_hi=16, d_lo=2, d_hi=6)
+    circs.append(W.qft(15))
+    circs.append(W.from_list(9, [W.gate(W.SWAP, [0, 8]), W.gate(W.H, [0])]))
+    states = []
+    for c in circs:
+        st = qk.sv_alloc(ctx, c.n_qubits, dtype)
+        st.init_basis(0)
+        states.append(st)
+    stats, lat = qk.simulate_batch(ctx, circs, states)
+    assert stats["errors"] == 0 and stats["items"] > 0
+    assert np.all(lat > 0)
+    for c, st in zip(circs, states):
+        ref = oracle.run(c, oracle.basis(c.n_qubits, 0))
+        got = st.download()
+        assert oracle.fidelity_loss(got, ref) <= _bar(dtype), c.name
+        st.free()
+
+
+def test_ansatz_sweep_batch(ctx):
+    """The batched-sweep workload: 256 ansatz circuits, n uniform 10..22,
+    depth 4..12, complex64, one launch; a sample checked against the oracle
+    (all the large ones among the sample) and every circuit against the
+    one-circuit-at-a-time path."""
+    circs = W.hea_batch(256, seed=4)
+    states = []
+    for c in circs:
+        st = qk.sv_alloc(ctx, c.n_qubits, qk.QK_C64)
+        st.init_basis(0)
+        states.append(st)
+    stats, lat = qk.simulate_batch(ctx, circs, states)
+    assert stats["errors"] == 0
+    print(f"batch: {stats} p50={np.percentile(lat, 50):.3f} ms p99={np.percentile(lat, 99):.3f} ms")
+    rng = np.random.default_rng(0)
+    sample = set(rng.choice(len(circs), 10, replace=False).tolist())
+    sample.add(int(np.argmax([c.n_qubits for c in circs])))
+    for i, (c, st) in enumerate(zip(circs, states)):
+        got = st.download()
+        if i in sample:
+            ref = oracle.run(c, oracle.basis(c.n_qubits, 0))
+            assert oracle.fidelity_loss(got, ref) <= 1e-6, c.name
+        one = qk.sv_alloc(ctx, c.n_qubits, qk.QK_C64)
+        one.init_basis(0)
+        qk.simulate(ctx, c, one, qk.kopts(dtype=qk.QK_C64))
+        assert oracle.fidelity_loss(got, one.download()) <= 1e-6, c.name
+        one.free()
+        st.free()
+
+
+def test_autotune_and_cache(ctx, tmp_path):
+    path = str(tmp_path / "tune.txt")
+    qk.autotune(ctx, qk.QK_C64, 10, 11, reps=1, cache_path=path)
+    ko, found = qk.get_tuned(ctx, qk.QK_C64, 11)
+    assert found and 1 <= ko.k_max <= 7
+    c2 = qk.Context()
+    qk.autotune_load(c2, qk.QK_C64, path)
+    ko2, found2 = qk.get_tuned(c2, qk.QK_C64, 11)
+    assert found2 and (ko2.k_max, ko2.m_max, ko2.ell) == (ko.k_max, ko.m_max, ko.ell)
+    bad = str(tmp_path / "bad.txt")
+    open(bad, "w").write(open(path).read().replace("k_max", "kmax", 1))
+    with pytest.raises(qk.QkError):
+        qk.autotune_load(c2, qk.QK_C64, bad)
+    c2.close()
