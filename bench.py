@@ -48,9 +48,18 @@ def run_gpu(args):
     dtype = qk.QK_C64
     ctx = qk.Context()
     stream = torch.cuda.current_stream()
+    # the analytic model's constants, measured on this device (calibration
+    # procedure of the paper's experimental setup)
+    t0 = time.perf_counter()
+    tables = ctx.calibrate(n, dtype, reps=3)
+    calib_s = time.perf_counter() - t0
+    have_model = ctx.load_costmodel(dtype)
+    cost = args.cost or ("both" if have_model else "analytic")
+    if cost in ("learned", "both") and not have_model:
+        raise SystemExit("no trained cost model at " + qk.costmodel_path(dtype))
     st = qk.sv_alloc(ctx, n, dtype)
     circuits = build_circuits(n)
-    models = ["analytic"] if args.cost == "analytic" else ["learned"] if args.cost == "learned" else ["analytic", "learned"]
+    models = ["analytic"] if cost == "analytic" else ["learned"] if cost == "learned" else ["analytic", "learned"]
 
     plans = {}
     kern_s = {}
@@ -61,9 +70,12 @@ def run_gpu(args):
             plans[(model, name)] = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, cost_model=cm, k_max=args.k_max,
                                                                     m_max=args.m_max, ell=args.ell))
             kern_s[(model, name)] = time.perf_counter() - t0
+            if model == "learned":
+                assert plans[(model, name)].cost_model()["learned_used"]
 
     amp_bytes = 8
     pass_bytes = 2 * (1 << n) * amp_bytes
+    impl_of = {key: [qk.IMPL_NAMES[k.impl] for k in p.kernels()] for key, p in plans.items()}
 
     def one_step(model, record_kernels):
         """Runs the three circuits; returns per-circuit ms and kernel timings."""
@@ -76,6 +88,7 @@ def run_gpu(args):
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             evs = []
+            impls = impl_of[(model, name)]
             for i in range(len(plan)):
                 if record_kernels:
                     a = torch.cuda.Event(enable_timing=True)
@@ -84,14 +97,14 @@ def run_gpu(args):
                 if record_kernels:
                     b = torch.cuda.Event(enable_timing=True)
                     b.record(stream)
-                    evs.append((a, b))
+                    evs.append((a, b, impls[i]))
             qk.plan_finish(ctx, plan, st)
             e1.record(stream)
             ms[name] = (e0, e1)
             ktimes.append(evs)
         torch.cuda.synchronize()
         out = {k: v[0].elapsed_time(v[1]) for k, v in ms.items()}
-        kt = [a.elapsed_time(b) for evs in ktimes for (a, b) in evs]
+        kt = [(a.elapsed_time(b), im) for evs in ktimes for (a, b, im) in evs]
         return out, kt
 
     results = {}
@@ -113,7 +126,7 @@ def run_gpu(args):
     norm = st.norm2()
     st.free()
     ctx.close()
-    return n, circuits, plans, kern_s, results, pass_bytes, norm
+    return n, circuits, plans, kern_s, results, pass_bytes, norm, tables, calib_s
 
 
 def cpu_baseline(circuits_n: int, sample_n: int, gates_per_circuit: int):
@@ -152,7 +165,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=32)
-    ap.add_argument("--cost", default="analytic", choices=["analytic", "learned", "both"])
+    ap.add_argument("--cost", default=None, choices=["analytic", "learned", "both"],
+                    help="default: both when a trained model is present, else analytic")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--k-max", type=int, default=None)
     ap.add_argument("--m-max", type=int, default=None)
@@ -165,7 +179,7 @@ def main():
                                    "(--gpus must be 1)"}))
         sys.exit(2)
 
-    n, circuits, plans, kern_s, results, pass_bytes, norm = run_gpu(args)
+    n, circuits, plans, kern_s, results, pass_bytes, norm, tables, calib_s = run_gpu(args)
     import numpy as np
     model = "learned" if "learned" in results else "analytic"
     r = results[model]
@@ -173,8 +187,15 @@ def main():
     step_ms = sum(per_ms.values())
     n_passes = sum(len(plans[(model, name)]) + (1 if name == "qft" else 0) for name, _, _ in circuits)
     gbps = n_passes * pass_bytes / (step_ms * 1e-3) / 1e9
-    kms = np.array(r["kernel_ms"])
+    # dominant device kernel: the implementation with the largest total time
+    by_impl = {}
+    for ms_, im in r["kernel_ms"]:
+        by_impl.setdefault(im, []).append(ms_)
+    dom = max(by_impl, key=lambda k: sum(by_impl[k]))
+    kms = np.array(by_impl[dom])
     achieved = pass_bytes / (float(kms.mean()) * 1e-3) / 1e9
+    kernel_names = {"register": "k_block_rb", "lds_sequence": "k_block_seq", "lds_dense": "k_block_dense",
+                    "mfma_dense": "k_block_mfma"}
     line = {
         "metric": "32q circuit wall time (QFT-32 + RL-32 + GHZ-32, complex64) + HBM GB/s",
         "value": round(step_ms, 3),
@@ -189,7 +210,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"qft{n}(basis seed 30) + rl{n}x20(seed 31) + ghz{n}; complex64; "
-                               f"{model}-cost OrderedKernelize plans", "qubits": n, "cost_model": model},
+                               f"{model}-cost OrderedKernelize plans", "qubits": n, "cost_model": model,
+                   "state_gib": (1 << n) * 8 / 2 ** 30},
         "hbm_gbps": round(gbps, 1),
         "per_circuit_ms": {k: round(v, 3) for k, v in per_ms.items()},
         "plans": {f"{m}/{name}": plan_summary(plans[(m, name)]) for (m, name) in plans},
@@ -197,9 +219,13 @@ def main():
         "norm2_after": norm,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "kernel": "k_block (staged-block kernel)", "launches": int(kms.size),
+                     "kernel": kernel_names[dom], "launches": int(kms.size),
+                     "time_share": {k: round(sum(v) / sum(sum(x) for x in by_impl.values()), 4)
+                                    for k, v in by_impl.items()},
                      "bytes_per_launch": pass_bytes, "avg_ms": round(float(kms.mean()), 4)},
     }
+    line["analytic_tables_ps"] = {"fused": tables[0][1:], "alpha": tables[1], "gate": tables[2],
+                                  "calibration_s": round(calib_s, 2)}
     if len(results) == 2:
         a = sum(float(np.median(v)) for v in results["analytic"]["per"].values())
         line["analytic_ms"] = round(a, 3)

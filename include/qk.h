@@ -201,7 +201,16 @@ typedef struct qk_kernel_info {
     int64_t cost_ps;       /* cost the DP charged for this kernel */
     int32_t block_qubits;  /* staged block size used at run time */
     int32_t n_ops;         /* device operations (1 for a fused kernel) */
+    int32_t impl;          /* device kernel: QK_IMPL_* */
+    int32_t n_phases;      /* register phases (register-blocked kernel), else 0 */
 } qk_kernel_info;
+/* Device kernel that runs a plan kernel. */
+enum {
+    QK_IMPL_LDS_SEQUENCE = 0,   /* block staged in LDS, one pass per gate */
+    QK_IMPL_REGISTER = 1,       /* register-blocked: gates on register bits, LDS transposes */
+    QK_IMPL_LDS_DENSE = 2,      /* dense product on the LDS-staged block (VALU) */
+    QK_IMPL_MFMA_DENSE = 3      /* dense product on matrix cores */
+};
 
 /* Run canonicalisation (SWAP absorption), segment costing, OrderedKernelize
  * and plan building (FP64 products of the fused kernels' gate matrices,

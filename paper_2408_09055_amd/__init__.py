@@ -36,6 +36,8 @@ QK_C64, QK_C128 = 0, 1
 QK_COST_ANALYTIC, QK_COST_LEARNED = 0, 1
 QK_KERNEL_FUSED, QK_KERNEL_LDS = 0, 1
 QK_CTX_HOST_ONLY = 1
+QK_IMPL_LDS_SEQUENCE, QK_IMPL_REGISTER, QK_IMPL_LDS_DENSE, QK_IMPL_MFMA_DENSE = 0, 1, 2, 3
+IMPL_NAMES = ["lds_sequence", "register", "lds_dense", "mfma_dense"]
 NUM_CLASSES = 7
 
 _ERRNAMES = {QK_EINVAL: "QK_EINVAL", QK_ENOMEM: "QK_ENOMEM", QK_EDEVICE: "QK_EDEVICE",
@@ -70,7 +72,8 @@ class qk_kopts(ctypes.Structure):
 class qk_kernel_info(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("k", ctypes.c_int32), ("gate_begin", ctypes.c_int64),
                 ("gate_end", ctypes.c_int64), ("qubit_mask", ctypes.c_uint64), ("cost_ps", ctypes.c_int64),
-                ("block_qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32)]
+                ("block_qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32), ("impl", ctypes.c_int32),
+                ("n_phases", ctypes.c_int32)]
 
 
 class qk_train_opts(ctypes.Structure):
@@ -405,6 +408,8 @@ class KernelInfo:
         self.cost_ps = s.cost_ps
         self.block_qubits = s.block_qubits
         self.n_ops = s.n_ops
+        self.impl = s.impl
+        self.n_phases = s.n_phases
 
     def as_tuple(self):
         return (self.gate_begin, self.gate_end, self.type, self.cost_ps)

@@ -500,6 +500,10 @@ int plan_kernel_info(const qk_plan* p, int64_t i, qk_kernel_info* out)
     out->cost_ps = K.cost;
     out->block_qubits = K.desc.m;
     out->n_ops = K.n_ops;
+    if (K.rb) out->impl = QK_IMPL_REGISTER;
+    else if (K.type == QK_KERNEL_LDS) out->impl = QK_IMPL_LDS_SEQUENCE;
+    else out->impl = K.k >= 5 && mfma_ok(K.k, K.desc.m) ? QK_IMPL_MFMA_DENSE : QK_IMPL_LDS_DENSE;
+    out->n_phases = K.rb ? K.rbd.n_phases : 0;
     return QK_OK;
 }
 

@@ -1182,9 +1182,9 @@ int launch_one(F* f, C* psi, const BlockDesc& d, const Op* ops, const void* coef
 // tiles and at most 4 x 4 tiles per wave.
 bool mfma_ok(int K, int m)
 {
-    if (m - K < 4) return false;
+    if (K < 3 || K > 7 || m - K < 4) return false;
     const int TM = (2 << K) / 16, TN = (1 << (m - K)) / 16;
-    if ((TM * TN) % 4) return false;
+    if (TM < 1 || TN < 1 || (TM * TN) % 4) return false;
     const int RM = TM < 4 ? TM : 4;
     const int RN = (TM * TN / 4) / RM;
     return RN >= 1 && RN <= 4 && RM * RN * 4 == TM * TN && TN % RN == 0 && TM % RM == 0 &&

@@ -155,6 +155,8 @@ int launch_overlap(int dtype, const void* psi, uint64_t offset, uint64_t count,
 int launch_gather(int dtype, const void* psi, const uint64_t* idx, uint64_t cnt,
                   double* out, void* stream);
 size_t block_lds_bytes(int dtype, int m, int ell0);
+// Whether the matrix-core fused kernel handles K kernel bits in a 2^m block.
+bool mfma_ok(int K, int m);
 
 }  // namespace qk
 

@@ -155,3 +155,33 @@ def test_empty_and_swap_only_circuits(hctx):
     assert len(e) == 0 and e.total_cost() == 0
     s = qk.kernelize(hctx, W.from_list(3, [W.gate(W.SWAP, [0, 2])]), qk.kopts())
     assert len(s) == 0 and s.final_layout() == [2, 1, 0]
+
+
+def test_autotune_cache_parse(hctx, tmp_path):
+    """The tuned-options cache is plain text; a host-only context parses it,
+    and malformed caches are refused without touching the stored options."""
+    good = tmp_path / "tune.txt"
+    good.write_text("qk-autotune 1\narch gfx950\ndtype c64\n"
+                    "n 12 k_max 4 m_max 12 ell 6 ms 0.5\nn 14 k_max 3 m_max 11 ell 0 ms 0.9\n")
+    qk.autotune_load(hctx, qk.QK_C64, str(good))
+    ko, found = qk.get_tuned(hctx, qk.QK_C64, 14)
+    assert found and (ko.k_max, ko.m_max, ko.ell) == (3, 11, 0)
+    ko, found = qk.get_tuned(hctx, qk.QK_C64, 13)
+    assert not found and ko.k_max == 5
+    for bad in ("qk-autotune 2\narch gfx950\ndtype c64\n",
+                "qk-autotune 1\narch gfx942\ndtype c64\n",
+                "qk-autotune 1\narch gfx950\ndtype c128\n",
+                "qk-autotune 1\narch gfx950\ndtype c64\nn 12 k_max 9 m_max 12 ell 6 ms 1\n",
+                "qk-autotune 1\narch gfx950\ndtype c64\nn 12 kmax 4 m_max 12 ell 6 ms 1\n"):
+        p = tmp_path / "bad.txt"
+        p.write_text(bad)
+        _expect(qk.QK_EINVAL, qk.autotune_load, hctx, qk.QK_C64, str(p))
+    ko, found = qk.get_tuned(hctx, qk.QK_C64, 12)
+    assert found and (ko.k_max, ko.m_max, ko.ell) == (4, 12, 6)
+
+
+def test_plan_kernel_impl_reported(hctx):
+    plan = qk.kernelize(hctx, W.random_layered(20, 4, 1), qk.kopts())
+    impls = {k.impl for k in plan.kernels()}
+    assert impls <= {qk.QK_IMPL_REGISTER, qk.QK_IMPL_LDS_SEQUENCE, qk.QK_IMPL_LDS_DENSE, qk.QK_IMPL_MFMA_DENSE}
+    assert all(k.n_phases >= 1 for k in plan.kernels() if k.impl == qk.QK_IMPL_REGISTER)
