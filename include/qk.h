@@ -320,21 +320,21 @@ int mlp_forward_backward(qk_ctx* ctx, const float* params, const float* x, const
 int mlp_adam_step(qk_ctx* ctx, float* params, const float* grads, float* m, float* v, float lr, int step);
 
 /* ---- batched execution ---------------------------------------------------
- * Many circuits of uneven size in one persistent launch (an addition to the
- * paper's method).  Each circuit is kernelized on the host with kos[i] (or,
- * when kos is NULL, the options tuned for its qubit count, else defaults);
- * workgroups then take (circuit, kernel, block) items from a device queue,
- * and kernel s of a circuit starts a block only after all blocks of its
- * kernel s-1 are done.  A circuit whose state is a single staged block runs
- * all its kernels in one item.  States must be distinct, share one dtype and
- * be in logical order; they are in logical order on return.  latency_ms[i]
- * (may be NULL) receives the time from the launch start to circuit i's
- * completion, from the device wall clock. */
+ * Many circuits of uneven size in one call (an addition to the paper's
+ * method, for parameter sweeps).  Each circuit is kernelized on the host with
+ * kos[i] (or, when kos is NULL, the options tuned for its qubit count, else
+ * defaults) and its plan uploaded; then the circuits are dealt, largest
+ * predicted cost first, to the least-loaded of four HIP streams, which run
+ * concurrently after the context's stream and before its later work.  States
+ * must be distinct, share one dtype and be in logical order; they are in
+ * logical order on return, and the call synchronises the context's stream.
+ * latency_ms[i] (may be NULL) receives the time from the batch start to
+ * circuit i's completion (HIP events). */
 typedef struct qk_batch_stats {
-    double total_ms;          /* launch duration (HIP events) */
-    int64_t items;            /* queue items (block-kernels) */
-    int32_t whole_circuits;   /* circuits run as a single item */
-    int32_t errors;           /* dependency waits that hit their limit (0) */
+    double total_ms;          /* batch duration (HIP events) */
+    int64_t items;            /* circuits with at least one kernel */
+    int32_t whole_circuits;   /* circuits whose state is a single block */
+    int32_t errors;           /* reserved, 0 */
 } qk_batch_stats;
 int simulate_batch(qk_ctx* ctx, const qk_circuit* circuits, qk_state* const* states, int64_t count,
                    const qk_kopts* kos, double* latency_ms, qk_batch_stats* stats);

@@ -557,8 +557,8 @@ def mlp_adam_step(ctx: Context, params, grads, m, v, lr: float, step: int):
 
 
 def simulate_batch(ctx: Context, circuits, states, kos=None):
-    """Run many circuits in one persistent launch.  Returns (stats dict,
-    per-circuit latency in ms from the device clock)."""
+    """Run many circuits, dealt over the library's HIP streams.  Returns
+    (stats dict, per-circuit latency in ms from the batch start)."""
     n = len(circuits)
     assert len(states) == n and n > 0
     cstructs = (qk_circuit * n)()

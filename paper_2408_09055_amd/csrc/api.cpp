@@ -72,9 +72,8 @@ int sync_stream(qk_ctx* ctx, const char* what)
 // One out-of-place permutation pass: bit b of the physical index moves to
 // bit perm[b].  Chooses the largest p such that the low p bits on both sides
 // fit in one tile of 2^m amplitudes, so reads and writes are 2^p-runs.
-int permute_pass(qk_state* st, const std::vector<int32_t>& perm)
+int permute_pass(qk_state* st, const std::vector<int32_t>& perm, void* stream)
 {
-    qk_ctx* ctx = st->ctx;
     const int n = st->n;
     const int m = std::min(n, st->dtype == QK_C128 ? 12 : 13);
     std::vector<int32_t> inv(n);
@@ -118,12 +117,12 @@ int permute_pass(qk_state* st, const std::vector<int32_t>& perm)
             return fail(QK_ENOMEM, "permutation scratch allocation failed");
         }
     }
-    int e = launch_permute(st->dtype, st->psi, st->tmp, d, ctx->stream);
+    int e = launch_permute(st->dtype, st->psi, st->tmp, d, stream);
     if (e) return hip_fail(e, "permute launch");
     if (st->owned) {
         std::swap(st->psi, st->tmp);
     } else {
-        hipError_t he = hipMemcpyAsync(st->psi, st->tmp, bytes, hipMemcpyDeviceToDevice, (hipStream_t)ctx->stream);
+        hipError_t he = hipMemcpyAsync(st->psi, st->tmp, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
         if (he != hipSuccess) return hip_fail(he, "permute copy-back");
     }
     for (int q = 0; q < n; ++q) st->layout[q] = perm[st->layout[q]];
@@ -131,6 +130,32 @@ int permute_pass(qk_state* st, const std::vector<int32_t>& perm)
 }
 
 }  // namespace
+
+// Back to logical order (layout[q] == q) with one permutation pass on `stream`.
+int restore_on(qk_state* st, void* stream)
+{
+    if (is_identity(st->layout)) return QK_OK;
+    std::vector<int32_t> p(st->n);
+    for (int q = 0; q < st->n; ++q) p[st->layout[q]] = q;
+    return permute_pass(st, p, stream);
+}
+
+// Kernel i of an uploaded plan on the state's amplitudes, enqueued on `stream`.
+int launch_plan_kernel(const qk_plan* p, int64_t i, qk_state* st, void* stream)
+{
+    const PKernel& K = p->kernels[i];
+    int e;
+    if (K.rb) {
+        e = launch_block_rb(p->dtype, st->psi, K.rbd, (const Phase*)p->d_phases + K.ph_off,
+                            (const Op*)p->d_ops + K.rbop_off, p->d_coef, stream);
+    } else {
+        const int fused_k = K.type == QK_KERNEL_FUSED ? K.k : 0;
+        e = launch_block(p->dtype, fused_k, st->psi, K.desc, (const Op*)p->d_ops + K.op_off, p->d_coef, stream);
+    }
+    if (e) return hip_fail(e, "kernel launch");
+    return QK_OK;
+}
+
 }  // namespace qk
 
 using namespace qk;
@@ -199,6 +224,7 @@ int qk_ctx_free(qk_ctx* ctx)
         if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
         for (int d = 0; d < 2; ++d)
             if (ctx->mlp[d].d_params) (void)hipFree(ctx->mlp[d].d_params);
+        for (void* bs : ctx->batch_streams) (void)hipStreamDestroy((hipStream_t)bs);
     }
     delete ctx;
     return QK_OK;
@@ -347,16 +373,13 @@ int sv_permute(qk_state* st, const int32_t* perm)
         seen[p[b]] = 1;
     }
     if (is_identity(p)) return QK_OK;
-    return permute_pass(st, p);
+    return permute_pass(st, p, st->ctx->stream);
 }
 
 int sv_restore(qk_state* st)
 {
     if (!st) return fail(QK_EINVAL, "sv_restore: null state");
-    if (is_identity(st->layout)) return QK_OK;
-    std::vector<int32_t> p(st->n);
-    for (int q = 0; q < st->n; ++q) p[st->layout[q]] = q;
-    return permute_pass(st, p);
+    return restore_on(st, st->ctx->stream);
 }
 
 int sv_norm2(qk_state* st, double* out)
@@ -568,17 +591,7 @@ int apply_kernel(qk_ctx* ctx, const qk_plan* p, int64_t i, qk_state* st)
     if (!p->d_ops) return fail(QK_ESTATE, "apply_kernel: plan was built without a device");
     // single stage: every kernel runs on the layout the plan started from
     if (!is_identity(st->layout)) return fail(QK_ESTATE, "apply_kernel: state layout differs from the plan's");
-    const PKernel& K = p->kernels[i];
-    int e;
-    if (K.rb) {
-        e = launch_block_rb(p->dtype, st->psi, K.rbd, (const Phase*)p->d_phases + K.ph_off,
-                            (const Op*)p->d_ops + K.rbop_off, p->d_coef, ctx->stream);
-    } else {
-        const int fused_k = K.type == QK_KERNEL_FUSED ? K.k : 0;
-        e = launch_block(p->dtype, fused_k, st->psi, K.desc, (const Op*)p->d_ops + K.op_off, p->d_coef, ctx->stream);
-    }
-    if (e) return hip_fail(e, "apply_kernel launch");
-    return QK_OK;
+    return launch_plan_kernel(p, i, st, ctx->stream);
 }
 
 int plan_finish(qk_ctx* ctx, const qk_plan* p, qk_state* st)

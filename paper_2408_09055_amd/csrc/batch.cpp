@@ -1,10 +1,13 @@
-// Batched execution of many circuits in one persistent launch, and the
-// autotuner that picks kernelization options per qubit count.
+// Batched execution of many circuits of uneven size, and the autotuner that
+// picks kernelization options per qubit count.
 //
 // Every circuit is kernelized on the host (OrderedKernelize with the tuned or
-// given options); the plans are packed into one set of device tables and a
-// queue of (circuit, kernel, block) items is run by k_batch (kernels.hip).
-// A circuit whose whole state is one staged block runs as a single item.
+// given options) and its plan uploaded.  The circuits are then dealt, largest
+// predicted cost first, to the least-loaded of a few HIP streams (longest
+// processing time first), and each stream runs its circuits' kernels in
+// order.  Small circuits from different streams share the device, which a
+// single stream cannot do: a kernel on a state of a few blocks fills only a
+// few compute units.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,12 +24,36 @@ namespace qk {
 
 int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_plan** out);
 
+int upload_plan(qk_ctx* ctx, qk_plan* P);
+int restore_on(qk_state* st, void* stream);
+int launch_plan_kernel(const qk_plan* p, int64_t i, qk_state* st, void* stream);
+
 namespace {
 
-struct DevMem {
-    void* p = nullptr;
-    ~DevMem() { if (p) (void)hipFree(p); }
+constexpr int kBatchStreams = 4;
+
+struct EventSet {
+    std::vector<hipEvent_t> ev;
+    ~EventSet() { for (hipEvent_t e : ev) if (e) (void)hipEventDestroy(e); }
+    int make(size_t count)
+    {
+        ev.assign(count, nullptr);
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) { e = nullptr; return fail(QK_EDEVICE, "simulate_batch: event creation failed"); }
+        return QK_OK;
+    }
 };
+
+int batch_streams(qk_ctx* ctx)
+{
+    while ((int)ctx->batch_streams.size() < kBatchStreams) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+            return fail(QK_EDEVICE, "simulate_batch: stream creation failed");
+        ctx->batch_streams.push_back((void*)s);
+    }
+    return QK_OK;
+}
 
 bool tuned_opts(const qk_ctx* ctx, int dtype, int n, qk_kopts* out)
 {
@@ -62,185 +89,97 @@ int simulate_batch(qk_ctx* ctx, const qk_circuit* cs, qk_state* const* sts, int6
         if (st->dtype != dtype) return fail(QK_EINVAL, "simulate_batch: all states must share one dtype");
         for (int q = 0; q < st->n; ++q)
             if (st->layout[q] != q) return fail(QK_ESTATE, "simulate_batch: state is not in logical order");
-        for (int64_t j = 0; j < i; ++j)
-            if (sts[j] == st) return fail(QK_EINVAL, "simulate_batch: a state appears twice");
     }
-    // ---- plans
+    {
+        std::vector<const qk_state*> sorted(sts, sts + count);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(QK_EINVAL, "simulate_batch: a state appears twice");
+    }
+    int rc = batch_streams(ctx);
+    if (rc) return rc;
+    // ---- plans (host DP), uploaded before the timed region
     std::vector<qk_plan*> plans(count, nullptr);
-    auto free_plans = [&]() { for (qk_plan* p : plans) if (p) plan_free(p); };
+    struct PlanGuard {
+        std::vector<qk_plan*>& v;
+        ~PlanGuard() { for (qk_plan* p : v) if (p) plan_free(p); }
+    } guard{plans};
     for (int64_t i = 0; i < count; ++i) {
         qk_kopts ko;
         if (kos) ko = kos[i];
         else if (!tuned_opts(ctx, dtype, cs[i].n_qubits, &ko)) qk_kopts_default(&ko);
         ko.dtype = dtype;
-        int rc = build_plan(ctx, &cs[i], &ko, &plans[i]);
-        if (rc) { free_plans(); return rc; }
+        rc = build_plan(ctx, &cs[i], &ko, &plans[i]);
+        if (rc) return rc;
+        rc = upload_plan(ctx, plans[i]);
+        if (rc) return rc;
     }
-    // ---- tables
-    std::vector<BatchCirc> circ(count);
-    std::vector<BatchKern> kern;
-    std::vector<Op> ops;
-    std::vector<cd> coefs;
-    for (int64_t i = 0; i < count; ++i) {
+    // ---- longest processing time first over the streams
+    std::vector<int64_t> order(count);
+    for (int64_t i = 0; i < count; ++i) order[i] = i;
+    auto weight = [&](int64_t i) {
+        // predicted cost (ps) plus a launch overhead per kernel
+        return (double)plans[i]->total_cost + 4.0e6 * (double)plans[i]->kernels.size();
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return weight(x) > weight(y); });
+    const int ns = (int)ctx->batch_streams.size();
+    std::vector<double> load(ns, 0.0);
+    std::vector<int> stream_of(count, 0);
+    for (int64_t i : order) {
+        const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        stream_of[i] = s;
+        load[s] += weight(i);
+    }
+    EventSet ev;   // [0] start, [1] end, [2 + s] stream s done, [2 + ns + i] circuit i done
+    rc = ev.make(2 + ns + count);
+    if (rc) return rc;
+    hipStream_t s0 = (hipStream_t)ctx->stream;
+    hipError_t he = hipEventRecord(ev.ev[0], s0);
+    for (int s = 0; s < ns && he == hipSuccess; ++s) he = hipStreamWaitEvent((hipStream_t)ctx->batch_streams[s], ev.ev[0], 0);
+    if (he != hipSuccess) return hip_fail(he, "simulate_batch: stream ordering");
+    int64_t items = 0;
+    int32_t whole = 0;
+    for (int64_t i : order) {
         const qk_plan* P = plans[i];
-        BatchCirc& c = circ[i];
-        std::memset(&c, 0, sizeof(c));
-        c.psi = (uint64_t)(uintptr_t)sts[i]->psi;
-        c.kern_off = (uint32_t)kern.size();
-        c.n_kernels = (uint32_t)P->kernels.size();
-        c.nblocks = P->kernels.empty() ? 1u : (uint32_t)P->kernels[0].desc.nblocks;
-        c.whole = c.nblocks == 1 ? 1u : 0u;
-        const uint32_t coef_base = (uint32_t)coefs.size();
-        coefs.insert(coefs.end(), P->coefs.begin(), P->coefs.end());
-        for (const PKernel& K : P->kernels) {
-            BatchKern bk;
-            std::memset(&bk, 0, sizeof(bk));
-            bk.d = K.desc;
-            bk.op_off = (uint32_t)ops.size();
-            bk.fused_k = K.type == QK_KERNEL_FUSED ? (uint32_t)K.k : 0u;
-            for (int o = 0; o < K.n_ops; ++o) {
-                Op op = P->ops[K.op_off + o];
-                op.coef += coef_base;
-                ops.push_back(op);
-            }
-            kern.push_back(bk);
-        }
-    }
-    // queue order: first kernels of the multi-block circuits (largest first),
-    // then the single-block circuits, then the remaining kernels round by round
-    std::vector<int64_t> big, small;
-    for (int64_t i = 0; i < count; ++i) {
-        if (circ[i].n_kernels == 0) continue;
-        (circ[i].whole ? small : big).push_back(i);
-    }
-    std::sort(big.begin(), big.end(), [&](int64_t a, int64_t b) { return cs[a].n_qubits > cs[b].n_qubits; });
-    std::vector<BatchSeg> segs;
-    uint64_t items = 0;
-    auto add_seg = [&](int64_t i, uint32_t k, uint32_t nitems) {
-        BatchSeg sg;
-        std::memset(&sg, 0, sizeof(sg));
-        sg.item_begin = items;
-        sg.circ = (uint32_t)i;
-        sg.kern = k;
-        segs.push_back(sg);
-        items += nitems;
-    };
-    for (int64_t i : big) add_seg(i, 0, circ[i].nblocks);
-    for (int64_t i : small) add_seg(i, 0, 1);
-    uint32_t kmax = 0;
-    for (int64_t i : big) kmax = std::max(kmax, circ[i].n_kernels);
-    for (uint32_t s = 1; s < kmax; ++s)
-        for (int64_t i : big)
-            if (s < circ[i].n_kernels) add_seg(i, s, circ[i].nblocks);
-    // ---- device buffers
-    const size_t amp = dtype == QK_C128 ? 16 : 8;
-    std::vector<char> coef_dev(std::max<size_t>(coefs.size(), 1) * amp);
-    for (size_t t = 0; t < coefs.size(); ++t) {
-        if (dtype == QK_C128) {
-            double v[2] = {coefs[t].real(), coefs[t].imag()};
-            std::memcpy(&coef_dev[t * 16], v, 16);
-        } else {
-            float v[2] = {(float)coefs[t].real(), (float)coefs[t].imag()};
-            std::memcpy(&coef_dev[t * 8], v, 8);
-        }
-    }
-    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t o_circ = 0;
-    const size_t o_kern = align(o_circ + circ.size() * sizeof(BatchCirc));
-    const size_t o_seg = align(o_kern + std::max<size_t>(kern.size(), 1) * sizeof(BatchKern));
-    const size_t o_ops = align(o_seg + std::max<size_t>(segs.size(), 1) * sizeof(BatchSeg));
-    const size_t o_coef = align(o_ops + std::max<size_t>(ops.size(), 1) * sizeof(Op));
-    const size_t o_u32 = align(o_coef + coef_dev.size());      // queue, error, done[count]
-    const size_t n_u32 = 2 + (size_t)count;
-    const size_t o_u64 = align(o_u32 + n_u32 * 4);             // t_start, t_done[count]
-    const size_t total = o_u64 + (1 + (size_t)count) * 8;
-    DevMem mem;
-    if (hipMalloc(&mem.p, total) != hipSuccess) { free_plans(); return fail(QK_ENOMEM, "simulate_batch: table allocation failed"); }
-    char* base = (char*)mem.p;
-    hipStream_t s = (hipStream_t)ctx->stream;
-    int rc = QK_OK;
-    auto up = [&](size_t off, const void* src, size_t bytes) {
-        if (rc || bytes == 0) return;
-        hipError_t e = hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) rc = hip_fail(e, "simulate_batch upload");
-    };
-    up(o_circ, circ.data(), circ.size() * sizeof(BatchCirc));
-    up(o_kern, kern.data(), kern.size() * sizeof(BatchKern));
-    up(o_seg, segs.data(), segs.size() * sizeof(BatchSeg));
-    up(o_ops, ops.data(), ops.size() * sizeof(Op));
-    up(o_coef, coef_dev.data(), coef_dev.size());
-    if (!rc) {
-        // counters and timestamps start at zero (a fill kernel, not a memset)
-        const size_t words = (total - o_u32) / 4;
-        int e = launch_fill_u32((uint32_t*)(base + o_u32), words, 0u, s);
-        if (e) rc = hip_fail(e, "simulate_batch fill");
-    }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = fail(QK_EDEVICE, "event creation");
-    if (!rc && items > 0) {
-        BatchArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.circ = (const BatchCirc*)(base + o_circ);
-        a.kern = (const BatchKern*)(base + o_kern);
-        a.seg = (const BatchSeg*)(base + o_seg);
-        a.ops = (const Op*)(base + o_ops);
-        a.coef = base + o_coef;
-        a.n_segs = (uint32_t)segs.size();
-        a.n_circ = (uint32_t)count;
-        a.total_items = items;
-        a.queue = (uint32_t*)(base + o_u32);
-        a.error = (uint32_t*)(base + o_u32) + 1;
-        a.done = (uint32_t*)(base + o_u32) + 2;
-        a.t_start = (uint64_t*)(base + o_u64);
-        a.t_done = (uint64_t*)(base + o_u64) + 1;
-        a.spin_limit = 1u << 26;
-        (void)hipEventRecord(e0, s);
-        int e = launch_batch(dtype, a, s);
-        (void)hipEventRecord(e1, s);
-        if (e) rc = hip_fail(e, "simulate_batch launch");
-    }
-    std::vector<uint32_t> hu(n_u32, 0);
-    std::vector<uint64_t> ht(1 + count, 0);
-    if (!rc) {
-        (void)hipMemcpyAsync(hu.data(), base + o_u32, n_u32 * 4, hipMemcpyDeviceToHost, s);
-        (void)hipMemcpyAsync(ht.data(), base + o_u64, (1 + count) * 8, hipMemcpyDeviceToHost, s);
-        hipError_t he = hipStreamSynchronize(s);
-        if (he != hipSuccess) rc = hip_fail(he, "simulate_batch");
-    }
-    float total_ms = 0.f;
-    if (!rc && items > 0) (void)hipEventElapsedTime(&total_ms, e0, e1);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (!rc && hu[1] != 0) rc = fail(QK_EDEVICE, "simulate_batch: dependency wait exceeded its limit");
-    if (!rc) {
-        int dev = 0, khz = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-        if (khz <= 0) khz = 100000;
-        for (int64_t i = 0; i < count; ++i) {
-            if (latency_ms)
-                latency_ms[i] = circ[i].n_kernels == 0 || ht[1 + i] < ht[0]
-                                    ? 0.0 : (double)(ht[1 + i] - ht[0]) / (double)khz;
+        void* s = ctx->batch_streams[stream_of[i]];
+        for (int64_t k = 0; k < (int64_t)P->kernels.size() && !rc; ++k) rc = launch_plan_kernel(P, k, sts[i], s);
+        if (!rc) {
             // SWAPs absorbed while planning: record the layout, then restore
-            sts[i]->layout = plans[i]->final_layout;
-            int r2 = sv_restore(sts[i]);
-            if (r2 && !rc) rc = r2;
+            sts[i]->layout = P->final_layout;
+            rc = restore_on(sts[i], s);
         }
-        if (stats) {
-            stats->total_ms = total_ms;
-            stats->items = (int64_t)items;
-            stats->whole_circuits = (int32_t)small.size();
-            stats->errors = (int32_t)hu[1];
+        if (!rc && hipEventRecord(ev.ev[2 + ns + i], (hipStream_t)s) != hipSuccess) rc = fail(QK_EDEVICE, "simulate_batch: event record");
+        if (rc) break;
+        if (!P->kernels.empty()) {
+            ++items;
+            whole += P->kernels[0].desc.nblocks == 1 ? 1 : 0;
         }
     }
-    if (!rc) {
-        hipError_t he = hipStreamSynchronize(s);   // tables stay alive until the launch is done
-        if (he != hipSuccess) rc = hip_fail(he, "simulate_batch");
-    } else {
-        (void)hipStreamSynchronize(s);
+    // the context's stream waits for every batch stream, also after a failure
+    for (int s = 0; s < ns; ++s) {
+        (void)hipEventRecord(ev.ev[2 + s], (hipStream_t)ctx->batch_streams[s]);
+        (void)hipStreamWaitEvent(s0, ev.ev[2 + s], 0);
     }
-    free_plans();
-    return rc;
+    (void)hipEventRecord(ev.ev[1], s0);
+    he = hipStreamSynchronize(s0);
+    if (rc) return rc;
+    if (he != hipSuccess) return hip_fail(he, "simulate_batch");
+    float total_ms = 0.f;
+    (void)hipEventElapsedTime(&total_ms, ev.ev[0], ev.ev[1]);
+    if (latency_ms) {
+        for (int64_t i = 0; i < count; ++i) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ev.ev[0], ev.ev[2 + ns + i]);
+            latency_ms[i] = t;
+        }
+    }
+    if (stats) {
+        stats->total_ms = total_ms;
+        stats->items = items;
+        stats->whole_circuits = whole;
+        stats->errors = 0;
+    }
+    return QK_OK;
 }
 
 int qk_set_tuned(qk_ctx* ctx, int dtype, int n, const qk_kopts* ko)

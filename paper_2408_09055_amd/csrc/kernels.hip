@@ -301,9 +301,15 @@ __device__ __forceinline__ uint64_t block_base(uint64_t blk, const uint8_t* act,
 // fields owned by t and by i, so its amplitude offset is
 // deposit(t part) + deposit(i part): one per-thread value plus a value that is
 // uniform across the workgroup.
+// first/stride = 0/0 selects the grid: blockIdx.x, gridDim.x.
 template <typename C, typename Body>
-__device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc& d, C* sm, Body body)
+__device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc& d, C* sm, Body body,
+                                           uint64_t first = 0, uint64_t stride = 0)
 {
+    if (stride == 0) {
+        first = blockIdx.x;
+        stride = gridDim.x;
+    }
     const int m = d.m;
     const int tid = threadIdx.x;
     constexpr int CH = 16 / sizeof(C);          // amplitudes per 16-byte access
@@ -314,7 +320,7 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
         off_i[I.value] = deposit((uint32_t)I.value * kNT * CH, d.act, m);
     });
 
-    uint64_t blk = blockIdx.x;
+    uint64_t blk = first;
     if (blk >= d.nblocks) return;
     u32x4 buf[kMaxChunks];
     uint64_t base = block_base(blk, d.act, m) + off_t;
@@ -331,7 +337,7 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
             if (c < nch) *reinterpret_cast<u32x4*>(&sm[c * CH]) = buf[I.value];
         });
         __syncthreads();
-        const uint64_t next = blk + gridDim.x;
+        const uint64_t next = blk + stride;
         const uint64_t nbase = next < d.nblocks ? block_base(next, d.act, m) + off_t : 0;
         if (next < d.nblocks) load_all(nbase);
         body(sm, m);
@@ -826,135 +832,6 @@ __global__ __launch_bounds__(NT) void k_block_rb(C* __restrict__ psi, RbDesc d, 
     }
 }
 
-// ----------------------------------------------------------- batched execution
-// One persistent launch runs many circuits.  Workgroups take queue positions
-// from an atomic counter; a position names (circuit, kernel, block).  Kernel
-// s of a circuit may start a block only after all blocks of kernels 0..s-1
-// are done (per-circuit counter, released and acquired at agent scope, since
-// the eight XCDs have separate L2 caches).  Queue order puts every kernel's
-// blocks after the previous kernel's, and all workgroups are resident, so a
-// waited-on block is always held by a running workgroup; every wait is also
-// bounded by a spin limit, after which the item is skipped and an error is
-// counted.  A circuit whose state is a single block runs all its kernels in
-// one item.  Operations run on the LDS-staged block (any block size).
-template <typename C>
-__device__ void batch_ops(C* sm, int m, const Op* __restrict__ ops, int n_ops, int fused_k, const C* __restrict__ coef)
-{
-    for (int o = 0; o < n_ops; ++o) {
-        const Op op = ops[o];
-        const C* u = coef + op.coef;
-        switch (op.code) {
-        case OP_DENSE1: op_dense1(sm, m, op.b[0], u); break;
-        case OP_DIAG1: op_diag1(sm, m, op.b[0], u); break;
-        case OP_X: op_x(sm, m, op.b[0]); break;
-        case OP_CX: op_cx(sm, m, op.b[0], op.b[1]); break;
-        case OP_CZ: op_cz(sm, m, op.b[0], op.b[1]); break;
-        case OP_CPHASE: op_cphase(sm, m, op.b[0], op.b[1], u); break;
-        case OP_DIAG2: op_diag2(sm, m, op.b[0], op.b[1], u); break;
-        case OP_SWAP: op_swap(sm, m, op.b[0], op.b[1]); break;
-        case OP_DENSEK:
-            switch (op.k) {
-            case 1: op_densek_group<C, 1>(sm, m, op.b, u); break;
-            case 2: op_densek_group<C, 2>(sm, m, op.b, u); break;
-            case 3: op_densek_group<C, 3>(sm, m, op.b, u); break;
-            case 4: op_densek_rows<C, 4>(sm, m, op.b, u); break;
-            case 5: op_densek_rows<C, 5>(sm, m, op.b, u); break;
-            case 6: op_densek_rows<C, 6>(sm, m, op.b, u); break;
-            default: op_densek_rows<C, 7>(sm, m, op.b, u); break;
-            }
-            break;
-        default: break;
-        }
-        __syncthreads();
-    }
-    (void)fused_k;
-}
-
-template <typename C>
-__device__ void batch_block_io(C* __restrict__ psi, const BlockDesc& d, uint64_t blk, C* sm, bool load)
-{
-    constexpr int CH = 16 / sizeof(C);
-    const int m = d.m;
-    const uint32_t nch = (1u << m) / CH;
-    const uint64_t base = block_base(blk, d.act, m);
-    for (uint32_t c = threadIdx.x; c < nch; c += kNT) {
-        const uint64_t a = base + deposit(c * CH, d.act, m);
-        if (load) *reinterpret_cast<u32x4*>(&sm[c * CH]) = *reinterpret_cast<const u32x4*>(&psi[a]);
-        else *reinterpret_cast<u32x4*>(&psi[a]) = *reinterpret_cast<const u32x4*>(&sm[c * CH]);
-    }
-}
-
-template <typename C>
-__global__ __launch_bounds__(kNT) void k_batch(BatchArgs a)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_item;
-    __shared__ uint32_t s_skip;
-    C* sm = reinterpret_cast<C*>(smem);
-    const C* coef = reinterpret_cast<const C*>(a.coef);
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        // launch start: the first workgroup's clock
-        __hip_atomic_store(a.t_start, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_item = __hip_atomic_fetch_add(a.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const uint64_t item = s_item;
-        if (item >= a.total_items) break;
-        // segment holding this queue position (binary search on item_begin)
-        uint32_t lo = 0, hi = a.n_segs - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) / 2;
-            if (a.seg[mid].item_begin <= item) lo = mid; else hi = mid - 1;
-        }
-        const BatchSeg sg = a.seg[lo];
-        const BatchCirc ci = a.circ[sg.circ];
-        const uint64_t blk = item - sg.item_begin;
-        if (threadIdx.x == 0) {
-            uint32_t skip = 0;
-            if (!ci.whole && sg.kern > 0) {
-                const uint32_t need = sg.kern * ci.nblocks;
-                uint32_t spins = 0;
-                while (__hip_atomic_load(a.done + sg.circ, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    if (++spins > a.spin_limit) { skip = 1; break; }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-            }
-            s_skip = skip;
-        }
-        __syncthreads();
-        // every wave sees the producers' writes
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        C* psi = reinterpret_cast<C*>(ci.psi);
-        if (!s_skip) {
-            const uint32_t k0 = ci.whole ? 0 : sg.kern, k1 = ci.whole ? ci.n_kernels : sg.kern + 1;
-            const BatchKern& first = a.kern[ci.kern_off + k0];
-            batch_block_io(psi, first.d, blk, sm, true);
-            __syncthreads();
-            for (uint32_t k = k0; k < k1; ++k) {
-                const BatchKern& kk = a.kern[ci.kern_off + k];
-                batch_ops(sm, kk.d.m, a.ops + kk.op_off, kk.d.n_ops, kk.fused_k, coef);
-            }
-            batch_block_io(psi, first.d, blk, sm, false);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (s_skip) __hip_atomic_fetch_add(a.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t add = ci.whole ? ci.n_kernels * ci.nblocks : 1u;
-            const uint32_t prev = __hip_atomic_fetch_add(a.done + sg.circ, add, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev + add == ci.n_kernels * ci.nblocks)
-                __hip_atomic_store(a.t_done + sg.circ, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-__global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t value)
-{
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
-}
-
 // ----------------------------------------------------------- permutation pass
 // Tile = the 2^m amplitudes with fixed source bits outside act_src.  Reads
 // use the source run (lo_src low bits contiguous), writes the destination run.
@@ -1330,27 +1207,6 @@ int launch_gather(int dtype, const void* psi, const uint64_t* idx, uint64_t cnt,
     else
         hipLaunchKernelGGL(k_gather<float2>, dim3((uint32_t)blocks), dim3(kNT), 0, s, (const float2*)psi, idx, cnt,
                            (double2*)out);
-    return (int)hipGetLastError();
-}
-
-int launch_batch(int dtype, const BatchArgs& a, void* stream)
-{
-    hipStream_t s = (hipStream_t)stream;
-    const size_t lds = 64 * 1024;
-    const void* f = dtype == QK_C128 ? reinterpret_cast<const void*>(k_batch<double2>)
-                                     : reinterpret_cast<const void*>(k_batch<float2>);
-    const uint64_t res = resident_groups(f, lds);
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res, a.total_items));
-    if (dtype == QK_C128) hipLaunchKernelGGL(k_batch<double2>, dim3(grid), dim3(kNT), lds, s, a);
-    else hipLaunchKernelGGL(k_batch<float2>, dim3(grid), dim3(kNT), lds, s, a);
-    return (int)hipGetLastError();
-}
-
-int launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, void* stream)
-{
-    if (count == 0) return 0;
-    const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, p, count, value);
     return (int)hipGetLastError();
 }
 

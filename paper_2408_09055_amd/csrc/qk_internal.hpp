@@ -101,42 +101,6 @@ int rb_threads(int dtype, int m);
 // Register bits of the load/store layout for that thread count.
 void rb_io_reg(int dtype, int threads, uint8_t* reg);
 
-// Batched execution: many circuits in one persistent launch.
-struct BatchCirc {
-    uint64_t psi;          // device address of the circuit's state
-    uint32_t kern_off;     // first kernel in the batch kernel table
-    uint32_t n_kernels;
-    uint32_t nblocks;      // blocks per kernel (all kernels of a circuit share it)
-    uint32_t whole;        // 1: the state is one block, all kernels run in one item
-};
-struct BatchKern {
-    BlockDesc d;           // geometry + n_ops
-    uint32_t op_off;       // operations in the batch op table
-    uint32_t fused_k;      // 0: gate sequence, else one dense 2^k product
-};
-struct BatchSeg {
-    uint64_t item_begin;   // first queue position of the segment
-    uint32_t circ;
-    uint32_t kern;         // kernel index within the circuit (ignored when whole)
-};
-struct BatchArgs {
-    const BatchCirc* circ;
-    const BatchKern* kern;
-    const BatchSeg* seg;
-    const Op* ops;
-    const void* coef;
-    uint32_t n_segs;
-    uint32_t n_circ;
-    uint64_t total_items;
-    uint32_t* queue;       // [0] next item
-    uint32_t* done;        // per circuit: completed block-kernels
-    uint64_t* t_done;      // per circuit: completion timestamp
-    uint64_t* t_start;     // [0] launch start timestamp
-    uint32_t* error;       // [0] spin-limit expiries
-    uint32_t spin_limit;
-};
-int launch_batch(int dtype, const BatchArgs& a, void* stream);
-int launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, void* stream);
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return a hipError_t value (0 = ok).
@@ -186,6 +150,8 @@ struct qk_ctx {
     MlpModel mlp[2];                // learned cost model per dtype
     // autotuned kernelization options keyed by n * 2 + dtype
     std::vector<std::pair<int, qk_kopts>> tuned;
+    // streams of the batched executor (created on first use, default priority)
+    std::vector<void*> batch_streams;
 };
 
 struct qk_state {

@@ -1,6 +1,13 @@
-"""Batched persistent execution: every circuit of a batch matches the FP64
-oracle (or the single-circuit path), the dependency waits never expire, and
-the autotuner's cache round-trips."""
+"""Batched execution: every circuit of a batch matches the FP64 oracle (or
+the single-circuit path), latencies are reported, and the autotuner's cache
+round-trips.
+
+The first two tests were written for an earlier single-launch persistent
+batch kernel (workgroups taking circuits from a device queue).  That kernel
+did not finish on the device in two runs, the cause was not found, and it was
+removed; the tests stay, skipped, as the record of that case.  The batch
+executor now deals circuits over HIP streams and runs the same kernels as the
+one-circuit path; the stream_* tests cover it."""
 import numpy as np
 import pytest
 
@@ -20,10 +27,15 @@ def ctx():
     c.close()
 
 
+PERSISTENT_HANG = ("the single-launch persistent batch kernel this test exercised did not finish on the "
+                   "device (two runs); it was removed with its cause unfound")
+
+
 def _bar(dtype):
     return 1e-12 if dtype == qk.QK_C128 else 1e-6
 
 
+@pytest.mark.skip(reason=PERSISTENT_HANG)
 @pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
 def test_small_batch_vs_oracle(ctx, dtype):
     circs = W.hea_batch(24, seed=40 + dtype, n_lo=4, n_hi=16, d_lo=2, d_hi=6)
@@ -44,6 +56,7 @@ def test_small_batch_vs_oracle(ctx, dtype):
         st.free()
 
 
+@pytest.mark.skip(reason=PERSISTENT_HANG)
 def test_ansatz_sweep_batch(ctx):
     """The batched-sweep workload: 256 ansatz circuits, n uniform 10..22,
     depth 4..12, complex64, one launch; a sample checked against the oracle
@@ -58,6 +71,65 @@ def test_ansatz_sweep_batch(ctx):
     stats, lat = qk.simulate_batch(ctx, circs, states)
     assert stats["errors"] == 0
     print(f"batch: {stats} p50={np.percentile(lat, 50):.3f} ms p99={np.percentile(lat, 99):.3f} ms")
+    rng = np.random.default_rng(0)
+    sample = set(rng.choice(len(circs), 10, replace=False).tolist())
+    sample.add(int(np.argmax([c.n_qubits for c in circs])))
+    for i, (c, st) in enumerate(zip(circs, states)):
+        got = st.download()
+        if i in sample:
+            ref = oracle.run(c, oracle.basis(c.n_qubits, 0))
+            assert oracle.fidelity_loss(got, ref) <= 1e-6, c.name
+        one = qk.sv_alloc(ctx, c.n_qubits, qk.QK_C64)
+        one.init_basis(0)
+        qk.simulate(ctx, c, one, qk.kopts(dtype=qk.QK_C64))
+        assert oracle.fidelity_loss(got, one.download()) <= 1e-6, c.name
+        one.free()
+        st.free()
+
+
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_stream_batch_vs_oracle(ctx, dtype):
+    """Uneven circuits (4..16 qubits, a QFT-15, a SWAP-only-plus-H circuit
+    whose absorbed SWAP must be undone, and an empty circuit) against the
+    oracle; every latency lies inside the batch."""
+    circs = W.hea_batch(24, seed=50 + dtype, n_lo=4, n_hi=16, d_lo=2, d_hi=6)
+    circs.append(W.qft(15))
+    circs.append(W.from_list(9, [W.gate(W.SWAP, [0, 8]), W.gate(W.H, [0])]))
+    circs.append(W.from_list(5, []))
+    states = []
+    psis = []
+    for i, c in enumerate(circs):
+        st = qk.sv_alloc(ctx, c.n_qubits, dtype)
+        psi = W.random_state(c.n_qubits, 700 + i)
+        st.upload(psi.astype(st.np_dtype))
+        states.append(st)
+        psis.append(psi)
+    stats, lat = qk.simulate_batch(ctx, circs, states)
+    print(f"stream batch dtype={dtype}: {stats}", flush=True)
+    assert stats["errors"] == 0 and stats["items"] == len(circs) - 1
+    assert np.all(lat >= 0) and np.all(lat <= stats["total_ms"] + 1e-3)
+    for c, st, psi in zip(circs, states, psis):
+        assert st.layout() == list(range(c.n_qubits))
+        ref = oracle.run(c, psi)
+        got = st.download()
+        assert oracle.fidelity_loss(got, ref) <= _bar(dtype), c.name
+        st.free()
+
+
+def test_stream_batch_sweep(ctx):
+    """The batched-sweep workload: 256 ansatz circuits, n uniform 10..22,
+    depth 4..12, complex64; a sample against the oracle (with the largest
+    circuit) and every circuit against the one-circuit-at-a-time path."""
+    circs = W.hea_batch(256, seed=4)
+    states = []
+    for c in circs:
+        st = qk.sv_alloc(ctx, c.n_qubits, qk.QK_C64)
+        st.init_basis(0)
+        states.append(st)
+    stats, lat = qk.simulate_batch(ctx, circs, states)
+    assert stats["errors"] == 0 and stats["items"] == len(circs)
+    print(f"stream batch: {stats} p50={np.percentile(lat, 50):.3f} ms p99={np.percentile(lat, 99):.3f} ms",
+          flush=True)
     rng = np.random.default_rng(0)
     sample = set(rng.choice(len(circs), 10, replace=False).tolist())
     sample.add(int(np.argmax([c.n_qubits for c in circs])))
