@@ -26,6 +26,9 @@
  *    the others only enqueue.  A device fault surfaces as QK_EDEVICE at the
  *    next synchronising call or at qk_sync.
  *  - No function allocates or frees memory it does not document.
+ *  - qk_ctx_free may be called while states or plans of the context are
+ *    still alive: the context is then closed and its resources are released
+ *    when the last of them is freed.
  */
 #ifndef QK_PUBLIC_API_H
 #define QK_PUBLIC_API_H

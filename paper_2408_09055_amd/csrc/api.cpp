@@ -160,6 +160,35 @@ int launch_plan_kernel(const qk_plan* p, int64_t i, qk_state* st, void* stream)
 
 using namespace qk;
 
+namespace qk {
+
+void ctx_destroy(qk_ctx* ctx)
+{
+    if (!ctx->host_only) {
+        (void)hipStreamSynchronize((hipStream_t)ctx->stream);
+        if (ctx->d_partials) (void)hipFree(ctx->d_partials);
+        if (ctx->d_stage) (void)hipFree(ctx->d_stage);
+        if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+        for (int d = 0; d < 2; ++d)
+            if (ctx->mlp[d].d_params) (void)hipFree(ctx->mlp[d].d_params);
+        for (void* bs : ctx->batch_streams) (void)hipStreamDestroy((hipStream_t)bs);
+    }
+    delete ctx;
+}
+
+void ctx_ref(qk_ctx* c)
+{
+    if (c) ++c->users;
+}
+
+void ctx_unref(qk_ctx* c)
+{
+    if (!c) return;
+    if (--c->users == 0 && c->closed) ctx_destroy(c);
+}
+
+}  // namespace qk
+
 extern "C" {
 
 const char* qk_last_error(void) { return g_err.c_str(); }
@@ -217,16 +246,8 @@ int qk_ctx_create(void* hip_stream, uint32_t flags, qk_ctx** out)
 int qk_ctx_free(qk_ctx* ctx)
 {
     if (!ctx) return QK_OK;
-    if (!ctx->host_only) {
-        (void)hipStreamSynchronize((hipStream_t)ctx->stream);
-        if (ctx->d_partials) (void)hipFree(ctx->d_partials);
-        if (ctx->d_stage) (void)hipFree(ctx->d_stage);
-        if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
-        for (int d = 0; d < 2; ++d)
-            if (ctx->mlp[d].d_params) (void)hipFree(ctx->mlp[d].d_params);
-        for (void* bs : ctx->batch_streams) (void)hipStreamDestroy((hipStream_t)bs);
-    }
-    delete ctx;
+    ctx->closed = true;
+    if (ctx->users == 0) qk::ctx_destroy(ctx);
     return QK_OK;
 }
 
@@ -252,6 +273,7 @@ int sv_alloc(qk_ctx* ctx, int n, int dtype, qk_state** out)
     }
     qk_state* st = new qk_state();
     st->ctx = ctx;
+    ctx_ref(ctx);
     st->n = n;
     st->dtype = dtype;
     st->psi = p;
@@ -272,6 +294,7 @@ int sv_wrap(qk_ctx* ctx, void* dev_ptr, int n, int dtype, qk_state** out)
     if (dtype != QK_C64 && dtype != QK_C128) return fail(QK_EINVAL, "sv_wrap: bad dtype");
     qk_state* st = new qk_state();
     st->ctx = ctx;
+    ctx_ref(ctx);
     st->n = n;
     st->dtype = dtype;
     st->psi = dev_ptr;

@@ -404,15 +404,22 @@ __global__ __launch_bounds__(kNT) void k_block_dense(C* __restrict__ psi, BlockD
 // Y = U X as the real product
 //     [Yr; Yi] = [[Ur, -Ui], [Ui, Ur]] [Xr; Xi]      (2D x 2D times 2D x N)
 // with D = 2^K, N = 2^(m-K), on 16x16x4 matrix-core tiles (FP32 for complex64,
-// FP64 for complex128).  Lane layout of the 16x16x4 instruction (wave64):
-// A lane l = A[l % 16][l / 16], B lane l = B[l / 16][l % 16], accumulator
-// register v of lane l = C[4 (l / 16) + v][l % 16].
+// FP64 for complex128).  Lane layout of the 16x16x4 instructions (wave64), as
+// measured on gfx950: A lane l = A[l % 16][l / 16], B lane l = B[l / 16][l % 16];
+// accumulator register v of lane l holds row 4 (l / 16) + v of the 16 x 16
+// tile for FP32 but row (l / 16) + 4 v for FP64 (column l % 16 for both).
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef double md4 __attribute__((ext_vector_type(4)));
 
 template <typename R> struct MfmaAcc;
-template <> struct MfmaAcc<float> { using T = mf4; };
-template <> struct MfmaAcc<double> { using T = md4; };
+template <> struct MfmaAcc<float> {
+    using T = mf4;
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+template <> struct MfmaAcc<double> {
+    using T = md4;
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
 
 __device__ __forceinline__ mf4 mfma16(float a, float b, mf4 c)
 {
@@ -515,7 +522,7 @@ __global__ __launch_bounds__(kNT) void k_block_mfma(C* __restrict__ psi, BlockDe
                 if (t >= RN) break;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int i = 16 * (tm0 + a) + 4 * lk + v;
+                    const int i = 16 * (tm0 + a) + MfmaAcc<R>::row(lk, v);
                     smr[2 * (rowtab[i & (D - 1)] + coff[t]) + (i >= D ? 1 : 0)] = acc[a][t][v];
                 }
             }

@@ -63,4 +63,5 @@ struct qk_plan {
     void* d_ops = nullptr;
     void* d_coef = nullptr;
     void* d_phases = nullptr;
+    ~qk_plan() { qk::ctx_unref(ctx); }
 };

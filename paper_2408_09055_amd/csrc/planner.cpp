@@ -446,6 +446,7 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
     P->dtype = ko.dtype;
     P->ko = ko;
     P->ctx = ctx;
+    ctx_ref(ctx);
     if (ko.tables) P->tab = *ko.tables;
     else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
 
@@ -574,6 +575,7 @@ int build_single(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, int ty
     P->dtype = ko.dtype;
     P->ko = ko;
     P->ctx = ctx;
+    ctx_ref(ctx);
     if (ko.tables) P->tab = *ko.tables;
     else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
     rc = canonicalize(c, ko, P);

@@ -152,7 +152,16 @@ struct qk_ctx {
     std::vector<std::pair<int, qk_kopts>> tuned;
     // streams of the batched executor (created on first use, default priority)
     std::vector<void*> batch_streams;
+    // states and plans that refer to this context; qk_ctx_free only marks the
+    // context closed while any remain, and the last one to go frees it
+    int64_t users = 0;
+    bool closed = false;
 };
+
+namespace qk {
+void ctx_ref(qk_ctx* c);
+void ctx_unref(qk_ctx* c);
+}  // namespace qk
 
 struct qk_state {
     qk_ctx* ctx = nullptr;
@@ -162,4 +171,5 @@ struct qk_state {
     bool owned = false;
     void* tmp = nullptr;            // permutation scratch (same size)
     std::vector<int32_t> layout;    // layout[q] = physical bit of logical q
+    ~qk_state() { qk::ctx_unref(ctx); }
 };

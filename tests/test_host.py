@@ -185,3 +185,13 @@ def test_plan_kernel_impl_reported(hctx):
     impls = {k.impl for k in plan.kernels()}
     assert impls <= {qk.QK_IMPL_REGISTER, qk.QK_IMPL_LDS_SEQUENCE, qk.QK_IMPL_LDS_DENSE, qk.QK_IMPL_MFMA_DENSE}
     assert all(k.n_phases >= 1 for k in plan.kernels() if k.impl == qk.QK_IMPL_REGISTER)
+
+
+def test_context_outlives_its_plans():
+    """Closing a context while a plan is alive defers the release: the plan
+    can still be inspected and freed afterwards."""
+    ctx = qk.Context(host_only=True)
+    plan = qk.kernelize(ctx, W.qft(10), qk.kopts(dtype=qk.QK_C64))
+    ctx.close()
+    assert len(plan) > 0 and plan.total_cost() > 0
+    plan.free()
