@@ -206,6 +206,7 @@ typedef struct qk_kernel_info {
     int32_t n_ops;         /* device operations (1 for a fused kernel) */
     int32_t impl;          /* device kernel: QK_IMPL_* */
     int32_t n_phases;      /* register phases (register-blocked kernel), else 0 */
+    int32_t n_transposes;  /* LDS layout changes per block (register-blocked kernel), else 0 */
 } qk_kernel_info;
 /* Device kernel that runs a plan kernel. */
 enum {

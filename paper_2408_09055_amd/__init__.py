@@ -73,7 +73,7 @@ class qk_kernel_info(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("k", ctypes.c_int32), ("gate_begin", ctypes.c_int64),
                 ("gate_end", ctypes.c_int64), ("qubit_mask", ctypes.c_uint64), ("cost_ps", ctypes.c_int64),
                 ("block_qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32), ("impl", ctypes.c_int32),
-                ("n_phases", ctypes.c_int32)]
+                ("n_phases", ctypes.c_int32), ("n_transposes", ctypes.c_int32)]
 
 
 class qk_train_opts(ctypes.Structure):
@@ -410,6 +410,7 @@ class KernelInfo:
         self.n_ops = s.n_ops
         self.impl = s.impl
         self.n_phases = s.n_phases
+        self.n_transposes = s.n_transposes
 
     def as_tuple(self):
         return (self.gate_begin, self.gate_end, self.type, self.cost_ps)

@@ -146,8 +146,7 @@ int launch_plan_kernel(const qk_plan* p, int64_t i, qk_state* st, void* stream)
     const PKernel& K = p->kernels[i];
     int e;
     if (K.rb) {
-        e = launch_block_rb(p->dtype, st->psi, K.rbd, (const Phase*)p->d_phases + K.ph_off,
-                            (const Op*)p->d_ops + K.rbop_off, p->d_coef, stream);
+        e = launch_block_rb(p->dtype, st->psi, K.rbd, (const uint8_t*)p->d_rbprog + K.prog_off, stream);
     } else {
         const int fused_k = K.type == QK_KERNEL_FUSED ? K.k : 0;
         e = launch_block(p->dtype, fused_k, st->psi, K.desc, (const Op*)p->d_ops + K.op_off, p->d_coef, stream);
@@ -493,11 +492,11 @@ int upload_plan(qk_ctx* ctx, qk_plan* P)
                 f[2 * i + 1] = (float)P->coefs[i].imag();
             }
         }
-        if (!P->phases.empty()) {
-            if (hipMalloc(&P->d_phases, P->phases.size() * sizeof(Phase)) != hipSuccess)
+        if (!P->rbprog.empty()) {
+            if (hipMalloc(&P->d_rbprog, P->rbprog.size()) != hipSuccess)
                 return fail(QK_ENOMEM, "kernelize: plan upload allocation failed");
-            hipError_t e0 = hipMemcpyAsync(P->d_phases, P->phases.data(), P->phases.size() * sizeof(Phase),
-                                           hipMemcpyHostToDevice, (hipStream_t)ctx->stream);
+            hipError_t e0 = hipMemcpyAsync(P->d_rbprog, P->rbprog.data(), P->rbprog.size(), hipMemcpyHostToDevice,
+                                           (hipStream_t)ctx->stream);
             if (e0 != hipSuccess) return hip_fail(e0, "kernelize: plan upload");
         }
         hipError_t e1 = hipMemcpyAsync(P->d_ops, P->ops.data(), ob, hipMemcpyHostToDevice, (hipStream_t)ctx->stream);
@@ -550,6 +549,7 @@ int plan_kernel_info(const qk_plan* p, int64_t i, qk_kernel_info* out)
     else if (K.type == QK_KERNEL_LDS) out->impl = QK_IMPL_LDS_SEQUENCE;
     else out->impl = K.k >= 5 && mfma_ok(K.k, K.desc.m) ? QK_IMPL_MFMA_DENSE : QK_IMPL_LDS_DENSE;
     out->n_phases = K.rb ? K.rbd.n_phases : 0;
+    out->n_transposes = K.rb ? K.rbd.n_transposes : 0;
     return QK_OK;
 }
 
@@ -593,11 +593,11 @@ int plan_final_layout(const qk_plan* p, int32_t* perm)
 int plan_free(qk_plan* p)
 {
     if (!p) return QK_OK;
-    if (p->ctx && !p->ctx->host_only && (p->d_ops || p->d_coef || p->d_phases)) {
+    if (p->ctx && !p->ctx->host_only && (p->d_ops || p->d_coef || p->d_rbprog)) {
         (void)hipStreamSynchronize((hipStream_t)p->ctx->stream);
         if (p->d_ops) (void)hipFree(p->d_ops);
         if (p->d_coef) (void)hipFree(p->d_coef);
-        if (p->d_phases) (void)hipFree(p->d_phases);
+        if (p->d_rbprog) (void)hipFree(p->d_rbprog);
     }
     delete p;
     return QK_OK;

@@ -82,14 +82,14 @@ int time_launch(qk_ctx* ctx, const qk_plan* P, int64_t i, qk_state* st, int reps
         d.n_ops = n_ops_override;
         rd.n_phases = 0;
         rd.uses_lds = 0;
+        std::memcpy(rd.st_reg, rd.ld_reg, sizeof(rd.ld_reg));
     }
     const int fused_k = (K.type == QK_KERNEL_FUSED && n_ops_override < 0) ? K.k : 0;
     std::vector<float> t;
     int rc = QK_OK;
     for (int r = 0; r <= reps; ++r) {
         (void)hipEventRecord(e0, s);
-        int e = K.rb ? launch_block_rb(P->dtype, st->psi, rd, (const Phase*)P->d_phases + K.ph_off,
-                                       (const Op*)P->d_ops + K.rbop_off, P->d_coef, s)
+        int e = K.rb ? launch_block_rb(P->dtype, st->psi, rd, (const uint8_t*)P->d_rbprog + K.prog_off, s)
                      : launch_block(P->dtype, fused_k, st->psi, d, (const Op*)P->d_ops + K.op_off, P->d_coef, s);
         (void)hipEventRecord(e1, s);
         if (e) { rc = hip_fail(e, "time_kernel launch"); break; }

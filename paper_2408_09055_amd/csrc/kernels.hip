@@ -279,15 +279,23 @@ __device__ __forceinline__ void static_for(F&& f)
 // 16-byte register vector (a plain clang vector, which scalar replacement of
 // aggregates handles; HIP's uint4 is a union-based struct).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Maximum 16-byte chunks a thread moves per block: 2^m amplitudes / (16 B
 // chunks) / kNT threads, with m <= 13 (c64) or 12 (c128) -> 64 KiB per block.
 constexpr int kMaxChunks = 16;
 
+// First amplitude of block blk: zeros inserted at the active qubits.  The
+// active set is read with compile-time indices, so it stays in scalar
+// registers; a loop with a variable index would read it from memory with a
+// vector load on every block, and waiting for that load would also wait for
+// the block's outstanding stores and prefetches.
 __device__ __forceinline__ uint64_t block_base(uint64_t blk, const uint8_t* act, int m)
 {
     uint64_t base = blk;
-    for (int j = 0; j < m; ++j) base = ins0_64(base, act[j]);
+    static_for<0, 16>([&](auto J) {
+        if (J.value < m) base = ins0_64(base, act[J.value]);
+    });
     return base;
 }
 
@@ -330,13 +338,19 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
             if (c < nch) buf[I.value] = *reinterpret_cast<const u32x4*>(&psi[b0 + off_i[I.value]]);
         });
     };
-    load_all(base);
-    for (;;) {
+    // prefetched chunks -> LDS.  After the first block it runs right after
+    // the previous block's stores, so it waits only for the loads issued
+    // before them.
+    auto fill = [&]() {
         static_for<0, kMaxChunks>([&](auto I) {
             const uint32_t c = tid + (uint32_t)I.value * kNT;
             if (c < nch) *reinterpret_cast<u32x4*>(&sm[c * CH]) = buf[I.value];
         });
         __syncthreads();
+    };
+    load_all(base);
+    fill();
+    for (;;) {
         const uint64_t next = blk + stride;
         const uint64_t nbase = next < d.nblocks ? block_base(next, d.act, m) + off_t : 0;
         if (next < d.nblocks) load_all(nbase);
@@ -347,9 +361,10 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
                 *reinterpret_cast<u32x4*>(&psi[base + off_i[I.value]]) = *reinterpret_cast<const u32x4*>(&sm[c * CH]);
         });
         if (next >= d.nblocks) break;
+        __syncthreads();   // all LDS reads of this block done before the next fill
+        fill();
         blk = next;
         base = nbase;
-        __syncthreads();   // all LDS reads of this block done before the next fill
     }
 }
 
@@ -366,7 +381,7 @@ __global__ __launch_bounds__(kNT) void k_block_seq(C* __restrict__ psi, BlockDes
             const Op op = ops[o];
             const C* u = coef + op.coef;
             switch (op.code) {
-            case OP_DENSE1: op_dense1(s, m, op.b[0], u); break;
+            case OP_DENSE1: case OP_H: op_dense1(s, m, op.b[0], u); break;
             case OP_DIAG1: op_diag1(s, m, op.b[0], u); break;
             case OP_X: op_x(s, m, op.b[0]); break;
             case OP_CX: op_cx(s, m, op.b[0], op.b[1]); break;
@@ -556,11 +571,23 @@ struct Cx {
 template <typename C>
 using CxOf = Cx<typename Real<C>::T>;
 
+// A coefficient of the kernel's program (in LDS, the same for every lane),
+// moved to scalar registers so that it costs no vector registers while used.
+__device__ __forceinline__ float uniform_real(float x) { return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x))); }
+__device__ __forceinline__ double uniform_real(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    // readfirstlane returns a signed int: widen through uint32_t, not int
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
 template <typename C>
-__device__ __forceinline__ CxOf<C> ld_coef(const C* __restrict__ p)
+__device__ __forceinline__ CxOf<C> ld_coef(const C* p)
 {
     const C c = *p;
-    return CxOf<C>{c.x, c.y};
+    return CxOf<C>{uniform_real(c.x), uniform_real(c.y)};
 }
 
 __host__ __device__ constexpr int cins0(int p, int k) { return ((p >> k) << (k + 1)) | (p & ((1 << k) - 1)); }
@@ -606,6 +633,19 @@ __device__ __forceinline__ void rb_dense1(V (&v)[kRbAmps], const C* __restrict__
         const V a = v[i0], b = v[i1];
         v[i0] = cmadd(u01, b, cmul(u00, a));
         v[i1] = cmadd(u11, b, cmul(u10, a));
+    });
+}
+
+// Hadamard on register bit K: sums and differences, scaled by coef[0] = 1/sqrt 2
+template <int K, typename C, typename V>
+__device__ __forceinline__ void rb_h(V (&v)[kRbAmps], const C* __restrict__ u)
+{
+    const auto s = uniform_real(u[0].x);
+    static_for<0, kRbAmps / 2>([&](auto P) QK_AI {
+        constexpr int i0 = cins0(P.value, K), i1 = i0 | (1 << K);
+        const V a = v[i0], b = v[i1];
+        v[i0] = V{(a.x + b.x) * s, (a.y + b.y) * s};
+        v[i1] = V{(a.x - b.x) * s, (a.y - b.y) * s};
     });
 }
 
@@ -704,11 +744,12 @@ __device__ __forceinline__ void rb_densek(V (&v)[kRbAmps], const C* __restrict__
 }
 
 template <typename C, typename V>
-__device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* __restrict__ coef)
+__device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* coef)
 {
     const C* u = coef + op.coef;
     switch (op.code) {
     case OP_DENSE1: dispatch1(op.b[0], [&](auto K) QK_AI { rb_dense1<K.value>(v, u); }); break;
+    case OP_H: dispatch1(op.b[0], [&](auto K) QK_AI { rb_h<K.value>(v, u); }); break;
     case OP_DIAG1: dispatch1(op.b[0], [&](auto K) QK_AI { rb_diag1<K.value>(v, u); }); break;
     case OP_X: dispatch1(op.b[0], [&](auto K) QK_AI { rb_x<K.value>(v); }); break;
     case OP_CX: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_cx<A.value, B.value>(v); }); break;
@@ -770,70 +811,162 @@ __device__ __forceinline__ bool same_reg(const uint8_t* a, const uint8_t* b)
     return a[0] == b[0] && a[1] == b[1] && a[2] == b[2] && a[3] == b[3];
 }
 
+// Offset of access I relative to the thread's amplitude 0: its register bits
+// select from the four per-bit offsets rb[k].  An access of CH = 2 amplitudes
+// holds the pair that differs in register bit 0.
+template <int CH>
+__device__ __forceinline__ uint64_t chunk_offset(int I, const uint64_t* rb)
+{
+    const int r = I * CH;
+    return ((r & 1) ? rb[0] : 0) + ((r & 2) ? rb[1] : 0) + ((r & 4) ? rb[2] : 0) + ((r & 8) ? rb[3] : 0);
+}
+
+// Occupancy target: two workgroups of 512 (complex64) or 256 (complex128)
+// threads per compute unit, i.e. 4 or 2 waves per SIMD.
+// Uniform copy of an LDS word (every lane reads the same address), so that
+// decisions on it are scalar branches.
+__device__ __forceinline__ uint32_t lds_uniform(const uint32_t* p) { return __builtin_amdgcn_readfirstlane(*p); }
+
 template <typename C, int NT>
-__global__ __launch_bounds__(NT) void k_block_rb(C* __restrict__ psi, RbDesc d, const Phase* __restrict__ phases,
-                                                 const Op* __restrict__ ops, const C* __restrict__ coef)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(C) == 8 ? 4 : 2)))
+void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog)
 {
     using V = CxOf<C>;
     using R = typename Real<C>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    V* sm = reinterpret_cast<V*>(smem);
-    constexpr int CH = 16 / sizeof(C);              // amplitudes per 16-byte chunk
-    constexpr int NCH = kRbAmps / CH;               // chunks per thread
+    // LDS: the kernel's program, then (when the layout changes) the block.
+    // Reading the program from LDS keeps the loop free of vector-memory loads,
+    // so waiting on one never waits for the next block's prefetch.
+    const uint8_t* prog = smem;
+    V* sm = reinterpret_cast<V*>(smem + d.prog_bytes);
+    const C* coef = reinterpret_cast<const C*>(smem + d.coef_off);
+    constexpr int CH = 16 / sizeof(C);              // amplitudes per 16-byte access
     const int m = d.b.m;
     const int tid = threadIdx.x;
-    // chunk i of thread t covers block index (t + NT i) * CH (+ e): the thread
-    // part and the chunk part occupy disjoint bit fields
-    const uint64_t off_t = deposit((uint32_t)tid * CH, d.b.act, m);
-    uint64_t off_i[NCH];
-    static_for<0, NCH>([&](auto I) QK_AI { off_i[I.value] = deposit((uint32_t)I.value * NT * CH, d.b.act, m); });
     uint64_t blk = blockIdx.x;
     if (blk >= d.b.nblocks) return;
-    u32x4 w[NCH];
-    uint64_t base = block_base(blk, d.b.act, m) + off_t;
-    auto load_all = [&](uint64_t b0) {
-        static_for<0, NCH>([&](auto I) QK_AI { w[I.value] = *reinterpret_cast<const u32x4*>(&psi[b0 + off_i[I.value]]); });
+    for (uint32_t i = tid; i < d.prog_bytes / 16; i += NT)
+        reinterpret_cast<u32x4*>(smem)[i] = reinterpret_cast<const u32x4*>(gprog)[i];
+    // Loads use the first phase's layout when it moves whole lines (else the
+    // default one), stores the last phase's.  Address of chunk I of this
+    // thread = block base + thread part + chunk part; the chunk part is the
+    // same for every thread.
+    const uint64_t ld_t = deposit(thr_deposit(tid, d.ld_reg, m), d.b.act, m);
+    const uint64_t st_t = deposit(thr_deposit(tid, d.st_reg, m), d.b.act, m);
+    // amplitude offset of each register bit (uniform: selected with
+    // compile-time indices into the active set, so it lives in scalar registers)
+    uint64_t ld_b[kRbBits], st_b[kRbBits];
+    static_for<0, kRbBits>([&](auto K) QK_AI {
+        uint32_t ql = 0, qs = 0;
+        static_for<0, 16>([&](auto J) QK_AI {
+            if (d.ld_reg[K.value] == J.value) ql = d.b.act[J.value];
+            if (d.st_reg[K.value] == J.value) qs = d.b.act[J.value];
+        });
+        ld_b[K.value] = 1ull << __builtin_amdgcn_readfirstlane(ql);
+        st_b[K.value] = 1ull << __builtin_amdgcn_readfirstlane(qs);
+    });
+    // Raw amplitudes of the prefetched block, one register entry per
+    // amplitude.  complex64 loads either 16-byte pairs (wide: register bit 0
+    // is block bit 0) or single 8-byte amplitudes; complex128 amplitudes are
+    // 16 bytes.
+    using Raw = typename std::conditional<CH == 2, u32x2, u32x4>::type;
+    Raw w[kRbAmps];
+    uint64_t base = block_base(blk, d.b.act, m);
+    // The thread's amplitude-0 offset is materialised once per block (the
+    // empty asm makes it opaque), so the compiler adds the uniform per-amplitude
+    // offsets at each access instead of keeping 16 precomputed 64-bit
+    // addresses live.
+    auto load_all = [&](uint64_t b) {
+        uint64_t b0 = b + ld_t;
+        asm volatile("" : "+v"(b0));
+        if constexpr (CH == 2) {
+            if (d.ld_wide) {
+                static_for<0, kRbAmps / 2>([&](auto I) QK_AI {
+                    const u32x4 x = *reinterpret_cast<const u32x4*>(&psi[b0 + chunk_offset<2>(I.value, ld_b)]);
+                    w[2 * I.value] = u32x2{x.x, x.y};
+                    w[2 * I.value + 1] = u32x2{x.z, x.w};
+                });
+            } else {
+                static_for<0, kRbAmps>([&](auto I) QK_AI {
+                    w[I.value] = *reinterpret_cast<const u32x2*>(&psi[b0 + chunk_offset<1>(I.value, ld_b)]);
+                });
+            }
+        } else {
+            static_for<0, kRbAmps>([&](auto I) QK_AI {
+                w[I.value] = *reinterpret_cast<const u32x4*>(&psi[b0 + chunk_offset<1>(I.value, ld_b)]);
+            });
+        }
     };
-    load_all(base);
-    for (;;) {
-        V v[kRbAmps];
-        static_for<0, NCH>([&](auto I) QK_AI {
-            const u32x4 x = w[I.value];
+    V v[kRbAmps];
+    // prefetched amplitudes -> working registers.  It runs right after the
+    // previous block's stores (or at the start), so the wait it needs is for
+    // the loads issued before those stores only.
+    auto unpack = [&]() QK_AI {
+        static_for<0, kRbAmps>([&](auto I) QK_AI {
+            const Raw x = w[I.value];
             if constexpr (CH == 2) {
-                v[2 * I.value] = V{__uint_as_float(x.x), __uint_as_float(x.y)};
-                v[2 * I.value + 1] = V{__uint_as_float(x.z), __uint_as_float(x.w)};
+                v[I.value] = V{__uint_as_float(x.x), __uint_as_float(x.y)};
             } else {
                 v[I.value] = V{__builtin_bit_cast(R, (uint64_t)x.x | ((uint64_t)x.y << 32)),
                                __builtin_bit_cast(R, (uint64_t)x.z | ((uint64_t)x.w << 32))};
             }
         });
+    };
+    load_all(base);
+    __syncthreads();   // program in LDS
+    unpack();
+    for (;;) {
         const uint64_t next = blk + gridDim.x;
-        const uint64_t nbase = next < d.b.nblocks ? block_base(next, d.b.act, m) + off_t : 0;
+        const uint64_t nbase = next < d.b.nblocks ? block_base(next, d.b.act, m) : 0;
         if (next < d.b.nblocks) load_all(nbase);
-        uint8_t cur[4] = {d.io_reg[0], d.io_reg[1], d.io_reg[2], d.io_reg[3]};
+        uint8_t cur[4] = {d.ld_reg[0], d.ld_reg[1], d.ld_reg[2], d.ld_reg[3]};
         for (int p = 0; p < d.n_phases; ++p) {
-            const Phase ph = phases[p];
-            if (!same_reg(cur, ph.reg) && d.uses_lds) {
-                rb_transition(sm, v, cur, ph.reg, m);
-                cur[0] = ph.reg[0]; cur[1] = ph.reg[1]; cur[2] = ph.reg[2]; cur[3] = ph.reg[3];
+            const uint32_t* pw = reinterpret_cast<const uint32_t*>(prog + p * sizeof(Phase));
+            const uint32_t regw = lds_uniform(pw), rng = lds_uniform(pw + 1);
+            const uint8_t reg[4] = {(uint8_t)regw, (uint8_t)(regw >> 8), (uint8_t)(regw >> 16), (uint8_t)(regw >> 24)};
+            if (!same_reg(cur, reg) && d.uses_lds) {
+                rb_transition(sm, v, cur, reg, m);
+                cur[0] = reg[0]; cur[1] = reg[1]; cur[2] = reg[2]; cur[3] = reg[3];
             }
-            for (int o = ph.op_begin; o < ph.op_end; ++o) rb_apply(v, ops[o], coef);
+            for (uint32_t o = rng & 0xffffu; o < (rng >> 16); ++o) {
+                const uint32_t* ow = reinterpret_cast<const uint32_t*>(prog + d.ops_off + o * sizeof(Op));
+                const uint32_t w0 = lds_uniform(ow);
+                Op op{};
+                op.code = (uint8_t)w0;
+                op.k = (uint8_t)(w0 >> 8);
+                op.b[0] = (uint8_t)(w0 >> 16);
+                op.b[1] = (uint8_t)(w0 >> 24);
+                op.coef = lds_uniform(ow + 3);
+                rb_apply(v, op, coef);
+            }
         }
-        if (!same_reg(cur, d.io_reg) && d.uses_lds) rb_transition(sm, v, cur, d.io_reg, m);
-        static_for<0, NCH>([&](auto I) QK_AI {
-            u32x4 x;
-            if constexpr (CH == 2) {
-                const V a = v[2 * I.value], b = v[2 * I.value + 1];
-                x.x = __float_as_uint(a.x); x.y = __float_as_uint(a.y);
-                x.z = __float_as_uint(b.x); x.w = __float_as_uint(b.y);
+        if (!same_reg(cur, d.st_reg) && d.uses_lds) rb_transition(sm, v, cur, d.st_reg, m);
+        uint64_t s0 = base + st_t;
+        asm volatile("" : "+v"(s0));
+        if constexpr (CH == 2) {
+            if (d.st_wide) {
+                static_for<0, kRbAmps / 2>([&](auto I) QK_AI {
+                    const V a = v[2 * I.value], b = v[2 * I.value + 1];
+                    const u32x4 x = {__float_as_uint(a.x), __float_as_uint(a.y), __float_as_uint(b.x), __float_as_uint(b.y)};
+                    *reinterpret_cast<u32x4*>(&psi[s0 + chunk_offset<2>(I.value, st_b)]) = x;
+                });
             } else {
+                static_for<0, kRbAmps>([&](auto I) QK_AI {
+                    const V a = v[I.value];
+                    *reinterpret_cast<u32x2*>(&psi[s0 + chunk_offset<1>(I.value, st_b)]) =
+                        u32x2{__float_as_uint(a.x), __float_as_uint(a.y)};
+                });
+            }
+        } else {
+            static_for<0, kRbAmps>([&](auto I) QK_AI {
                 const V a = v[I.value];
                 const uint64_t re = __builtin_bit_cast(uint64_t, a.x), im = __builtin_bit_cast(uint64_t, a.y);
-                x.x = (uint32_t)re; x.y = (uint32_t)(re >> 32); x.z = (uint32_t)im; x.w = (uint32_t)(im >> 32);
-            }
-            *reinterpret_cast<u32x4*>(&psi[base + off_i[I.value]]) = x;
-        });
+                const u32x4 x = {(uint32_t)re, (uint32_t)(re >> 32), (uint32_t)im, (uint32_t)(im >> 32)};
+                *reinterpret_cast<u32x4*>(&psi[s0 + chunk_offset<1>(I.value, st_b)]) = x;
+            });
+        }
         if (next >= d.b.nblocks) break;
+        unpack();
         blk = next;
         base = nbase;
     }
@@ -1111,6 +1244,20 @@ int rb_threads(int dtype, int m)
     return m == 12 ? 256 : 0;
 }
 
+bool rb_io_friendly(int dtype, const uint8_t* reg)
+{
+    // complex128: block bits 0..2 are lane bits.  complex64: either register
+    // bit 0 is block bit 0 and block bits 1..3 are lane bits (16-byte pairs),
+    // or block bits 0..3 are all lane bits (8-byte amplitudes).
+    const int lo = dtype == QK_C128 ? 3 : 4;
+    for (int k = 0; k < kRbBits; ++k) {
+        if (reg[k] >= lo) continue;
+        if (dtype == QK_C64 && k == 0 && reg[0] == 0) continue;
+        return false;
+    }
+    return true;
+}
+
 void rb_io_reg(int dtype, int threads, uint8_t* reg)
 {
     const int lt = threads == 512 ? 9 : 8;
@@ -1123,26 +1270,26 @@ void rb_io_reg(int dtype, int threads, uint8_t* reg)
 }
 
 template <typename C, int NT>
-int launch_rb_typed(void* psi, const RbDesc& d, const Phase* phases, const Op* ops, const void* coef, hipStream_t s)
+int launch_rb_typed(void* psi, const RbDesc& d, const void* prog, hipStream_t s)
 {
-    const size_t lds = d.uses_lds ? ((size_t)sizeof(C) << d.b.m) : 0;
+    const size_t lds = d.prog_bytes + (d.uses_lds ? ((size_t)sizeof(C) << d.b.m) : 0);
     auto f = k_block_rb<C, NT>;
     const uint64_t res = resident_groups(reinterpret_cast<const void*>(f), lds, NT);
     const dim3 grid((uint32_t)std::min<uint64_t>(d.b.nblocks, res)), block(NT);
-    hipLaunchKernelGGL(f, grid, block, lds, s, (C*)psi, d, phases, ops, (const C*)coef);
+    hipLaunchKernelGGL(f, grid, block, lds, s, (C*)psi, d, (const uint8_t*)prog);
     return (int)hipGetLastError();
 }
 
-int launch_block_rb(int dtype, void* psi, const RbDesc& d, const Phase* phases, const Op* ops, const void* coef,
-                    void* stream)
+int launch_block_rb(int dtype, void* psi, const RbDesc& d, const void* prog, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     const int nt = rb_threads(dtype, d.b.m);
+    if (d.prog_bytes > kRbProgMax || d.prog_bytes % 16) return (int)hipErrorInvalidValue;
     if (dtype == QK_C64) {
-        if (nt == 512) return launch_rb_typed<float2, 512>(psi, d, phases, ops, coef, s);
-        if (nt == 256) return launch_rb_typed<float2, 256>(psi, d, phases, ops, coef, s);
+        if (nt == 512) return launch_rb_typed<float2, 512>(psi, d, prog, s);
+        if (nt == 256) return launch_rb_typed<float2, 256>(psi, d, prog, s);
     } else if (nt == 256) {
-        return launch_rb_typed<double2, 256>(psi, d, phases, ops, coef, s);
+        return launch_rb_typed<double2, 256>(psi, d, prog, s);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -26,8 +26,7 @@ struct PKernel {
     int op_off, n_ops; // slice of the plan's op table (block-bit form)
     bool rb;           // runs on the register-blocked kernel
     RbDesc rbd;        // its launch descriptor
-    int ph_off;        // slice of the plan's phase table
-    int rbop_off;      // slice of the op table in register-position form
+    int64_t prog_off;  // its program in the plan's register-kernel blob
 };
 
 // Feature vector of a candidate kernel for the learned cost model.
@@ -56,12 +55,12 @@ struct qk_plan {
     std::vector<qk::PKernel> kernels;
     std::vector<int32_t> final_layout;   // logical q -> physical bit
     std::vector<qk::Op> ops;
-    std::vector<qk::Phase> phases;
     std::vector<qk::cd> coefs;           // FP64 master copy
+    std::vector<uint8_t> rbprog;         // register-kernel programs (16-byte aligned each)
     int64_t total_cost = 0;
     qk_ctx* ctx = nullptr;
     void* d_ops = nullptr;
     void* d_coef = nullptr;
-    void* d_phases = nullptr;
+    void* d_rbprog = nullptr;
     ~qk_plan() { qk::ctx_unref(ctx); }
 };

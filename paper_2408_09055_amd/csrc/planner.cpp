@@ -250,9 +250,8 @@ void build_rb(qk_plan* P, PKernel& K)
     RbDesc& d = K.rbd;
     std::memset(&d, 0, sizeof(d));
     d.b = K.desc;
-    rb_io_reg(P->dtype, nt, d.io_reg);
-    K.ph_off = (int)P->phases.size();
-    K.rbop_off = (int)P->ops.size();
+    uint8_t io_reg[4];
+    rb_io_reg(P->dtype, nt, io_reg);
     std::vector<Phase> ph;
     std::vector<Op> lops;
     auto has = [](const uint8_t* reg, int nreg, int b) {
@@ -261,27 +260,31 @@ void build_rb(qk_plan* P, PKernel& K)
         return false;
     };
     // complete reg[0..nreg) to four bits: first from `prefer`, then the lowest
-    auto fill = [&](uint8_t* reg, int nreg, const uint8_t* prefer) {
-        for (int k = 0; k < kRbBits && nreg < kRbBits; ++k)
-            if (!has(reg, nreg, prefer[k])) reg[nreg++] = prefer[k];
+    // complete reg[0..nreg) to four bits, preferring bits that keep the
+    // layout directly loadable (above the 128-byte line), highest first
+    const int safe_lo = P->dtype == QK_C128 ? 3 : 4;
+    auto fill = [&](uint8_t* reg, int nreg) {
+        for (int b = m - 1; b >= safe_lo && nreg < kRbBits; --b)
+            if (!has(reg, nreg, b)) reg[nreg++] = (uint8_t)b;
         for (int b = 0; b < m && nreg < kRbBits; ++b)
             if (!has(reg, nreg, b)) reg[nreg++] = (uint8_t)b;
     };
     if (K.type == QK_KERNEL_FUSED) {
+        // register bits 0..k-1 hold the kernel bits
         const Op& src = P->ops[K.op_off];
         Phase p{};
         int nreg = 0;
         for (int u = 0; u < src.k; ++u) p.reg[nreg++] = src.b[u];
-        fill(p.reg, nreg, d.io_reg);
+        fill(p.reg, nreg);
         Op o = src;
-        for (int u = 0; u < src.k; ++u) o.b[u] = (uint8_t)u;
+        for (int u = 0; u < 7; ++u) o.b[u] = 0;
         lops.push_back(o);
         p.op_begin = 0;
         p.op_end = 1;
         ph.push_back(p);
     } else {
         uint8_t cur[4];
-        std::memcpy(cur, d.io_reg, 4);
+        std::memcpy(cur, io_reg, 4);
         bool open = false;
         for (int o = 0; o < K.n_ops; ++o) {
             Op op = P->ops[K.op_off + o];
@@ -310,7 +313,7 @@ void build_rb(qk_plan* P, PKernel& K)
                     std::memcpy(set, tmp, 4);
                     ns = nt2;
                 }
-                fill(set, ns, cur);
+                fill(set, ns);
                 std::sort(set, set + kRbBits);
                 if (open) ph.back().op_end = (uint16_t)lops.size();
                 Phase p{};
@@ -333,18 +336,64 @@ void build_rb(qk_plan* P, PKernel& K)
         }
         if (open) ph.back().op_end = (uint16_t)lops.size();
     }
-    // does some phase leave the load/store layout (then the kernel needs LDS)?
+    // load in the first phase's layout and store in the last one's when they
+    // move whole lines; otherwise in the default layout, with a transition
+    std::memcpy(d.ld_reg, io_reg, 4);
+    std::memcpy(d.st_reg, io_reg, 4);
+    if (!ph.empty() && rb_io_friendly(P->dtype, ph.front().reg)) std::memcpy(d.ld_reg, ph.front().reg, 4);
+    if (!ph.empty() && rb_io_friendly(P->dtype, ph.back().reg)) std::memcpy(d.st_reg, ph.back().reg, 4);
+    // complex64 moves 16-byte amplitude pairs when register bit 0 is block bit 0
+    d.ld_wide = (uint8_t)(P->dtype == QK_C64 && d.ld_reg[0] == 0);
+    d.st_wide = (uint8_t)(P->dtype == QK_C64 && d.st_reg[0] == 0);
+    // does the block change layout anywhere (then the kernel needs LDS)?
     uint8_t cur[4];
-    std::memcpy(cur, d.io_reg, 4);
+    std::memcpy(cur, d.ld_reg, 4);
     int uses = 0;
     for (const Phase& p : ph) {
-        if (std::memcmp(cur, p.reg, 4) != 0) { uses = 1; std::memcpy(cur, p.reg, 4); }
+        if (std::memcmp(cur, p.reg, 4) != 0) { ++uses; std::memcpy(cur, p.reg, 4); }
     }
-    if (std::memcmp(cur, d.io_reg, 4) != 0) uses = 1;
+    if (std::memcmp(cur, d.st_reg, 4) != 0) ++uses;
+    d.n_transposes = uses;
+    uses = uses > 0;
     d.uses_lds = uses;
     d.n_phases = (int)ph.size();
-    P->phases.insert(P->phases.end(), ph.begin(), ph.end());
-    P->ops.insert(P->ops.end(), lops.begin(), lops.end());
+    // program blob: phases, operations (coefficients renumbered from 0), and
+    // the coefficients rounded once to the state's precision
+    const size_t csz = P->dtype == QK_C128 ? 16 : 8;
+    auto up16 = [](size_t x) { return (x + 15) & ~size_t(15); };
+    std::vector<cd> kc;
+    for (Op& o : lops) {
+        int cnt = 0;
+        switch (o.code) {
+        case OP_DENSE1: case OP_H: case OP_DIAG2: cnt = 4; break;
+        case OP_DIAG1: cnt = 2; break;
+        case OP_CPHASE: cnt = 1; break;
+        case OP_DENSEK: cnt = 1 << (2 * o.k); break;
+        default: cnt = 0; break;
+        }
+        const uint32_t first = (uint32_t)kc.size();
+        for (int t = 0; t < cnt; ++t) kc.push_back(P->coefs[o.coef + t]);
+        o.coef = cnt ? first : 0;
+    }
+    d.ops_off = (uint32_t)up16(ph.size() * sizeof(Phase));
+    d.coef_off = d.ops_off + (uint32_t)(lops.size() * sizeof(Op));
+    const size_t bytes = up16(d.coef_off + kc.size() * csz);
+    if (bytes > kRbProgMax) return;   // stays on the staged-block kernels
+    d.prog_bytes = (uint32_t)bytes;
+    K.prog_off = (int64_t)P->rbprog.size();
+    P->rbprog.resize(P->rbprog.size() + bytes, 0);
+    uint8_t* dst = P->rbprog.data() + K.prog_off;
+    std::memcpy(dst, ph.data(), ph.size() * sizeof(Phase));
+    std::memcpy(dst + d.ops_off, lops.data(), lops.size() * sizeof(Op));
+    for (size_t t = 0; t < kc.size(); ++t) {
+        if (P->dtype == QK_C128) {
+            const double v[2] = {kc[t].real(), kc[t].imag()};
+            std::memcpy(dst + d.coef_off + t * csz, v, csz);
+        } else {
+            const float v[2] = {(float)kc[t].real(), (float)kc[t].imag()};
+            std::memcpy(dst + d.coef_off + t * csz, v, csz);
+        }
+    }
     K.rb = true;
 }
 
@@ -401,6 +450,10 @@ void emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m
             gate_unitary(rec, U);
             switch (g.kind) {
             case QK_X: op.code = OP_X; break;
+            case QK_H:
+                op.code = OP_H;
+                for (int r = 0; r < 4; ++r) P->coefs.push_back(U[r]);
+                break;
             case QK_CX: op.code = OP_CX; break;
             case QK_CZ: op.code = OP_CZ; break;
             case QK_SWAP: op.code = OP_SWAP; break;

@@ -40,7 +40,9 @@ enum OpCode : uint8_t {
     OP_CPHASE = 5,  // multiply by coef[0] where b0 and b1 are set
     OP_DIAG2 = 6,   // diag(coef[0..3]) indexed by bit(b0) + 2 bit(b1)
     OP_SWAP = 7,    // exchange bits b0 and b1
-    OP_DENSEK = 8,  // 2^k x 2^k matrix on bits b[0..k-1] (sorted ascending)
+    OP_DENSEK = 8,  // 2^k x 2^k matrix on bits b[0..k-1] (sorted ascending);
+                    // register form: on register bits 0..k-1
+    OP_H = 9,       // Hadamard on bit b0: coef[0..3] hold its matrix (coef[0] = 1/sqrt 2)
 };
 
 struct Op {
@@ -90,16 +92,31 @@ static_assert(sizeof(Phase) == 8, "Phase layout");
 struct RbDesc {
     BlockDesc b;         // block geometry (act, ell0, m, nblocks)
     int32_t n_phases;
-    int32_t uses_lds;    // 1 if some phase differs from the I/O layout
-    uint8_t io_reg[4];   // register bits of the HBM load/store layout
-    int32_t pad;
+    int32_t uses_lds;    // 1 if the block changes layout through LDS
+    uint8_t ld_reg[4];   // register bits of the HBM load layout
+    uint8_t st_reg[4];   // register bits of the HBM store layout
+    // the kernel's program, copied to LDS at launch: n_phases Phase records,
+    // then (at ops_off) the operations in register form, then (at coef_off)
+    // their coefficients in the state's precision; prog_bytes in total
+    uint32_t prog_bytes, ops_off, coef_off;
+    // complex64 only: 1 = loads (stores) move 16-byte amplitude pairs, which
+    // needs register bit 0 = block bit 0; 0 = single 8-byte amplitudes
+    uint8_t ld_wide, st_wide, pad[2];
+    int32_t n_transposes;   // layout changes per block (host statistics)
+    int32_t pad2;
 };
+// Largest program a register-blocked kernel stages in LDS.
+constexpr uint32_t kRbProgMax = 16384;
 
 // Threads per workgroup of the register-blocked kernel for a block of 2^m
 // amplitudes (2^m / 16), or 0 when m has no register-blocked variant.
 int rb_threads(int dtype, int m);
-// Register bits of the load/store layout for that thread count.
+// Register bits of the default load/store layout for that thread count.
 void rb_io_reg(int dtype, int threads, uint8_t* reg);
+// True when a phase layout with these register bits can be loaded or stored
+// directly: every group of consecutive lanes then moves whole 128-byte lines
+// (complex64: 8 lanes of 16-byte pairs or 16 lanes of 8-byte amplitudes).
+bool rb_io_friendly(int dtype, const uint8_t* reg);
 
 
 // ---------------------------------------------------------------- launchers
@@ -107,8 +124,7 @@ void rb_io_reg(int dtype, int threads, uint8_t* reg);
 // fused_k = 0: LDS gate sequence (ops[0..n_ops)); 1..7: one dense product.
 int launch_block(int dtype, int fused_k, void* psi, const BlockDesc& d, const Op* ops,
                  const void* coef, void* stream);
-int launch_block_rb(int dtype, void* psi, const RbDesc& d, const Phase* phases, const Op* ops, const void* coef,
-                    void* stream);
+int launch_block_rb(int dtype, void* psi, const RbDesc& d, const void* prog, void* stream);
 int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream);
 int launch_fill_basis(int dtype, void* psi, uint64_t N, uint64_t x, void* stream);
 // Reductions: partial buffer must hold at least reduce_partials() doubles x 2.
