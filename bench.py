@@ -129,6 +129,26 @@ def run_gpu(args):
     return n, circuits, plans, kern_s, results, pass_bytes, norm, tables, calib_s
 
 
+def measured_traffic(kernel: str, n: int):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (profiles/<kernel>_<n>q_c64_step.md), or None when there is none or the
+    kernel source changed since the counters were taken (hash mismatch)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{n}q_c64_step.md")
+    src = os.path.join(ROOT, "paper_2408_09055_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    traffic = sha = None
+    for line in open(path):
+        if line.startswith(f"traffic_bytes_per_launch {kernel}:"):
+            traffic = int(line.split(":")[1])
+        elif line.startswith("kernels.hip sha256:"):
+            sha = line.split(":")[1].strip()
+    if traffic is None or sha != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return traffic
+
+
 def cpu_baseline(circuits_n: int, sample_n: int, gates_per_circuit: int):
     """Oracle timed on a bounded sample: the first `gates_per_circuit` gates of
     each evaluation circuit rebuilt at `sample_n` qubits (complex128 FP64),
@@ -218,7 +238,8 @@ def main():
         "kernelize_s": {f"{m}/{name}": round(v, 4) for (m, name), v in kern_s.items()},
         "norm2_after": norm,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": measured_traffic(kernel_names[dom], n),
                      "kernel": kernel_names[dom], "launches": int(kms.size),
                      "time_share": {k: round(sum(v) / sum(sum(x) for x in by_impl.values()), 4)
                                     for k, v in by_impl.items()},

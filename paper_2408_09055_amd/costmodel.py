@@ -107,8 +107,10 @@ def sample_kernels(count, dtype, seed, n_lo=24, n_hi=32, k_max=7):
         yield n, c, ktype
 
 
-def collect(ctx: Context, dtype: int, count: int, seed: int, reps: int = 3, n_lo=24, n_hi=32, log=print):
-    """Times `count` sampled kernels; returns (features, log ps/amplitude, ms, n)."""
+def collect(ctx: Context, dtype: int, count: int, seed: int, reps: int = 3, n_lo=24, n_hi=32, log=print,
+            budget_s: float | None = None):
+    """Times `count` sampled kernels (fewer if `budget_s` seconds run out
+    first); returns (features, log ps/amplitude, ms, n)."""
     big = State.alloc(ctx, n_hi, dtype)
     big.init_basis(0)
     ptr = big.device_ptr()
@@ -132,6 +134,9 @@ def collect(ctx: Context, dtype: int, count: int, seed: int, reps: int = 3, n_lo
         ns.append(n)
         if (i + 1) % 500 == 0:
             log(f"collected {i + 1}/{count} kernels in {time.time() - t0:.1f} s", flush=True)
+        if budget_s is not None and time.time() - t0 > budget_s:
+            log(f"time budget reached after {i + 1} kernels", flush=True)
+            break
     for v in views.values():
         v.free()
     big.free()
@@ -160,6 +165,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--out", default=None)
     ap.add_argument("--dump", default=None, help="save the dataset (.npz)")
+    ap.add_argument("--budget", type=float, default=None, help="collection time limit in seconds")
     args = ap.parse_args()
     dtype = QK_C64 if args.dtype == "c64" else QK_C128
     ctx = Context()
@@ -167,7 +173,7 @@ def main():
     for n in range(24, 33):
         tables[n] = ctx.calibrate(n, dtype)
         print(f"calibrated n={n}: fused={tables[n][0][1:]} alpha={tables[n][1]} gate={tables[n][2]}", flush=True)
-    X, y, ms, ns = collect(ctx, dtype, args.count, args.seed, args.reps)
+    X, y, ms, ns = collect(ctx, dtype, args.count, args.seed, args.reps, budget_s=args.budget)
     if args.dump:
         np.savez(args.dump, X=X, y=y, ms=ms, n=ns)
     rep = ctx.train_costmodel(dtype, X, y, epochs=args.epochs, seed=args.seed)
