@@ -186,13 +186,19 @@ typedef struct qk_kopts {
     int32_t allow_lds;
     int32_t block_qubits;  /* amplitudes per staged block = 2^block_qubits
                               (>= m_max and >= k_max; 0 = m_max) */
-    int32_t reserved;      /* must be 0 */
+    int32_t insular;       /* 1: LDS kernels need only the non-insular qubits of
+                              their gates in the active set (appendix, "Insular
+                              qubits" optimisation; Definition def:insular_qubit):
+                              a diagonal gate's qubits and a CX control outside
+                              the block become per-block phases, selections or
+                              conditions read from the block index.  0: every
+                              qubit of every gate must be active. */
     const qk_cost_tables* tables;  /* explicit analytic tables, or NULL for the
                                       context's tables for (n, dtype) */
 } qk_kopts;
 
 /* Defaults: complex64, analytic, k_max 5, m_max 0 (auto), ell 0 (auto), swaps absorbed,
- * both kernel types, block_qubits 0, tables NULL. */
+ * both kernel types, block_qubits 0, insular 1, tables NULL. */
 void qk_kopts_default(qk_kopts* ko);
 
 typedef struct qk_kernel_info {

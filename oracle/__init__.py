@@ -269,6 +269,28 @@ class KOpts:
     allow_fused: bool = True
     allow_lds: bool = True
     absorb_swaps: bool = True
+    insular: bool = False
+
+
+def need_qubits(kind: int, qs, insular: bool):
+    """Qubits of a gate that a shared-memory (LDS) kernel must hold active.
+
+    Without the relaxation: all of them.  With it (the appendix's insular
+    qubits optimisation, after the insular-qubit definition): a qubit is
+    insular when the gate's matrix is diagonal in it; such a qubit may stay
+    outside the active set, because its value is fixed within a block and the
+    gate reduces to a smaller gate on the active qubits.  Diagonal gates
+    (Z, S, T, RZ, P, CZ, CP, RZZ) are diagonal in all their qubits; CX is
+    diagonal in its control.  Reading: anti-diagonal gates (X, Y) keep their
+    qubit active, since relabelling blocks is not done inside a kernel."""
+    from workloads import Z, S, T, RZ, P, CZ, CP, RZZ, CX
+    if not insular:
+        return tuple(qs)
+    if kind in (Z, S, T, RZ, P, CZ, CP, RZZ):
+        return ()
+    if kind == CX:
+        return (qs[1],)
+    return tuple(qs)
 
 
 def canonicalize(circuit, absorb_swaps: bool = True):
@@ -297,15 +319,18 @@ def segment_cost(seg, opts: KOpts, tab: CostTables):
     alpha + sum of per-gate costs), infinite when neither type fits.
     Returns (cost, type) with the fused type preferred on an exact tie."""
     mask = 0
+    need = 0
     s = tab.alpha
     for (kind, qs, _) in seg:
         for q in qs:
             mask |= 1 << q
+        for q in need_qubits(kind, qs, opts.insular):
+            need |= 1 << q
         s += tab.gate[gate_class(kind)]
     k = bin(mask).count("1")
     lowmask = (1 << opts.ell) - 1
     fused = tab.fused[k] if (opts.allow_fused and k <= opts.k_max) else INF
-    lds = s if (opts.allow_lds and bin(mask | lowmask).count("1") <= opts.m_max) else INF
+    lds = s if (opts.allow_lds and bin(need | lowmask).count("1") <= opts.m_max) else INF
     if fused <= lds:
         return fused, TYPE_FUSED
     return lds, TYPE_LDS
@@ -326,15 +351,18 @@ def ordered_kernelize(gates, opts: KOpts, tab: CostTables):
     lowmask = (1 << opts.ell) - 1
     for i in range(m):
         mask = 0
+        need = 0
         s = tab.alpha
         for j in range(i, -1, -1):
             kind, qs, _ = gates[j]
             for q in qs:
                 mask |= 1 << q
+            for q in need_qubits(kind, qs, opts.insular):
+                need |= 1 << q
             s += tab.gate[gate_class(kind)]
             k = bin(mask).count("1")
             fused = tab.fused[k] if (opts.allow_fused and k <= opts.k_max) else INF
-            lds = s if (opts.allow_lds and bin(mask | lowmask).count("1") <= opts.m_max) else INF
+            lds = s if (opts.allow_lds and bin(need | lowmask).count("1") <= opts.m_max) else INF
             c, t = (fused, TYPE_FUSED) if fused <= lds else (lds, TYPE_LDS)
             if c >= INF:
                 continue
@@ -466,8 +494,10 @@ def check_plan(gates, kernels, opts: KOpts, tab: CostTables) -> int:
 NUM_FEATURES = 20
 
 
-def features(seg, n: int, ktype: int, dtype_c128: bool) -> np.ndarray:
+def features(seg, n: int, ktype: int, dtype_c128: bool, insular: bool = False) -> np.ndarray:
     """Feature vector of one candidate kernel (a contiguous gate segment).
+    With ``insular``, an LDS kernel's qubit statistics count only the qubits
+    it must hold active (``need_qubits``); 0 for min/max/mean when none.
 
     [0] k = number of distinct qubits   [1] gate count
     [2..8] gate-class histogram {H, X, U3, CX, CZ, CP, RZZ}
@@ -480,8 +510,9 @@ def features(seg, n: int, ktype: int, dtype_c128: bool) -> np.ndarray:
     diag_kinds = {Z, S, T, RZ, P, CZ, CP, RZZ}
     f = np.zeros(NUM_FEATURES)
     mask = 0
+    need_only = insular and ktype == TYPE_LDS
     for (kind, qs, _) in seg:
-        for q in qs:
+        for q in (need_qubits(kind, qs, True) if need_only else qs):
             mask |= 1 << q
         f[2 + gate_class(kind)] += 1
         if kind in diag_kinds:
@@ -490,7 +521,8 @@ def features(seg, n: int, ktype: int, dtype_c128: bool) -> np.ndarray:
     k = len(qs)
     f[0] = k
     f[1] = len(seg)
-    f[9] = min(qs); f[10] = max(qs); f[11] = sum(qs) / k
+    if k:
+        f[9] = min(qs); f[10] = max(qs); f[11] = sum(qs) / k
     f[12] = sum(1 for q in qs if q < 6)
     f[14] = 1.0 if ktype == TYPE_FUSED else 0.0
     f[15] = 1.0 - f[14]

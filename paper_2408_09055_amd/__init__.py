@@ -65,7 +65,7 @@ class qk_kopts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("cost_model", ctypes.c_int32), ("k_max", ctypes.c_int32),
                 ("m_max", ctypes.c_int32), ("ell", ctypes.c_int32), ("absorb_swaps", ctypes.c_int32),
                 ("allow_fused", ctypes.c_int32), ("allow_lds", ctypes.c_int32),
-                ("block_qubits", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("block_qubits", ctypes.c_int32), ("insular", ctypes.c_int32),
                 ("tables", ctypes.POINTER(qk_cost_tables))]
 
 
@@ -175,13 +175,15 @@ def version() -> str:
 
 # ---------------------------------------------------------------- options
 def kopts(dtype=QK_C64, cost_model=QK_COST_ANALYTIC, k_max=None, m_max=None, ell=None,
-          absorb_swaps=None, allow_fused=None, allow_lds=None, block_qubits=None, tables=None) -> qk_kopts:
+          absorb_swaps=None, allow_fused=None, allow_lds=None, block_qubits=None, tables=None,
+          insular=None) -> qk_kopts:
     ko = qk_kopts()
     _lib.qk_kopts_default(ctypes.byref(ko))
     ko.dtype = int(dtype)
     ko.cost_model = int(cost_model)
     for name, val in (("k_max", k_max), ("m_max", m_max), ("ell", ell), ("absorb_swaps", absorb_swaps),
-                      ("allow_fused", allow_fused), ("allow_lds", allow_lds), ("block_qubits", block_qubits)):
+                      ("allow_fused", allow_fused), ("allow_lds", allow_lds), ("block_qubits", block_qubits),
+                      ("insular", insular)):
         if val is not None:
             setattr(ko, name, int(val))
     if tables is not None:

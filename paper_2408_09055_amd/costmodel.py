@@ -10,7 +10,8 @@ Sample distribution (n uniform on [24, 32]):
 * 60 %: random kernels -- fused (k uniform 1..7) or LDS (up to m_max qubits of
   which at most m_max - ell outside the forced low run) with equal
   probability, 1..64 gates over {H, X, U3, CX, CZ, CP, RZZ}, 30 % of them
-  forced to touch a qubit below 6;
+  forced to touch a qubit below 6; half of the LDS kernels also get 1..64
+  insular gates (diagonal gates on any qubit, CX with any control);
 * 40 %: random contiguous segments of the evaluation families (QFT, random
   layered, GHZ, hardware-efficient ansatz), which is what OrderedKernelize
   queries on those circuits.
@@ -52,6 +53,22 @@ def _family(n, rng):
     return W.hea(n, int(rng.integers(2, 6)), rng)
 
 
+_DIAG_KINDS = None
+
+
+def _need(kind, qs):
+    """Qubits an LDS kernel must hold active (insular relaxation): none for
+    diagonal gates, the target for CX, all otherwise."""
+    global _DIAG_KINDS
+    if _DIAG_KINDS is None:
+        _DIAG_KINDS = {W.Z, W.S, W.T, W.RZ, W.P, W.CZ, W.CP, W.RZZ}
+    if kind in _DIAG_KINDS:
+        return ()
+    if kind == W.CX:
+        return (qs[1],)
+    return tuple(qs)
+
+
 def _segment(n, ktype, rng, k_max, m_max, ell):
     """A random contiguous gate segment of a family circuit that fits ktype."""
     c = _family(n, rng)
@@ -63,8 +80,9 @@ def _segment(n, ktype, rng, k_max, m_max, ell):
     end = start
     while end < len(g) and end - start < limit:
         mm = mask
-        for q in g[end]["q"][: g[end]["nq"]]:
-            mm |= 1 << int(q)
+        qs = [int(q) for q in g[end]["q"][: g[end]["nq"]]]
+        for q in (qs if ktype == QK_KERNEL_FUSED else _need(int(g[end]["kind"]), qs)):
+            mm |= 1 << q
         ok = bin(mm).count("1") <= k_max if ktype == QK_KERNEL_FUSED else bin(mm | low).count("1") <= m_max
         if not ok:
             break
@@ -86,7 +104,26 @@ def _lds_kernel(n, rng, m_max, ell):
     high = rng.choice(high_pool, size=min(nh, len(high_pool)), replace=False)
     pool = np.concatenate([low, high]).astype(int)
     kinds = W.TRAIN_KINDS if len(pool) >= 2 else [W.H, W.X, W.U3]
-    return W.random_circuit(n, int(rng.integers(1, 65)), rng, kinds=kinds, qubit_pool=pool)
+    c = W.random_circuit(n, int(rng.integers(1, 65)), rng, kinds=kinds, qubit_pool=pool)
+    if rng.random() < 0.5:
+        # insular gates on any qubit: diagonal gates anywhere, CX controls anywhere
+        extra = []
+        for _ in range(int(rng.integers(1, 65))):
+            r = rng.random()
+            if r < 0.3:
+                extra.append(W.gate([W.RZ, W.T][int(rng.integers(2))], [int(rng.integers(n))],
+                                    [float(rng.uniform(0, 6.3))]))
+            elif r < 0.8 or len(pool) < 1:
+                a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+                extra.append(W.gate([W.CZ, W.CP, W.RZZ][int(rng.integers(3))], [a, b], [float(rng.uniform(0, 6.3))]))
+            else:
+                t = int(rng.choice(pool))
+                ctl = int(rng.choice([q for q in range(n) if q != t]))
+                extra.append(W.gate(W.CX, [ctl, t]))
+        gl = [tuple(x) for x in c.gates] + extra
+        order = rng.permutation(len(gl))
+        c = W.from_list(n, [gl[i] for i in order], c.name + "+insular")
+    return c
 
 
 def sample_kernels(count, dtype, seed, n_lo=24, n_hi=32, k_max=7):

@@ -207,6 +207,7 @@ void qk_kopts_default(qk_kopts* ko)
     ko->allow_fused = 1;
     ko->allow_lds = 1;
     ko->block_qubits = 0;
+    ko->insular = 1;
     ko->tables = nullptr;
 }
 

@@ -218,7 +218,7 @@ int plan_kernel_features(const qk_plan* p, int64_t i, float* out)
     if (!p || !out) return fail(QK_EINVAL, "plan_kernel_features: null argument");
     if (i < 0 || i >= (int64_t)p->kernels.size()) return fail(QK_EINVAL, "plan_kernel_features: index out of range");
     const PKernel& K = p->kernels[i];
-    segment_features(&p->gates[K.g0], (int)(K.g1 - K.g0), p->n, K.type, p->dtype, out);
+    segment_features(&p->gates[K.g0], (int)(K.g1 - K.g0), p->n, K.type, p->dtype, p->ko.insular != 0, out);
     return QK_OK;
 }
 

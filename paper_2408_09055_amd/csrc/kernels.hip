@@ -103,6 +103,15 @@ __device__ void op_diag1(C* sm, int m, int j, const C* __restrict__ u)
         sm[r] = cmul(sm[r], ((r >> j) & 1u) ? d1 : d0);
 }
 
+// Whole block times one coefficient (a phase fixed by qubits outside the block).
+template <typename C>
+__device__ void op_scale(C* sm, int m, const C c)
+{
+    if (c.x == 1 && c.y == 0) return;
+#pragma unroll 4
+    for (uint32_t r = threadIdx.x; r < (1u << m); r += kNT) sm[r] = cmul(sm[r], c);
+}
+
 template <typename C>
 __device__ void op_x(C* sm, int m, int j)
 {
@@ -331,7 +340,8 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
     uint64_t blk = first;
     if (blk >= d.nblocks) return;
     u32x4 buf[kMaxChunks];
-    uint64_t base = block_base(blk, d.act, m) + off_t;
+    uint64_t bb = block_base(blk, d.act, m);   // first amplitude index of the block
+    uint64_t base = bb + off_t;
     auto load_all = [&](uint64_t b0) {
         static_for<0, kMaxChunks>([&](auto I) {
             const uint32_t c = tid + (uint32_t)I.value * kNT;
@@ -352,9 +362,10 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
     fill();
     for (;;) {
         const uint64_t next = blk + stride;
-        const uint64_t nbase = next < d.nblocks ? block_base(next, d.act, m) + off_t : 0;
+        const uint64_t nbb = next < d.nblocks ? block_base(next, d.act, m) : 0;
+        const uint64_t nbase = nbb + off_t;
         if (next < d.nblocks) load_all(nbase);
-        body(sm, m);
+        body(sm, m, bb);
         static_for<0, kMaxChunks>([&](auto I) {
             const uint32_t c = tid + (uint32_t)I.value * kNT;
             if (c < nch)
@@ -364,6 +375,7 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
         __syncthreads();   // all LDS reads of this block done before the next fill
         fill();
         blk = next;
+        bb = nbb;
         base = nbase;
     }
 }
@@ -376,11 +388,15 @@ __global__ __launch_bounds__(kNT) void k_block_seq(C* __restrict__ psi, BlockDes
 {
     extern __shared__ __align__(16) unsigned char smem[];
     C* sm = reinterpret_cast<C*>(smem);
-    block_loop(psi, d, sm, [&](C* s, int m) {
+    block_loop(psi, d, sm, [&](C* s, int m, uint64_t bb) {
         for (int o = 0; o < d.n_ops; ++o) {
             const Op op = ops[o];
             const C* u = coef + op.coef;
+            const uint32_t s2 = (uint32_t)(bb >> op.b[2]) & 1u, s3 = (uint32_t)(bb >> op.b[3]) & 1u;
             switch (op.code) {
+            case OP_BPHASE: op_scale(s, m, u[op.k == 2 ? s2 + 2 * s3 : s2]); break;
+            case OP_DIAG1C: op_diag1(s, m, op.b[0], u + 2 * s2); break;
+            case OP_XC: if (s2) op_x(s, m, op.b[0]); break;
             case OP_DENSE1: case OP_H: op_dense1(s, m, op.b[0], u); break;
             case OP_DIAG1: op_diag1(s, m, op.b[0], u); break;
             case OP_X: op_x(s, m, op.b[0]); break;
@@ -406,7 +422,7 @@ __global__ __launch_bounds__(kNT) void k_block_dense(C* __restrict__ psi, BlockD
     C* sm = reinterpret_cast<C*>(smem);
     const Op op = ops[0];
     const C* U = coef + op.coef;
-    block_loop(psi, d, sm, [&](C* s, int m) {
+    block_loop(psi, d, sm, [&](C* s, int m, uint64_t) {
         if constexpr (K <= 5) op_densek_group<C, K>(s, m, op.b, U);
         else op_densek_rows<C, K>(s, m, op.b, U);
         __syncthreads();
@@ -492,7 +508,7 @@ __global__ __launch_bounds__(kNT) void k_block_mfma(C* __restrict__ psi, BlockDe
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int tm0 = (wave / WN) * RM, tn0 = (wave % WN) * RN;
     const int lr = lane % 16, lk = lane / 16;
-    block_loop(psi, d, sm, [&](C*, int) {
+    block_loop(psi, d, sm, [&](C*, int, uint64_t) {
         // column offsets of this lane's B columns (RN tiles, col = 16 tn + lr)
         constexpr int MAXRN = 16;
         uint32_t coff[MAXRN];
@@ -653,7 +669,13 @@ template <int K, typename C, typename V>
 __device__ __forceinline__ void rb_diag1(V (&v)[kRbAmps], const C* __restrict__ u)
 {
     const V d0 = ld_coef(u), d1 = ld_coef(u + 1);
-    static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], ((I.value >> K) & 1) ? d1 : d0); });
+    // uniform tests: a unit entry leaves its half untouched (P, S, T, CP with a set control)
+    const bool one0 = d0.x == 1 && d0.y == 0, one1 = d1.x == 1 && d1.y == 0;
+    if (!one0) static_for<0, kRbAmps / 2>([&](auto P) QK_AI { v[cins0(P.value, K)] = cmul(v[cins0(P.value, K)], d0); });
+    if (!one1)
+        static_for<0, kRbAmps / 2>([&](auto P) QK_AI {
+            v[cins0(P.value, K) | (1 << K)] = cmul(v[cins0(P.value, K) | (1 << K)], d1);
+        });
 }
 
 template <int K, typename V>
@@ -744,10 +766,22 @@ __device__ __forceinline__ void rb_densek(V (&v)[kRbAmps], const C* __restrict__
 }
 
 template <typename C, typename V>
-__device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* coef)
+__device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* coef, uint64_t bb)
 {
     const C* u = coef + op.coef;
+    // values of the state qubits b[2], b[3] outside the block (uniform)
+    const uint32_t s2 = (uint32_t)(bb >> op.b[2]) & 1u, s3 = (uint32_t)(bb >> op.b[3]) & 1u;
     switch (op.code) {
+    case OP_BPHASE: {
+        const V c = ld_coef(u + (op.k == 2 ? s2 + 2 * s3 : s2));
+        if (!(c.x == 1 && c.y == 0))
+            static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], c); });
+        break;
+    }
+    case OP_DIAG1C: dispatch1(op.b[0], [&](auto K) QK_AI { rb_diag1<K.value>(v, u + 2 * s2); }); break;
+    case OP_XC:
+        if (s2) dispatch1(op.b[0], [&](auto K) QK_AI { rb_x<K.value>(v); });
+        break;
     case OP_DENSE1: dispatch1(op.b[0], [&](auto K) QK_AI { rb_dense1<K.value>(v, u); }); break;
     case OP_H: dispatch1(op.b[0], [&](auto K) QK_AI { rb_h<K.value>(v, u); }); break;
     case OP_DIAG1: dispatch1(op.b[0], [&](auto K) QK_AI { rb_diag1<K.value>(v, u); }); break;
@@ -930,14 +964,16 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
             }
             for (uint32_t o = rng & 0xffffu; o < (rng >> 16); ++o) {
                 const uint32_t* ow = reinterpret_cast<const uint32_t*>(prog + d.ops_off + o * sizeof(Op));
-                const uint32_t w0 = lds_uniform(ow);
+                const uint32_t w0 = lds_uniform(ow), w1 = lds_uniform(ow + 1);
                 Op op{};
                 op.code = (uint8_t)w0;
                 op.k = (uint8_t)(w0 >> 8);
                 op.b[0] = (uint8_t)(w0 >> 16);
                 op.b[1] = (uint8_t)(w0 >> 24);
+                op.b[2] = (uint8_t)w1;
+                op.b[3] = (uint8_t)(w1 >> 8);
                 op.coef = lds_uniform(ow + 3);
-                rb_apply(v, op, coef);
+                rb_apply(v, op, coef, base);
             }
         }
         if (!same_reg(cur, d.st_reg) && d.uses_lds) rb_transition(sm, v, cur, d.st_reg, m);

@@ -31,7 +31,13 @@ struct PKernel {
 
 // Feature vector of a candidate kernel for the learned cost model.
 constexpr int kNumFeatures = 20;
-void segment_features(const CGate* g, int count, int n, int type, int dtype, float* out);
+// insular: LDS kernels count only the qubits that must be active
+void segment_features(const CGate* g, int count, int n, int type, int dtype, bool insular, float* out);
+
+// Qubits of g that an LDS kernel must hold in its active set.  With the
+// insular relaxation a diagonal gate needs none of its qubits and CX only its
+// target; every other gate needs all of its qubits.
+uint64_t need_mask(const CGate& g, bool insular);
 
 // Learned-model hook: predicts log(ps per amplitude) for `cnt` feature rows.
 // Returns QK_OK or an error (then the planner falls back to analytic costs).

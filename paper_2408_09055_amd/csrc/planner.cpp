@@ -131,13 +131,25 @@ bool ctx_lookup_tables(const qk_ctx* ctx, int n, int dtype, qk_cost_tables* out)
 }
 
 // ------------------------------------------------------------------ features
-void segment_features(const CGate* g, int count, int n, int type, int dtype, float* f)
+uint64_t need_mask(const CGate& g, bool insular)
+{
+    uint64_t all = 0;
+    for (int t = 0; t < g.nq; ++t) all |= 1ull << g.q[t];
+    if (!insular) return all;
+    if (kind_is_diagonal(g.kind)) return 0;
+    if (g.kind == QK_CX) return 1ull << g.q[1];
+    return all;
+}
+
+void segment_features(const CGate* g, int count, int n, int type, int dtype, bool insular, float* f)
 {
     for (int i = 0; i < kNumFeatures; ++i) f[i] = 0.0f;
     uint64_t mask = 0;
     int diag = 0;
+    const bool need_only = insular && type == QK_KERNEL_LDS;
     for (int i = 0; i < count; ++i) {
-        for (int j = 0; j < g[i].nq; ++j) mask |= 1ull << g[i].q[j];
+        if (need_only) mask |= need_mask(g[i], true);
+        else for (int j = 0; j < g[i].nq; ++j) mask |= 1ull << g[i].q[j];
         f[2 + gate_class(g[i].kind)] += 1.0f;
         if (kind_is_diagonal(g[i].kind)) ++diag;
     }
@@ -151,11 +163,12 @@ void segment_features(const CGate* g, int count, int n, int type, int dtype, flo
         sum += q;
         if (q < 6) ++below6;
     }
+    if (k == 0) lo = hi = 0;   // an LDS kernel of diagonal gates only
     f[0] = (float)k;
     f[1] = (float)count;
     f[9] = (float)lo;
     f[10] = (float)hi;
-    f[11] = (float)(sum / k);
+    f[11] = k ? (float)(sum / k) : 0.0f;
     f[12] = (float)below6;
     f[13] = (float)diag;
     f[14] = type == QK_KERNEL_FUSED ? 1.0f : 0.0f;
@@ -224,9 +237,13 @@ int canonicalize(const qk_circuit* c, const qk_kopts& ko, qk_plan* P)
     return QK_OK;
 }
 
-bool op_two_bits(const Op& op)
+// Block bits an operation acts on (b[0], b[1]); OP_BPHASE acts on none.
+int op_nbits(const Op& op)
 {
-    return op.code == OP_CX || op.code == OP_CZ || op.code == OP_CPHASE || op.code == OP_DIAG2 || op.code == OP_SWAP;
+    if (op.code == OP_BPHASE) return 0;
+    if (op.code == OP_CX || op.code == OP_CZ || op.code == OP_CPHASE || op.code == OP_DIAG2 || op.code == OP_SWAP)
+        return 2;
+    return 1;
 }
 
 int reg_pos(const uint8_t* reg, int bit)
@@ -288,8 +305,8 @@ void build_rb(qk_plan* P, PKernel& K)
         bool open = false;
         for (int o = 0; o < K.n_ops; ++o) {
             Op op = P->ops[K.op_off + o];
-            const int nb = op_two_bits(op) ? 2 : 1;
-            bool fits = reg_pos(cur, op.b[0]) >= 0 && (nb == 1 || reg_pos(cur, op.b[1]) >= 0);
+            const int nb = op_nbits(op);
+            bool fits = (nb == 0 || reg_pos(cur, op.b[0]) >= 0) && (nb < 2 || reg_pos(cur, op.b[1]) >= 0);
             if (!fits) {
                 // bits of this and the following operations while four suffice
                 uint8_t set[4];
@@ -297,7 +314,7 @@ void build_rb(qk_plan* P, PKernel& K)
                 for (int o2 = o; o2 < K.n_ops; ++o2) {
                     const Op& q = P->ops[K.op_off + o2];
                     uint8_t nbits[2] = {q.b[0], q.b[1]};
-                    const int qn = op_two_bits(q) ? 2 : 1;
+                    const int qn = op_nbits(q);
                     uint8_t tmp[4];
                     std::memcpy(tmp, set, 4);
                     int nt2 = ns;
@@ -330,7 +347,7 @@ void build_rb(qk_plan* P, PKernel& K)
                 open = true;
             }
             Op lo = op;
-            lo.b[0] = (uint8_t)reg_pos(cur, op.b[0]);
+            if (nb >= 1) lo.b[0] = (uint8_t)reg_pos(cur, op.b[0]);
             if (nb == 2) lo.b[1] = (uint8_t)reg_pos(cur, op.b[1]);
             lops.push_back(lo);
         }
@@ -365,8 +382,9 @@ void build_rb(qk_plan* P, PKernel& K)
     for (Op& o : lops) {
         int cnt = 0;
         switch (o.code) {
-        case OP_DENSE1: case OP_H: case OP_DIAG2: cnt = 4; break;
+        case OP_DENSE1: case OP_H: case OP_DIAG2: case OP_DIAG1C: cnt = 4; break;
         case OP_DIAG1: cnt = 2; break;
+        case OP_BPHASE: cnt = 2 << (o.k - 1); break;
         case OP_CPHASE: cnt = 1; break;
         case OP_DENSEK: cnt = 1 << (2 * o.k); break;
         default: cnt = 0; break;
@@ -398,7 +416,7 @@ void build_rb(qk_plan* P, PKernel& K)
 }
 
 // Append the kernel covering canonical gates [j, i) with the given type.
-void emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m_exec)
+int emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m_exec)
 {
     const std::vector<CGate>& G = P->gates;
     const int n = P->n;
@@ -413,7 +431,12 @@ void emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m
     K.mask = mask;
     K.k = popcount64(mask);
     const int ell = (K.type == QK_KERNEL_LDS) ? P->ko.ell : 1;
-    fill_desc(K.desc, active_set(mask, std::min(ell, n), m_exec, n), n);
+    uint64_t need = mask;
+    if (K.type == QK_KERNEL_LDS) {
+        need = 0;
+        for (int64_t t = j; t < i; ++t) need |= need_mask(G[t], P->ko.insular != 0);
+    }
+    fill_desc(K.desc, active_set(need, std::min(ell, n), m_exec, n), n);
     K.op_off = (int)P->ops.size();
     if (K.type == QK_KERNEL_FUSED) {
         // kernel qubits in ascending order give the matrix index bits
@@ -440,14 +463,60 @@ void emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m
         for (int64_t t = j; t < i; ++t) {
             const CGate& g = G[t];
             Op op{};
-            op.b[0] = (uint8_t)block_bit(K.desc, g.q[0]);
-            if (g.nq == 2) op.b[1] = (uint8_t)block_bit(K.desc, g.q[1]);
+            const int bb0 = block_bit(K.desc, g.q[0]);
+            const int bb1 = g.nq == 2 ? block_bit(K.desc, g.q[1]) : 0;
             op.coef = (uint32_t)P->coefs.size();
             cd U[16];
             qk_gate rec{};
             rec.kind = g.kind; rec.nq = g.nq;
             rec.p[0] = g.p[0]; rec.p[1] = g.p[1]; rec.p[2] = g.p[2];
             gate_unitary(rec, U);
+            if (bb0 < 0 || bb1 < 0) {
+                // Insular qubits outside the block: their value is fixed per
+                // block (a bit of the block's first index), so the gate becomes
+                // a block phase, a diagonal on its active qubit selected by that
+                // bit, or an X on the active target conditioned on it.
+                if (kind_is_diagonal(g.kind) && g.nq == 1) {
+                    op.code = OP_BPHASE;
+                    op.k = 1;
+                    op.b[2] = (uint8_t)g.q[0];
+                    P->coefs.push_back(U[0]);
+                    P->coefs.push_back(U[3]);
+                } else if (kind_is_diagonal(g.kind)) {
+                    const cd D[4] = {U[0], U[5], U[10], U[15]};   // index bit(q0) + 2 bit(q1)
+                    if (bb0 < 0 && bb1 < 0) {
+                        op.code = OP_BPHASE;
+                        op.k = 2;
+                        op.b[2] = (uint8_t)g.q[0];
+                        op.b[3] = (uint8_t)g.q[1];
+                        for (int r = 0; r < 4; ++r) P->coefs.push_back(D[r]);
+                    } else if (bb0 >= 0) {
+                        op.code = OP_DIAG1C;   // on q0, pair selected by bit(q1)
+                        op.b[0] = (uint8_t)bb0;
+                        op.b[2] = (uint8_t)g.q[1];
+                        for (int r = 0; r < 4; ++r) P->coefs.push_back(D[r]);
+                    } else {
+                        op.code = OP_DIAG1C;   // on q1, pair selected by bit(q0)
+                        op.b[0] = (uint8_t)bb1;
+                        op.b[2] = (uint8_t)g.q[0];
+                        P->coefs.push_back(D[0]);
+                        P->coefs.push_back(D[2]);
+                        P->coefs.push_back(D[1]);
+                        P->coefs.push_back(D[3]);
+                    }
+                } else if (g.kind == QK_CX && bb1 >= 0) {
+                    op.code = OP_XC;
+                    op.b[0] = (uint8_t)bb1;
+                    op.b[2] = (uint8_t)g.q[0];
+                } else {
+                    // the DP only leaves insular qubits outside the block
+                    return fail(QK_EINVAL, "kernelize: non-insular qubit outside the active set");
+                }
+                P->ops.push_back(op);
+                continue;
+            }
+            op.b[0] = (uint8_t)bb0;
+            if (g.nq == 2) op.b[1] = (uint8_t)bb1;
             switch (g.kind) {
             case QK_X: op.code = OP_X; break;
             case QK_H:
@@ -480,6 +549,7 @@ void emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m
     K.rb = false;
     build_rb(P, K);
     P->kernels.push_back(K);
+    return QK_OK;
 }
 
 }  // namespace
@@ -512,16 +582,18 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
     const uint64_t lowmask = (1ull << ko.ell) - 1;
     std::vector<int64_t> seg_off(m + 1, 0);
     std::vector<int64_t> seg_fused, seg_lds;
+    const bool insular = ko.insular != 0;
     for (int64_t i = 0; i < m; ++i) {
         seg_off[i] = (int64_t)seg_fused.size();
-        uint64_t mask = 0;
+        uint64_t mask = 0, need = 0;
         int64_t s = P->tab.lds_alpha_ps;
         for (int64_t j = i; j >= 0; --j) {
             for (int t = 0; t < G[j].nq; ++t) mask |= 1ull << G[j].q[t];
+            need |= need_mask(G[j], insular);
             s += P->tab.lds_gate_ps[gate_class(G[j].kind)];
             const int k = popcount64(mask);
             const bool fok = ko.allow_fused && k <= ko.k_max;
-            const bool lok = ko.allow_lds && popcount64(mask | lowmask) <= ko.m_max;
+            const bool lok = ko.allow_lds && popcount64(need | lowmask) <= ko.m_max;
             if (!fok && !lok) break;
             seg_fused.push_back(fok ? P->tab.fused_ps[k] : kInf);
             seg_lds.push_back(lok ? s : kInf);
@@ -542,12 +614,12 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
                 for (int64_t e = seg_off[i]; e < seg_off[i + 1]; ++e) {
                     const int64_t j = i - (e - seg_off[i]);
                     if (seg_fused[e] < kInf) {
-                        segment_features(&G[j], (int)(i - j + 1), n, QK_KERNEL_FUSED, ko.dtype, f);
+                        segment_features(&G[j], (int)(i - j + 1), n, QK_KERNEL_FUSED, ko.dtype, insular, f);
                         feats.insert(feats.end(), f, f + kNumFeatures);
                         dst.push_back(&seg_fused[e]);
                     }
                     if (seg_lds[e] < kInf) {
-                        segment_features(&G[j], (int)(i - j + 1), n, QK_KERNEL_LDS, ko.dtype, f);
+                        segment_features(&G[j], (int)(i - j + 1), n, QK_KERNEL_LDS, ko.dtype, insular, f);
                         feats.insert(feats.end(), f, f + kNumFeatures);
                         dst.push_back(&seg_lds[e]);
                     }
@@ -604,7 +676,8 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
     const int m_exec = std::min(n, mblk);
     int64_t j = 0;
     for (int64_t i : cuts) {
-        emit_kernel(P, j, i, back_t[i], back_cost[i], m_exec);
+        rc = emit_kernel(P, j, i, back_t[i], back_cost[i], m_exec);
+        if (rc) { delete P; return rc; }
         j = i;
     }
     *out = P;
@@ -635,10 +708,11 @@ int build_single(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, int ty
     if (rc) { delete P; return rc; }
     const int64_t m = (int64_t)P->gates.size();
     if (m == 0) { delete P; return fail(QK_EINVAL, "kernelize_single: no gate left after SWAP absorption"); }
-    uint64_t mask = 0;
+    uint64_t mask = 0, need = 0;
     int64_t s = P->tab.lds_alpha_ps;
     for (const CGate& g : P->gates) {
         for (int t = 0; t < g.nq; ++t) mask |= 1ull << g.q[t];
+        need |= need_mask(g, ko.insular != 0);
         s += P->tab.lds_gate_ps[gate_class(g.kind)];
     }
     const int k = popcount64(mask);
@@ -648,11 +722,12 @@ int build_single(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, int ty
         if (k > ko.k_max) { delete P; return fail(QK_EINVAL, "kernelize_single: too many qubits for a fused kernel"); }
         cost = P->tab.fused_ps[k];
     } else {
-        if (popcount64(mask | lowmask) > ko.m_max) { delete P; return fail(QK_EINVAL, "kernelize_single: too many qubits for an LDS kernel"); }
+        if (popcount64(need | lowmask) > ko.m_max) { delete P; return fail(QK_EINVAL, "kernelize_single: too many qubits for an LDS kernel"); }
         cost = s;
     }
     P->total_cost = cost;
-    emit_kernel(P, 0, m, type, cost, std::min(n, mblk));
+    rc = emit_kernel(P, 0, m, type, cost, std::min(n, mblk));
+    if (rc) { delete P; return rc; }
     *out = P;
     return QK_OK;
 }

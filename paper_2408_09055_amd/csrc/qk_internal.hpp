@@ -43,6 +43,11 @@ enum OpCode : uint8_t {
     OP_DENSEK = 8,  // 2^k x 2^k matrix on bits b[0..k-1] (sorted ascending);
                     // register form: on register bits 0..k-1
     OP_H = 9,       // Hadamard on bit b0: coef[0..3] hold its matrix (coef[0] = 1/sqrt 2)
+    // Insular forms: b[2], b[3] are state qubits outside the block, whose
+    // values are bits of the block's first amplitude index.
+    OP_BPHASE = 10, // multiply the block by coef[bit(b2) + 2 bit(b3)] (k = 2) or coef[bit(b2)] (k = 1)
+    OP_DIAG1C = 11, // diag(coef[2 s], coef[2 s + 1]) on bit b0, s = bit(b2)
+    OP_XC = 12,     // swap the halves of bit b0 when bit(b2) = 1
 };
 
 struct Op {

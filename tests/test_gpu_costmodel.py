@@ -166,7 +166,7 @@ def test_learned_planner_matches_oracle_dp(ctx, tmp_path):
     pd = _flat_to_dict(p)
     n = 14
     for circ in (W.qft(n), W.random_layered(n, 3, 4), W.ghz(n)):
-        ko = qk.kopts(dtype=0, cost_model=qk.QK_COST_LEARNED, m_max=10, ell=4)
+        ko = qk.kopts(dtype=0, cost_model=qk.QK_COST_LEARNED, m_max=10, ell=4, insular=0)
         plan = qk.kernelize(ctx, circ, ko)
         assert plan.cost_model()["learned_used"]
         gates, _ = oracle.canonicalize(circ)

@@ -310,3 +310,66 @@ def test_sv_alloc_too_large(ctx):
     with pytest.raises(qk.QkError) as ei:
         qk.sv_alloc(ctx, 40)
     assert ei.value.code == qk.QK_EINVAL
+
+
+# ---------------------------------------------------------------- insular qubits
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m_max,ell", [(12, 6), (13, 7), (10, 4)])
+def test_insular_lds_kernels(ctx, dtype, m_max, ell):
+    """One LDS kernel whose non-diagonal gates touch only a few qubits while
+    diagonal gates (RZ, T, CP, CZ, RZZ) and CX controls range over all 18:
+    the qubits outside the block become block phases, selected diagonals and
+    conditioned X (register-blocked kernel for m = 12/13, staged LDS kernel
+    for m = 10), against the oracle."""
+    if dtype == qk.QK_C128 and m_max > 12:
+        pytest.skip("complex128 blocks hold 2^12 amplitudes")
+    n = 18
+    rng = np.random.default_rng(40 + m_max + dtype)
+    active_pool = list(range(ell)) + [int(q) for q in rng.choice(np.arange(ell, n), m_max - ell, replace=False)]
+    gates = []
+    for _ in range(80):
+        r = rng.random()
+        if r < 0.25:
+            gates.append(W.gate(W.U3 if rng.random() < 0.5 else W.H, [int(rng.choice(active_pool))],
+                                list(rng.uniform(0, 6, 3))))
+        elif r < 0.4:
+            t = int(rng.choice(active_pool))
+            c = int(rng.choice([q for q in range(n) if q != t]))
+            gates.append(W.gate(W.CX, [c, t]))
+        elif r < 0.55:
+            gates.append(W.gate([W.RZ, W.T, W.P, W.S][int(rng.integers(4))], [int(rng.integers(n))],
+                                [float(rng.uniform(0, 6))]))
+        else:
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            gates.append(W.gate([W.CP, W.CZ, W.RZZ][int(rng.integers(3))], [a, b], [float(rng.uniform(0, 6))]))
+    circ = W.from_list(n, gates)
+    psi = W.random_state(n, 77)
+    ref = oracle.run(circ, psi)
+    ko = qk.kopts(dtype=dtype, m_max=m_max, ell=ell, insular=1)
+    plan = qk.kernelize_single(ctx, circ, ko, qk.QK_KERNEL_LDS)
+    st = qk.sv_alloc(ctx, n, dtype)
+    st.upload(psi.astype(st.np_dtype))
+    qk.execute_plan(ctx, plan, st)
+    got = st.download()
+    st.free()
+    _check(got, ref, dtype, f"insular m={m_max} ell={ell}")
+    # without the relaxation the same kernel is infeasible
+    with pytest.raises(qk.QkError):
+        qk.kernelize_single(ctx, circ, qk.kopts(dtype=dtype, m_max=m_max, ell=ell, insular=0), qk.QK_KERNEL_LDS)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_insular_plans_match_plain_plans(ctx, dtype):
+    """Whole-circuit plans with and without the relaxation give the same
+    state (QFT-18, random layered, GHZ) and the relaxed plan has no more
+    kernels."""
+    n = 18
+    for circ in (W.qft(n), W.random_layered(n, 6, 12), W.ghz(n)):
+        psi = W.random_state(n, 5)
+        ref = oracle.run(circ, psi)
+        out = {}
+        for ins in (0, 1):
+            ko = qk.kopts(dtype=dtype, insular=ins)
+            out[ins] = (_run(ctx, circ, psi, dtype, ko), len(qk.kernelize(ctx, circ, ko)))
+            _check(out[ins][0], ref, dtype, f"{circ.name} insular={ins}")
+        assert out[1][1] <= out[0][1]

@@ -51,7 +51,7 @@ def _native_plan(ctx, circ, opts, tab, dtype=qk.QK_C64):
     ko = qk.kopts(dtype=dtype, k_max=opts.k_max, m_max=opts.m_max, ell=opts.ell,
                   absorb_swaps=int(opts.absorb_swaps), allow_fused=int(opts.allow_fused),
                   allow_lds=int(opts.allow_lds), block_qubits=max(opts.m_max, opts.k_max + 1),
-                  tables=(tab.fused, tab.alpha, tab.gate))
+                  tables=(tab.fused, tab.alpha, tab.gate), insular=int(opts.insular))
     return qk.kernelize(ctx, circ, ko)
 
 
@@ -65,6 +65,15 @@ def _rand_tables(rng, scale):
 
 @pytest.mark.parametrize("seed", range(40))
 def test_native_dp_equals_oracle_random(seed, hctx):
+    _random_case(seed, hctx, insular=False)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_native_dp_equals_oracle_random_insular(seed, hctx):
+    _random_case(seed, hctx, insular=True)
+
+
+def _random_case(seed, hctx, insular):
     rng = np.random.default_rng(1000 + seed)
     n = int(rng.integers(2, 14))
     circ = W.random_circuit(n, int(rng.integers(1, 120)), rng)
@@ -72,7 +81,7 @@ def test_native_dp_equals_oracle_random(seed, hctx):
     m_max = int(rng.integers(max(2, k_max), 15))
     opts = oracle.KOpts(k_max=k_max, m_max=m_max, ell=int(rng.integers(1, m_max + 1)),
                         allow_fused=bool(rng.integers(0, 2)) or True, allow_lds=bool(rng.integers(0, 2)),
-                        absorb_swaps=bool(rng.integers(0, 2)))
+                        absorb_swaps=bool(rng.integers(0, 2)), insular=insular)
     if opts.k_max < 2 and not opts.allow_lds:
         opts.k_max = 2
     tab = _rand_tables(rng, int(rng.choice([10, 1000, 10 ** 9])))
@@ -102,7 +111,9 @@ def test_native_dp_equals_oracle_workloads(name, hctx):
             "hea16": lambda: W.hea(16, 8, np.random.default_rng(4))}[name]()
     rng = np.random.default_rng(len(name))
     for opts in (oracle.KOpts(k_max=5, m_max=12, ell=3), oracle.KOpts(k_max=7, m_max=13, ell=4),
-                 oracle.KOpts(k_max=3, m_max=10, ell=1, allow_lds=False)):
+                 oracle.KOpts(k_max=3, m_max=10, ell=1, allow_lds=False),
+                 oracle.KOpts(k_max=5, m_max=12, ell=3, insular=True),
+                 oracle.KOpts(k_max=7, m_max=13, ell=7, insular=True)):
         tab = _rand_tables(rng, 10 ** 6)
         gates, P, cost, ks = _oracle_plan(circ, opts, tab)
         plan = _native_plan(hctx, circ, opts, tab)

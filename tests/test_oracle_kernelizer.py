@@ -178,3 +178,60 @@ def test_mlp_training_reduces_loss():
         l, g = oracle.mlp_loss_grad(p, x, t)
         oracle.adam_step(p, g, st, lr=1e-2)
     assert l < 0.2 * l0
+
+
+# ---------------------------------------------------------------- insular qubits
+@pytest.mark.parametrize("seed", range(30))
+def test_insular_dp_equals_brute_force_and_never_costs_more(seed):
+    """With the insular relaxation the DP still equals the brute force, and
+    since it only enlarges the set of feasible LDS segments, its optimum is
+    never above the plain one."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(3, 8))
+    gates = _rand_gates(n, int(rng.integers(1, 12)), rng)
+    base = dict(k_max=int(rng.integers(1, 4)), m_max=int(rng.integers(2, 5)), ell=int(rng.integers(0, 2)))
+    tab = _rand_tables(rng)
+    ins = KOpts(insular=True, **base)
+    c_dp, k_dp = oracle.ordered_kernelize(gates, ins, tab)
+    c_bf, k_bf = oracle.brute_force_kernelize(gates, ins, tab)
+    assert (c_dp, k_dp) == (c_bf, k_bf)
+    assert oracle.check_plan(gates, k_dp, ins, tab) == c_dp
+    try:
+        c_plain, _ = oracle.ordered_kernelize(gates, KOpts(**base), tab)
+    except ValueError:
+        return   # plain infeasible: the relaxation can only add plans
+    assert c_dp <= c_plain
+
+
+def test_insular_qubit_sets_by_definition():
+    """Diagonal gates need no active qubit, CX needs its target only, every
+    other gate needs all of its qubits (the definition applied gate by gate:
+    a qubit is insular when the matrix is diagonal in it)."""
+    for kind, qs in ((W.Z, (3,)), (W.S, (3,)), (W.T, (3,)), (W.RZ, (3,)), (W.P, (3,)), (W.CZ, (1, 4)),
+                     (W.CP, (1, 4)), (W.RZZ, (1, 4))):
+        assert oracle.need_qubits(kind, qs, True) == ()
+        # and the matrix is indeed diagonal
+        g = W.gate(kind, list(qs), [0.7, 0.3, 0.1])
+        mtx = oracle.gate_matrix(g)
+        assert np.allclose(mtx, np.diag(np.diag(mtx)))
+    assert oracle.need_qubits(W.CX, (2, 5), True) == (5,)
+    # CX is block diagonal in its control (bit 0 of the matrix index)
+    cx = oracle.gate_matrix(W.gate(W.CX, [2, 5]))
+    assert np.allclose(cx[np.ix_([0, 2], [1, 3])], 0) and np.allclose(cx[np.ix_([1, 3], [0, 2])], 0)
+    for kind, qs in ((W.H, (2,)), (W.X, (2,)), (W.U3, (2,)), (W.SWAP, (1, 2))):
+        assert oracle.need_qubits(kind, qs, True) == qs
+    assert oracle.need_qubits(W.CZ, (1, 4), False) == (1, 4)
+
+
+def test_insular_qft_needs_one_pass_per_few_hadamards():
+    """QFT's controlled phases are diagonal, so with the relaxation only the
+    Hadamards constrain LDS kernels: with unit kernel costs the DP needs
+    ceil((n - ell) / (m - ell)) kernels or fewer, far below the plain DP."""
+    n, m, ell = 24, 10, 4
+    gates, _ = oracle.canonicalize(W.qft(n))
+    tab = CostTables(fused=[0] + [10 ** 9] * 7, alpha=1, gate=[0] * 7)
+    c_ins, k_ins = oracle.ordered_kernelize(gates, KOpts(k_max=1, m_max=m, ell=ell, allow_fused=False,
+                                                         insular=True), tab)
+    c_plain, _ = oracle.ordered_kernelize(gates, KOpts(k_max=1, m_max=m, ell=ell, allow_fused=False), tab)
+    assert len(k_ins) <= math.ceil((n - ell) / (m - ell)) + 1
+    assert c_ins < c_plain
