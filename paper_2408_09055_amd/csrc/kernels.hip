@@ -103,6 +103,24 @@ __device__ void op_diag1(C* sm, int m, int j, const C* __restrict__ u)
         sm[r] = cmul(sm[r], ((r >> j) & 1u) ? d1 : d0);
 }
 
+// Run of controlled phases on target bit t (OP_PHRUN, block form): each
+// amplitude with bit t set takes the product of the phases whose partner bit
+// (a block bit, or 64 + a state qubit outside the block) is 1.
+template <typename C>
+__device__ void op_phrun(C* sm, int m, int t, const C* __restrict__ u, int len, uint64_t bb)
+{
+    for (uint32_t r = threadIdx.x; r < (1u << m); r += kNT) {
+        if (!((r >> t) & 1u)) continue;
+        C f = C{1, 0};
+        for (int e = 0; e < len; ++e) {
+            const int code = (int)u[2 * e + 1].x;
+            const uint32_t bit = code >= 64 ? (uint32_t)(bb >> (code - 64)) & 1u : (r >> code) & 1u;
+            if (bit) f = cmul(f, u[2 * e]);
+        }
+        sm[r] = cmul(sm[r], f);
+    }
+}
+
 // Whole block times one coefficient (a phase fixed by qubits outside the block).
 template <typename C>
 __device__ void op_scale(C* sm, int m, const C c)
@@ -397,6 +415,7 @@ __global__ __launch_bounds__(kNT) void k_block_seq(C* __restrict__ psi, BlockDes
             case OP_BPHASE: op_scale(s, m, u[op.k == 2 ? s2 + 2 * s3 : s2]); break;
             case OP_DIAG1C: op_diag1(s, m, op.b[0], u + 2 * s2); break;
             case OP_XC: if (s2) op_x(s, m, op.b[0]); break;
+            case OP_PHRUN: op_phrun(s, m, op.b[0], u, op.k, bb); break;
             case OP_DENSE1: case OP_H: op_dense1(s, m, op.b[0], u); break;
             case OP_DIAG1: op_diag1(s, m, op.b[0], u); break;
             case OP_X: op_x(s, m, op.b[0]); break;
@@ -765,12 +784,109 @@ __device__ __forceinline__ void rb_densek(V (&v)[kRbAmps], const C* __restrict__
     });
 }
 
+// Operations on bits the thread index supplies (register-form bit code
+// 0x80 | block bit): the bit's value is the same for all 16 amplitudes of the
+// thread, so a diagonal factor or a control is a per-thread selection.
+__device__ __forceinline__ uint32_t tbit(uint32_t tb, uint8_t code) { return (tb >> (code & 0x7fu)) & 1u; }
+
+template <typename V>
+__device__ __forceinline__ bool is_one(const V& c) { return c.x == 1 && c.y == 0; }
+
+// c ? a : b per component (a select of whole structs can become an indexed
+// scratch access for complex128)
+template <typename V>
+__device__ __forceinline__ V vsel(bool c, const V& a, const V& b) { return V{c ? a.x : b.x, c ? a.y : b.y}; }
+
+// every amplitude times (s ? d1 : d0)
+template <typename V>
+__device__ __forceinline__ void rb_scale_sel(V (&v)[kRbAmps], uint32_t s, const V d0, const V d1)
+{
+    if (is_one(d0) && is_one(d1)) return;
+    const V f = vsel(s != 0, d1, d0);
+    static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], f); });
+}
+
+// amplitudes with register bit K set times f
+template <int K, typename V>
+__device__ __forceinline__ void rb_mul_half(V (&v)[kRbAmps], const V f)
+{
+    static_for<0, kRbAmps / 2>([&](auto P) QK_AI {
+        constexpr int i1 = cins0(P.value, K) | (1 << K);
+        v[i1] = cmul(v[i1], f);
+    });
+}
+
+// swap the halves of register bit K where c is set (CX with a thread-bit control)
+template <int K, typename V>
+__device__ __forceinline__ void rb_cswap(V (&v)[kRbAmps], uint32_t c)
+{
+    static_for<0, kRbAmps / 2>([&](auto P) QK_AI {
+        constexpr int i0 = cins0(P.value, K), i1 = i0 | (1 << K);
+        const V a = v[i0], b = v[i1];
+        v[i0] = vsel(c != 0, b, a);
+        v[i1] = vsel(c != 0, a, b);
+    });
+}
+
 template <typename C, typename V>
-__device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* coef, uint64_t bb)
+__device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* coef, uint64_t bb, uint32_t tb)
 {
     const C* u = coef + op.coef;
     // values of the state qubits b[2], b[3] outside the block (uniform)
     const uint32_t s2 = (uint32_t)(bb >> op.b[2]) & 1u, s3 = (uint32_t)(bb >> op.b[3]) & 1u;
+    const bool t0 = (op.b[0] & 0x80u) != 0, t1 = (op.b[1] & 0x80u) != 0;
+    if (op.code == OP_DIAG1 && t0) {
+        rb_scale_sel(v, tbit(tb, op.b[0]), ld_coef(u), ld_coef(u + 1));
+        return;
+    }
+    if (op.code == OP_DIAG1C && t0) {
+        rb_scale_sel(v, tbit(tb, op.b[0]), ld_coef(u + 2 * s2), ld_coef(u + 2 * s2 + 1));
+        return;
+    }
+    if ((op.code == OP_CZ || op.code == OP_CPHASE) && (t0 || t1)) {
+        const V ph = op.code == OP_CZ ? V{-1, 0} : ld_coef(u);
+        const V one{1, 0};
+        if (t0 && t1) {
+            const uint32_t c = tbit(tb, op.b[0]) & tbit(tb, op.b[1]);
+            if (__ballot(c)) {
+                const V f = vsel(c != 0, ph, one);
+                static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], f); });
+            }
+        } else {
+            const V f = vsel(tbit(tb, t0 ? op.b[0] : op.b[1]) != 0, ph, one);
+            dispatch1(t0 ? op.b[1] : op.b[0], [&](auto K) QK_AI { rb_mul_half<K.value>(v, f); });
+        }
+        return;
+    }
+    if (op.code == OP_CX && t0) {
+        const uint32_t c = tbit(tb, op.b[0]);
+        dispatch1(op.b[1], [&](auto K) QK_AI { rb_cswap<K.value>(v, c); });
+        return;
+    }
+    if (op.code == OP_PHRUN) {
+        // product of the run's phases (partners: thread-index bits or qubits
+        // outside the block) as one factor per thread, then the target half
+        // is scaled once
+        const V one{1, 0};
+        V f = one;
+        for (int e = 0; e < op.k; ++e) {
+            const V ph = ld_coef(u + 2 * e);
+            const uint32_t code = (uint32_t)ld_coef(u + 2 * e + 1).x;
+            if (code >= 0x100u) {
+                if ((bb >> (code - 0x100u)) & 1u) f = cmul(f, ph);
+            } else {
+                const V g = cmul(f, ph);
+                f = vsel(tbit(tb, (uint8_t)code) != 0, g, f);
+            }
+        }
+        if (t0) {
+            const V g = vsel(tbit(tb, op.b[0]) != 0, f, one);
+            static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], g); });
+        } else {
+            dispatch1(op.b[0], [&](auto K) QK_AI { rb_mul_half<K.value>(v, f); });
+        }
+        return;
+    }
     switch (op.code) {
     case OP_BPHASE: {
         const V c = ld_coef(u + (op.k == 2 ? s2 + 2 * s3 : s2));
@@ -885,7 +1001,8 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     // default one), stores the last phase's.  Address of chunk I of this
     // thread = block base + thread part + chunk part; the chunk part is the
     // same for every thread.
-    const uint64_t ld_t = deposit(thr_deposit(tid, d.ld_reg, m), d.b.act, m);
+    const uint32_t tb_ld = thr_deposit(tid, d.ld_reg, m);
+    const uint64_t ld_t = deposit(tb_ld, d.b.act, m);
     const uint64_t st_t = deposit(thr_deposit(tid, d.st_reg, m), d.b.act, m);
     // amplitude offset of each register bit (uniform: selected with
     // compile-time indices into the active set, so it lives in scalar registers)
@@ -954,6 +1071,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
         const uint64_t nbase = next < d.b.nblocks ? block_base(next, d.b.act, m) : 0;
         if (next < d.b.nblocks) load_all(nbase);
         uint8_t cur[4] = {d.ld_reg[0], d.ld_reg[1], d.ld_reg[2], d.ld_reg[3]};
+        uint32_t tb = tb_ld;   // block index of this thread's register 0 in layout cur
         for (int p = 0; p < d.n_phases; ++p) {
             const uint32_t* pw = reinterpret_cast<const uint32_t*>(prog + p * sizeof(Phase));
             const uint32_t regw = lds_uniform(pw), rng = lds_uniform(pw + 1);
@@ -961,6 +1079,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
             if (!same_reg(cur, reg) && d.uses_lds) {
                 rb_transition(sm, v, cur, reg, m);
                 cur[0] = reg[0]; cur[1] = reg[1]; cur[2] = reg[2]; cur[3] = reg[3];
+                tb = thr_deposit(tid, cur, m);
             }
             for (uint32_t o = rng & 0xffffu; o < (rng >> 16); ++o) {
                 const uint32_t* ow = reinterpret_cast<const uint32_t*>(prog + d.ops_off + o * sizeof(Op));
@@ -973,7 +1092,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
                 op.b[2] = (uint8_t)w1;
                 op.b[3] = (uint8_t)(w1 >> 8);
                 op.coef = lds_uniform(ow + 3);
-                rb_apply(v, op, coef, base);
+                rb_apply(v, op, coef, base, tb);
             }
         }
         if (!same_reg(cur, d.st_reg) && d.uses_lds) rb_transition(sm, v, cur, d.st_reg, m);

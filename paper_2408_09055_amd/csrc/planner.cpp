@@ -17,6 +17,7 @@
 //   FP64 (later gates on the left) and turns each LDS kernel's gates into
 //   block-local operations.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -246,6 +247,18 @@ int op_nbits(const Op& op)
     return 1;
 }
 
+// Which of those bits the register-blocked kernel needs in registers (bit t
+// of the result <-> b[t]).  Diagonal operations and the CX control also run
+// on thread-index bits: each thread knows those bits of its amplitudes.
+unsigned op_reg_required(const Op& op)
+{
+    switch (op.code) {
+    case OP_BPHASE: case OP_DIAG1: case OP_DIAG1C: case OP_CZ: case OP_CPHASE: case OP_PHRUN: return 0u;
+    case OP_CX: return 2u;
+    default: return op_nbits(op) == 2 ? 3u : 1u;
+    }
+}
+
 int reg_pos(const uint8_t* reg, int bit)
 {
     for (int k = 0; k < kRbBits; ++k)
@@ -271,12 +284,12 @@ void build_rb(qk_plan* P, PKernel& K)
     rb_io_reg(P->dtype, nt, io_reg);
     std::vector<Phase> ph;
     std::vector<Op> lops;
+    std::vector<std::array<uint8_t, 4>> lop_reg;   // register layout each operation runs in
     auto has = [](const uint8_t* reg, int nreg, int b) {
         for (int t = 0; t < nreg; ++t)
             if (reg[t] == b) return true;
         return false;
     };
-    // complete reg[0..nreg) to four bits: first from `prefer`, then the lowest
     // complete reg[0..nreg) to four bits, preferring bits that keep the
     // layout directly loadable (above the 128-byte line), highest first
     const int safe_lo = P->dtype == QK_C128 ? 3 : 4;
@@ -296,6 +309,7 @@ void build_rb(qk_plan* P, PKernel& K)
         Op o = src;
         for (int u = 0; u < 7; ++u) o.b[u] = 0;
         lops.push_back(o);
+        lop_reg.push_back({p.reg[0], p.reg[1], p.reg[2], p.reg[3]});
         p.op_begin = 0;
         p.op_end = 1;
         ph.push_back(p);
@@ -306,15 +320,19 @@ void build_rb(qk_plan* P, PKernel& K)
         for (int o = 0; o < K.n_ops; ++o) {
             Op op = P->ops[K.op_off + o];
             const int nb = op_nbits(op);
-            bool fits = (nb == 0 || reg_pos(cur, op.b[0]) >= 0) && (nb < 2 || reg_pos(cur, op.b[1]) >= 0);
+            const unsigned rq = op_reg_required(op);
+            bool fits = (!(rq & 1u) || reg_pos(cur, op.b[0]) >= 0) && (!(rq & 2u) || reg_pos(cur, op.b[1]) >= 0);
             if (!fits) {
-                // bits of this and the following operations while four suffice
+                // required bits of this and the following operations while four suffice
                 uint8_t set[4];
                 int ns = 0;
                 for (int o2 = o; o2 < K.n_ops; ++o2) {
                     const Op& q = P->ops[K.op_off + o2];
-                    uint8_t nbits[2] = {q.b[0], q.b[1]};
-                    const int qn = op_nbits(q);
+                    const unsigned qr = op_reg_required(q);
+                    uint8_t nbits[2];
+                    int qn = 0;
+                    if (qr & 1u) nbits[qn++] = q.b[0];
+                    if (qr & 2u) nbits[qn++] = q.b[1];
                     uint8_t tmp[4];
                     std::memcpy(tmp, set, 4);
                     int nt2 = ns;
@@ -346,10 +364,41 @@ void build_rb(qk_plan* P, PKernel& K)
                 ph.push_back(p);
                 open = true;
             }
+            // register form: a register position, or 0x80 | block bit for a
+            // bit the thread index supplies
             Op lo = op;
-            if (nb >= 1) lo.b[0] = (uint8_t)reg_pos(cur, op.b[0]);
-            if (nb == 2) lo.b[1] = (uint8_t)reg_pos(cur, op.b[1]);
+            for (int t = 0; t < nb; ++t) {
+                const int rp = reg_pos(cur, op.b[t]);
+                lo.b[t] = (uint8_t)(rp >= 0 ? rp : (0x80 | op.b[t]));
+            }
+            if (op.code == OP_PHRUN) {
+                // partners held in registers leave the run as single phases
+                // (applied to their quarter); the run keeps the partners that
+                // are thread-index bits or outside the block
+                std::vector<cd> rest;
+                for (int e = 0; e < op.k; ++e) {
+                    const int code = (int)P->coefs[op.coef + 2 * e + 1].real();
+                    const int rp = code < 64 ? reg_pos(cur, code) : -1;
+                    if (rp >= 0) {
+                        Op cp{};
+                        cp.code = OP_CPHASE;
+                        cp.b[0] = lo.b[0];
+                        cp.b[1] = (uint8_t)rp;
+                        cp.coef = op.coef + 2 * e;
+                        lops.push_back(cp);
+                        lop_reg.push_back({cur[0], cur[1], cur[2], cur[3]});
+                    } else {
+                        rest.push_back(P->coefs[op.coef + 2 * e]);
+                        rest.push_back(P->coefs[op.coef + 2 * e + 1]);
+                    }
+                }
+                if (rest.empty()) continue;
+                lo.k = (uint8_t)(rest.size() / 2);
+                lo.coef = (uint32_t)P->coefs.size();
+                P->coefs.insert(P->coefs.end(), rest.begin(), rest.end());
+            }
             lops.push_back(lo);
+            lop_reg.push_back({cur[0], cur[1], cur[2], cur[3]});
         }
         if (open) ph.back().op_end = (uint16_t)lops.size();
     }
@@ -379,7 +428,23 @@ void build_rb(qk_plan* P, PKernel& K)
     const size_t csz = P->dtype == QK_C128 ? 16 : 8;
     auto up16 = [](size_t x) { return (x + 15) & ~size_t(15); };
     std::vector<cd> kc;
-    for (Op& o : lops) {
+    // phase runs: the partner codes become register form in the current
+    // phase's layout (recorded per operation while the phases were built)
+    for (size_t oi = 0; oi < lops.size(); ++oi) {
+        Op& o = lops[oi];
+        if (o.code == OP_PHRUN) {
+            const uint32_t first = (uint32_t)kc.size();
+            for (int e = 0; e < o.k; ++e) {
+                kc.push_back(P->coefs[o.coef + 2 * e]);
+                const int code = (int)P->coefs[o.coef + 2 * e + 1].real();
+                // partners are thread-index bits or outside the block here
+                const int rcode = code >= 64 ? 0x100 + (code - 64) : (0x80 | code);
+                (void)lop_reg;
+                kc.push_back(cd((double)rcode, 0.0));
+            }
+            o.coef = first;
+            continue;
+        }
         int cnt = 0;
         switch (o.code) {
         case OP_DENSE1: case OP_H: case OP_DIAG2: case OP_DIAG1C: cnt = 4; break;
@@ -413,6 +478,66 @@ void build_rb(qk_plan* P, PKernel& K)
         }
     }
     K.rb = true;
+}
+
+// A controlled phase on two block bits, or on one block bit with a partner
+// qubit outside the block: multiplies the amplitudes whose two bits are 1 by
+// `ph`.  Recognises CPHASE, CZ and the DIAG1C form of such a gate.
+struct CPForm {
+    int a, b;       // block bits; b = -1 when the partner is outside
+    int outside;    // partner state qubit when b == -1
+    cd ph;
+};
+
+bool cp_form(const qk_plan* P, const Op& op, CPForm& f)
+{
+    const cd one(1.0, 0.0);
+    switch (op.code) {
+    case OP_CPHASE: f = CPForm{op.b[0], op.b[1], -1, P->coefs[op.coef]}; return true;
+    case OP_CZ: f = CPForm{op.b[0], op.b[1], -1, cd(-1.0, 0.0)}; return true;
+    case OP_DIAG1C: {
+        const cd* D = &P->coefs[op.coef];
+        if (D[0] != one || D[1] != one || D[2] != one) return false;
+        f = CPForm{op.b[0], -1, op.b[2], D[3]};
+        return true;
+    }
+    default: return false;
+    }
+}
+
+// Merge runs of consecutive controlled phases that share one block bit (the
+// QFT's phases after each Hadamard) into one OP_PHRUN each: the kernels then
+// compute the product of the run's phases per thread and scale the target
+// half once, instead of once per gate.
+void group_phase_runs(qk_plan* P, int op_off)
+{
+    std::vector<Op> in(P->ops.begin() + op_off, P->ops.end());
+    P->ops.resize(op_off);
+    size_t o = 0;
+    while (o < in.size()) {
+        CPForm f0, f1;
+        int target = -1;
+        if (o + 1 < in.size() && cp_form(P, in[o], f0) && cp_form(P, in[o + 1], f1)) {
+            for (int c : {f0.a, f0.b})
+                if (c >= 0 && (c == f1.a || c == f1.b)) { target = c; break; }
+        }
+        if (target < 0) { P->ops.push_back(in[o]); ++o; continue; }
+        Op run{};
+        run.code = OP_PHRUN;
+        run.b[0] = (uint8_t)target;
+        run.coef = (uint32_t)P->coefs.size();
+        int len = 0;
+        CPForm f;
+        while (o < in.size() && len < 255 && cp_form(P, in[o], f) && (f.a == target || f.b == target)) {
+            const int partner = f.b < 0 ? 64 + f.outside : (f.a == target ? f.b : f.a);
+            P->coefs.push_back(f.ph);
+            P->coefs.push_back(cd((double)partner, 0.0));
+            ++len;
+            ++o;
+        }
+        run.k = (uint8_t)len;
+        P->ops.push_back(run);
+    }
 }
 
 // Append the kernel covering canonical gates [j, i) with the given type.
@@ -544,6 +669,7 @@ int emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m_
             P->ops.push_back(op);
         }
     }
+    if (K.type == QK_KERNEL_LDS) group_phase_runs(P, K.op_off);
     K.n_ops = (int)P->ops.size() - K.op_off;
     K.desc.n_ops = K.n_ops;
     K.rb = false;

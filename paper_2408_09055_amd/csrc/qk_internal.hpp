@@ -48,6 +48,13 @@ enum OpCode : uint8_t {
     OP_BPHASE = 10, // multiply the block by coef[bit(b2) + 2 bit(b3)] (k = 2) or coef[bit(b2)] (k = 1)
     OP_DIAG1C = 11, // diag(coef[2 s], coef[2 s + 1]) on bit b0, s = bit(b2)
     OP_XC = 12,     // swap the halves of bit b0 when bit(b2) = 1
+    // A run of k controlled phases sharing the target bit b0: entry e
+    // multiplies the amplitudes whose target bit and partner bit are both 1 by
+    // coef[2 e]; coef[2 e + 1].x holds the partner's code as a real number
+    // (block form: block bit, or 64 + state qubit outside the block; register
+    // form: register position 0..3, 0x80 | block bit for a thread-index bit,
+    // 0x100 + state qubit outside the block).
+    OP_PHRUN = 13,
 };
 
 struct Op {
