@@ -921,6 +921,10 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
 
 // LDS index swizzle: XOR the low 5 bits with higher bits so that lanes whose
 // block index differs only in high bits land in different banks.
+// LDS index swizzle: XOR the low 5 bits with higher bits so that lanes whose
+// block index differs only in high bits land in different banks.  Linear over
+// XOR: swz(a | b) = swz(a) ^ swz(b) for disjoint a, b.
+template <int ESZ>
 __device__ __forceinline__ uint32_t lds_swz(uint32_t i) { return i ^ (((i >> 5) ^ (i >> 10)) & 31u); }
 
 // Block index of this thread's rho = 0 under register bits reg: the thread
@@ -949,11 +953,13 @@ template <typename V>
 __device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint8_t* from, const uint8_t* to, int m)
 {
     __syncthreads();   // earlier readers of the LDS block are done
-    const uint32_t tf = thr_deposit(threadIdx.x, from, m);
-    static_for<0, kRbAmps>([&](auto R) QK_AI { sm[lds_swz(tf | reg_deposit<R.value>(from))] = v[R.value]; });
+    constexpr int ESZ = sizeof(V);
+    // swizzled thread part once per thread, swizzled register parts uniform
+    const uint32_t tf = lds_swz<ESZ>(thr_deposit(threadIdx.x, from, m));
+    static_for<0, kRbAmps>([&](auto R) QK_AI { sm[tf ^ lds_swz<ESZ>(reg_deposit<R.value>(from))] = v[R.value]; });
     __syncthreads();
-    const uint32_t tt = thr_deposit(threadIdx.x, to, m);
-    static_for<0, kRbAmps>([&](auto R) QK_AI { v[R.value] = sm[lds_swz(tt | reg_deposit<R.value>(to))]; });
+    const uint32_t tt = lds_swz<ESZ>(thr_deposit(threadIdx.x, to, m));
+    static_for<0, kRbAmps>([&](auto R) QK_AI { v[R.value] = sm[tt ^ lds_swz<ESZ>(reg_deposit<R.value>(to))]; });
 }
 
 __device__ __forceinline__ bool same_reg(const uint8_t* a, const uint8_t* b)
