@@ -139,8 +139,15 @@ int sv_restore(qk_state* st);
  * pi(x), where bit b of x goes to bit perm[b] (perm is a permutation of
  * 0..n-1).  The logical layout is updated accordingly, so the state's logical
  * content is unchanged.  Out of place through a scratch buffer of the state's
- * size (held by the state until sv_free). */
+ * size (held by the state until sv_free), except as noted below. */
 int sv_permute(qk_state* st, const int32_t* perm);
+/* The same relabelling in place, for a permutation that is its own inverse
+ * (perm[perm[b]] == b, e.g. the bit reversal left by the QFT's SWAPs): tiles
+ * over the lowest qubits and their images are exchanged in pairs, so no
+ * scratch buffer is needed.  sv_permute and sv_restore take this path for
+ * states of 64 GiB and more, or when the scratch buffer cannot be allocated.
+ * QK_EINVAL if perm is not an involution. */
+int sv_permute_inplace(qk_state* st, const int32_t* perm);
 /* ||psi||^2 in FP64 (compensated per-thread sums, fixed-order tree). */
 int sv_norm2(qk_state* st, double* out);
 /* <psi|ref> restricted to logical indices [offset, offset+count), FP64;

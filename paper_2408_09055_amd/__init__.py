@@ -113,6 +113,7 @@ _SIGS = {
     "sv_layout": [_P, _P], "sv_init_basis": [_P, _u64], "sv_upload": [_P, _P], "sv_download": [_P, _P],
     "sv_download_physical": [_P, _P],
     "sv_download_range": [_P, _u64, _u64, _P], "sv_restore": [_P], "sv_permute": [_P, _P],
+    "sv_permute_inplace": [_P, _P],
     "sv_norm2": [_P, _dbl_p], "sv_overlap_host": [_P, _P, _u64, _u64, _P],
     "sv_gather": [_P, _P, _u64, _P],
     "kernelize": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _PP],
@@ -381,6 +382,10 @@ class State:
     def permute(self, perm):
         p = np.ascontiguousarray(perm, np.int32)
         _check(_lib.sv_permute(self.h, p.ctypes.data))
+
+    def permute_inplace(self, perm):
+        p = np.ascontiguousarray(perm, np.int32)
+        _check(_lib.sv_permute_inplace(self.h, p.ctypes.data))
 
     def norm2(self) -> float:
         out = ctypes.c_double()

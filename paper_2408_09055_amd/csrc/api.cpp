@@ -72,8 +72,59 @@ int sync_stream(qk_ctx* ctx, const char* what)
 // One out-of-place permutation pass: bit b of the physical index moves to
 // bit perm[b].  Chooses the largest p such that the low p bits on both sides
 // fit in one tile of 2^m amplitudes, so reads and writes are 2^p-runs.
+// In place, for a permutation that is its own inverse: tile bits A are the
+// lowest qubits together with their images (A is closed under perm), so the
+// tiles come in pairs and both tiles of a pair are read before either is
+// written.  Returns QK_EUNSUPPORTED when no tile of at least 2^4 amplitudes
+// with a low run exists.
+int permute_pairs_pass(qk_state* st, const std::vector<int32_t>& perm, void* stream)
+{
+    const int n = st->n;
+    const int m_max = std::min(n, st->dtype == QK_C128 ? 11 : 12);
+    uint64_t A = 0;
+    for (int q = 0; q < n; ++q) {
+        if ((A >> q) & 1) continue;
+        const uint64_t add = (1ull << q) | (1ull << perm[q]);
+        if (__builtin_popcountll(A | add) > m_max) continue;
+        A |= add;
+        if (__builtin_popcountll(A) == m_max) break;
+    }
+    const int m = __builtin_popcountll(A);
+    if (m < 4 || !(A & 1)) return fail(QK_EUNSUPPORTED, "in-place permutation: no suitable tile");
+    PermPairDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.n = n;
+    d.m = m;
+    d.ntiles = 1ull << (n - m);
+    int j = 0;
+    for (int q = 0; q < n; ++q) if ((A >> q) & 1) d.act[j++] = (uint8_t)q;
+    for (int t = 0; t < m; ++t) {
+        const int img = perm[d.act[t]];
+        int u = 0;
+        while (d.act[u] != img) ++u;
+        d.sig[t] = (uint8_t)u;
+    }
+    for (int b = 0; b < n; ++b) d.perm[b] = (uint8_t)perm[b];
+    int e = launch_permute_pairs(st->dtype, st->psi, d, stream);
+    if (e) return hip_fail(e, "permute launch");
+    for (int q = 0; q < n; ++q) st->layout[q] = perm[st->layout[q]];
+    return QK_OK;
+}
+
+bool is_involution(const std::vector<int32_t>& perm)
+{
+    for (size_t b = 0; b < perm.size(); ++b)
+        if (perm[perm[b]] != (int32_t)b) return false;
+    return true;
+}
+
 int permute_pass(qk_state* st, const std::vector<int32_t>& perm, void* stream)
 {
+    // states of 64 GiB and more are permuted in place when the permutation
+    // is its own inverse (a second buffer would not fit beside them)
+    if ((amp_bytes(st->dtype) << st->n) >= (64ull << 30) && is_involution(perm))
+        return permute_pairs_pass(st, perm, stream);
+
     const int n = st->n;
     const int m = std::min(n, st->dtype == QK_C128 ? 12 : 13);
     std::vector<int32_t> inv(n);
@@ -114,6 +165,8 @@ int permute_pass(qk_state* st, const std::vector<int32_t>& perm, void* stream)
     if (!st->tmp) {
         if (hipMalloc(&st->tmp, bytes) != hipSuccess) {
             st->tmp = nullptr;
+            (void)hipGetLastError();
+            if (is_involution(perm)) return permute_pairs_pass(st, perm, stream);
             return fail(QK_ENOMEM, "permutation scratch allocation failed");
         }
     }
@@ -384,6 +437,22 @@ int sv_download(qk_state* st, void* host)
 {
     if (!st) return fail(QK_EINVAL, "sv_download: null state");
     return sv_download_range(st, 0, 1ull << st->n, host);
+}
+
+int sv_permute_inplace(qk_state* st, const int32_t* perm)
+{
+    if (!st || !perm) return fail(QK_EINVAL, "sv_permute_inplace: null argument");
+    int rc = need_device(st->ctx);
+    if (rc) return rc;
+    std::vector<int32_t> p(perm, perm + st->n);
+    std::vector<int> seen(st->n, 0);
+    for (int b = 0; b < st->n; ++b) {
+        if (p[b] < 0 || p[b] >= st->n || seen[p[b]]) return fail(QK_EINVAL, "sv_permute_inplace: not a permutation");
+        seen[p[b]] = 1;
+    }
+    if (!is_involution(p)) return fail(QK_EINVAL, "sv_permute_inplace: not its own inverse");
+    if (is_identity(p)) return QK_OK;
+    return permute_pairs_pass(st, p, st->ctx->stream);
 }
 
 int sv_permute(qk_state* st, const int32_t* perm)

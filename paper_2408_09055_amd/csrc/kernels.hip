@@ -1166,7 +1166,9 @@ __global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* _
     });
     auto dest_base = [&](uint64_t sb) {
         uint64_t db = 0;
-        for (int b = 0; b < d.n; ++b) if ((sb >> b) & 1) db |= 1ull << d.perm[b];
+        static_for<0, 40>([&](auto B) {
+            if (B.value < d.n && ((sb >> B.value) & 1)) db |= 1ull << d.perm[B.value];
+        });
         return db;
     };
     __syncthreads();
@@ -1206,6 +1208,77 @@ __global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* _
         if (next >= d.nblocks) break;
         blk = next;
         sb = nsb;
+        __syncthreads();
+    }
+}
+
+// In-place permutation pass for a bit permutation that is its own inverse
+// (the QFT's bit reversal): amplitude (T, i) -- tile T of the bits outside A,
+// local index i over A -- moves to (rho T, sigma i).  A workgroup takes the
+// tile pair {T, rho T} with base(T) <= base(rho T), stages both tiles in LDS
+// and writes each from the other: new_T[j] = old_{rho T}[sigma j].
+template <typename C>
+__global__ __launch_bounds__(kNT) void k_permute_pairs(C* __restrict__ psi, PermPairDesc d)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint16_t rlo[128], rhi[128];   // local index -> local index under sigma
+    const int m = d.m, tid = threadIdx.x;
+    C* sa = reinterpret_cast<C*>(smem);
+    C* sb = sa + (1u << m);
+    const int nlo = m / 2, nhi = m - nlo;
+    for (int h = tid; h < (1 << nlo); h += kNT) {
+        uint32_t r = 0;
+        for (int j = 0; j < nlo; ++j) if ((h >> j) & 1) r |= 1u << d.sig[j];
+        rlo[h] = (uint16_t)r;
+    }
+    for (int h = tid; h < (1 << nhi); h += kNT) {
+        uint32_t r = 0;
+        for (int j = 0; j < nhi; ++j) if ((h >> j) & 1) r |= 1u << d.sig[nlo + j];
+        rhi[h] = (uint16_t)r;
+    }
+    constexpr int CH = 16 / sizeof(C);
+    const uint32_t nch = (1u << m) / CH;
+    const uint64_t off_t = deposit((uint32_t)tid * CH, d.act, m);
+    uint64_t off_i[kMaxChunks];
+    static_for<0, kMaxChunks>([&](auto I) { off_i[I.value] = deposit((uint32_t)I.value * kNT * CH, d.act, m); });
+    auto image = [&](uint64_t b) {
+        uint64_t r = 0;
+        static_for<0, 40>([&](auto B) {
+            if (B.value < d.n && ((b >> B.value) & 1)) r |= 1ull << d.perm[B.value];
+        });
+        return r;
+    };
+    __syncthreads();
+    for (uint64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x) {
+        const uint64_t bt = block_base(t, d.act, m);
+        const uint64_t bp = image(bt);
+        if (bp < bt) continue;   // the partner tile's workgroup moves this pair
+        const bool same = bp == bt;
+        static_for<0, kMaxChunks>([&](auto I) {
+            const uint32_t c = tid + (uint32_t)I.value * kNT;
+            if (c < nch) {
+                *reinterpret_cast<u32x4*>(&sa[c * CH]) = *reinterpret_cast<const u32x4*>(&psi[bt + off_t + off_i[I.value]]);
+                if (!same)
+                    *reinterpret_cast<u32x4*>(&sb[c * CH]) = *reinterpret_cast<const u32x4*>(&psi[bp + off_t + off_i[I.value]]);
+            }
+        });
+        __syncthreads();
+        const C* from_t = same ? sa : sb;   // new tile T takes the partner's amplitudes
+        static_for<0, kMaxChunks>([&](auto I) {
+            const uint32_t c = tid + (uint32_t)I.value * kNT;
+            if (c < nch) {
+                union { C v[CH]; u32x4 w; } ut, up;
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    const uint32_t j = c * CH + e;
+                    const uint32_t sj = rlo[j & ((1u << nlo) - 1u)] | rhi[j >> nlo];
+                    ut.v[e] = from_t[sj];
+                    up.v[e] = sa[sj];
+                }
+                *reinterpret_cast<u32x4*>(&psi[bt + off_t + off_i[I.value]]) = ut.w;
+                if (!same) *reinterpret_cast<u32x4*>(&psi[bp + off_t + off_i[I.value]]) = up.w;
+            }
+        });
         __syncthreads();
     }
 }
@@ -1453,6 +1526,19 @@ int launch_block_rb(int dtype, void* psi, const RbDesc& d, const void* prog, voi
         return launch_rb_typed<double2, 256>(psi, d, prog, s);
     }
     return (int)hipErrorInvalidValue;
+}
+
+int launch_permute_pairs(int dtype, void* psi, const PermPairDesc& d, void* stream)
+{
+    const size_t lds = (size_t)(dtype == QK_C128 ? 32 : 16) << d.m;   // two tiles
+    hipStream_t s = (hipStream_t)stream;
+    const void* f = dtype == QK_C128 ? reinterpret_cast<const void*>(k_permute_pairs<double2>)
+                                     : reinterpret_cast<const void*>(k_permute_pairs<float2>);
+    const uint64_t res = resident_groups(f, lds);
+    const dim3 grid((uint32_t)std::min<uint64_t>(d.ntiles, res)), block(kNT);
+    if (dtype == QK_C128) hipLaunchKernelGGL(k_permute_pairs<double2>, grid, block, lds, s, (double2*)psi, d);
+    else hipLaunchKernelGGL(k_permute_pairs<float2>, grid, block, lds, s, (float2*)psi, d);
+    return (int)hipGetLastError();
 }
 
 int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream)

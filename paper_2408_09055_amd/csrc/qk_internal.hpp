@@ -87,6 +87,17 @@ struct PermDesc {
     uint8_t perm[40];      // source bit b -> destination bit perm[b]
 };
 
+// Descriptor of one in-place pass for a permutation that is its own inverse:
+// tiles over bits A (closed under the permutation) are processed in pairs
+// (T, image of T).
+struct PermPairDesc {
+    uint64_t ntiles;       // 2^(n - m)
+    int32_t n, m;
+    uint8_t act[16];       // tile bits A, ascending (act[0] = 0)
+    uint8_t sig[16];       // tile-local bit j -> tile-local bit sig[j]
+    uint8_t perm[40];      // bit b -> bit perm[b] (perm[perm[b]] = b)
+};
+
 // Register-blocked execution of a staged block: every thread keeps
 // kRbAmps = 16 amplitudes in registers (kRbBits = 4 block bits); a phase is a
 // choice of those 4 bits plus the operations that act only on them.  Moving
@@ -138,6 +149,7 @@ int launch_block(int dtype, int fused_k, void* psi, const BlockDesc& d, const Op
                  const void* coef, void* stream);
 int launch_block_rb(int dtype, void* psi, const RbDesc& d, const void* prog, void* stream);
 int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, void* stream);
+int launch_permute_pairs(int dtype, void* psi, const PermPairDesc& d, void* stream);
 int launch_fill_basis(int dtype, void* psi, uint64_t N, uint64_t x, void* stream);
 // Reductions: partial buffer must hold at least reduce_partials() doubles x 2.
 int reduce_partials();

@@ -373,3 +373,39 @@ def test_insular_plans_match_plain_plans(ctx, dtype):
             out[ins] = (_run(ctx, circ, psi, dtype, ko), len(qk.kernelize(ctx, circ, ko)))
             _check(out[ins][0], ref, dtype, f"{circ.name} insular={ins}")
         assert out[1][1] <= out[0][1]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_inplace_involution_pass_bit_exact(ctx, dtype):
+    """The in-place paired-tile pass moves every amplitude x to pi(x) for
+    involutions (bit reversal, random pair swaps with fixed points), bit for
+    bit, and refuses permutations that are not their own inverse."""
+    rng = np.random.default_rng(12)
+    for n in (5, 12, 16, 19, 22):
+        perms = [np.arange(n)[::-1].astype(np.int32)]
+        p = np.arange(n)
+        q = rng.permutation(n)
+        for a, b in zip(q[0:n // 2:2], q[1:n // 2:2]):
+            p[a], p[b] = b, a
+        perms.append(p.astype(np.int32))
+        for perm in perms:
+            assert np.array_equal(perm[perm], np.arange(n))
+            psi = W.random_state(n, 3 * n).astype(np.complex64 if dtype == qk.QK_C64 else np.complex128)
+            st = qk.sv_alloc(ctx, n, dtype)
+            st.upload(psi)
+            st.permute_inplace(perm)
+            assert st.layout() == [int(perm[q]) for q in range(n)]
+            raw = _raw_download(st)
+            x = np.arange(1 << n, dtype=np.int64)
+            px = np.zeros_like(x)
+            for b in range(n):
+                px |= ((x >> b) & 1) << int(perm[b])
+            assert np.array_equal(raw[px], psi), (n, perm)
+            st.permute_inplace(perm)            # involution: back to the start
+            assert st.layout() == list(range(n))
+            assert np.array_equal(st.download(), psi)
+            st.free()
+    st = qk.sv_alloc(ctx, 6, dtype)
+    with pytest.raises(qk.QkError):
+        st.permute_inplace(np.array([1, 2, 0, 3, 4, 5], np.int32))
+    st.free()

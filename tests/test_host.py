@@ -30,6 +30,16 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_binding_declares_every_int_function():
+    """Every int-returning function of the header has an argument signature
+    in the binding: an undeclared pointer argument would be truncated to a C
+    int by ctypes."""
+    header = open(os.path.join(os.path.dirname(__file__), "..", "include", "qk.h")).read()
+    int_funcs = set(re.findall(r"^int\s+(\w+)\s*\(", header, re.M))
+    undeclared = sorted(f for f in int_funcs if f not in qk._SIGS and f != "mlp_num_params")
+    assert not undeclared, undeclared
+
+
 def test_version_and_defaults():
     assert "gfx950" in qk.version()
     ko = qk.kopts()
