@@ -949,17 +949,35 @@ __device__ __forceinline__ uint32_t reg_deposit(const uint8_t* reg)
            ((RHO & 4) ? (1u << reg[2]) : 0u) | ((RHO & 8) ? (1u << reg[3]) : 0u);
 }
 
+// The block goes through LDS as 4-byte words: complex64 as a real plane and
+// an imaginary plane, complex128 as four planes.  Consecutive lanes then touch
+// consecutive 4-byte banks; 8- or 16-byte element accesses would pair up banks
+// and take twice the LDS cycles.
 template <typename V>
 __device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint8_t* from, const uint8_t* to, int m)
 {
+    constexpr int W = sizeof(V) / 4;             // 4-byte words per amplitude
+    uint32_t* plane = reinterpret_cast<uint32_t*>(sm);
+    const uint32_t P = 1u << m;                  // words per plane
     __syncthreads();   // earlier readers of the LDS block are done
-    constexpr int ESZ = sizeof(V);
     // swizzled thread part once per thread, swizzled register parts uniform
-    const uint32_t tf = lds_swz<ESZ>(thr_deposit(threadIdx.x, from, m));
-    static_for<0, kRbAmps>([&](auto R) QK_AI { sm[tf ^ lds_swz<ESZ>(reg_deposit<R.value>(from))] = v[R.value]; });
+    const uint32_t tf = lds_swz<4>(thr_deposit(threadIdx.x, from, m));
+    static_for<0, kRbAmps>([&](auto R) QK_AI {
+        const uint32_t i = tf ^ lds_swz<4>(reg_deposit<R.value>(from));
+        uint32_t w[W];
+        __builtin_memcpy(w, &v[R.value], sizeof(V));
+#pragma unroll
+        for (int k = 0; k < W; ++k) plane[k * P + i] = w[k];
+    });
     __syncthreads();
-    const uint32_t tt = lds_swz<ESZ>(thr_deposit(threadIdx.x, to, m));
-    static_for<0, kRbAmps>([&](auto R) QK_AI { v[R.value] = sm[tt ^ lds_swz<ESZ>(reg_deposit<R.value>(to))]; });
+    const uint32_t tt = lds_swz<4>(thr_deposit(threadIdx.x, to, m));
+    static_for<0, kRbAmps>([&](auto R) QK_AI {
+        const uint32_t i = tt ^ lds_swz<4>(reg_deposit<R.value>(to));
+        uint32_t w[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) w[k] = plane[k * P + i];
+        __builtin_memcpy(&v[R.value], w, sizeof(V));
+    });
 }
 
 __device__ __forceinline__ bool same_reg(const uint8_t* a, const uint8_t* b)
