@@ -504,16 +504,22 @@ def features(seg, n: int, ktype: int, dtype_c128: bool, insular: bool = False) -
     [9] min qubit  [10] max qubit  [11] mean qubit  (physical positions)
     [12] qubits below 6  [13] diagonal gates  [14] fused one-hot
     [15] LDS one-hot  [16] n  [17] complex128 flag
-    [18] k * [fused]  [19] gate count * [LDS]
+    [18] k * [fused]
+    [19] LDS only: register phases beyond the first, ceil(r / 4) - 1 (at
+         least 0), with r the qubits some gate needs in registers (all
+         qubits of non-diagonal gates except a CX control)
     """
     from workloads import Z, S, T, RZ, P, CZ, CP, RZZ
     diag_kinds = {Z, S, T, RZ, P, CZ, CP, RZZ}
     f = np.zeros(NUM_FEATURES)
     mask = 0
     need_only = insular and ktype == TYPE_LDS
+    regq = 0
     for (kind, qs, _) in seg:
         for q in (need_qubits(kind, qs, True) if need_only else qs):
             mask |= 1 << q
+        for q in need_qubits(kind, qs, True):
+            regq |= 1 << q
         f[2 + gate_class(kind)] += 1
         if kind in diag_kinds:
             f[13] += 1
@@ -529,7 +535,8 @@ def features(seg, n: int, ktype: int, dtype_c128: bool, insular: bool = False) -
     f[16] = n
     f[17] = 1.0 if dtype_c128 else 0.0
     f[18] = k * f[14]
-    f[19] = len(seg) * f[15]
+    r = bin(regq).count("1")
+    f[19] = max(0, (r + 3) // 4 - 1) if ktype == TYPE_LDS else 0.0
     return f
 
 

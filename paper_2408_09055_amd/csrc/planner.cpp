@@ -148,9 +148,11 @@ void segment_features(const CGate* g, int count, int n, int type, int dtype, boo
     uint64_t mask = 0;
     int diag = 0;
     const bool need_only = insular && type == QK_KERNEL_LDS;
+    uint64_t regq = 0;   // qubits some operation needs in registers
     for (int i = 0; i < count; ++i) {
         if (need_only) mask |= need_mask(g[i], true);
         else for (int j = 0; j < g[i].nq; ++j) mask |= 1ull << g[i].q[j];
+        regq |= need_mask(g[i], true);
         f[2 + gate_class(g[i].kind)] += 1.0f;
         if (kind_is_diagonal(g[i].kind)) ++diag;
     }
@@ -177,7 +179,10 @@ void segment_features(const CGate* g, int count, int n, int type, int dtype, boo
     f[16] = (float)n;
     f[17] = dtype == QK_C128 ? 1.0f : 0.0f;
     f[18] = (float)k * f[14];
-    f[19] = (float)count * f[15];
+    // LDS kernels: register phases beyond the first (four register bits per
+    // phase; each further phase costs an LDS transpose of the block)
+    const int kr = popcount64(regq);
+    f[19] = type == QK_KERNEL_LDS ? (float)std::max(0, (kr + 3) / 4 - 1) : 0.0f;
 }
 
 // ------------------------------------------------------------------ kernelize

@@ -106,8 +106,15 @@ def test_features_by_hand():
     exp[0] = 3; exp[1] = 4
     exp[2 + oracle.CLASS_H] = 1; exp[2 + oracle.CLASS_CZ] = 1; exp[2 + oracle.CLASS_U3] = 2
     exp[9] = 1; exp[10] = 7; exp[11] = 11 / 3; exp[12] = 2; exp[13] = 2
-    exp[14] = 0; exp[15] = 1; exp[16] = 8; exp[17] = 0; exp[18] = 0; exp[19] = 4
+    exp[14] = 0; exp[15] = 1; exp[16] = 8; exp[17] = 0; exp[18] = 0; exp[19] = 0
     assert np.allclose(f, exp)
+    # register phases: H on 1, U3 on 7 need registers (2 qubits: one phase);
+    # five more one-qubit gates and a CX target make 8 -> two phases
+    c2 = W.from_list(12, [W.gate(W.H, [q]) for q in (1, 2, 3, 4, 5)] + [W.gate(W.U3, [7], [1, 2, 3]),
+                                                                          W.gate(W.CX, [9, 8]), W.gate(W.CZ, [10, 11])])
+    g2, _ = oracle.canonicalize(c2)
+    assert oracle.features(g2, 12, oracle.TYPE_LDS, True)[19] == 1
+    assert oracle.features(g2, 12, oracle.TYPE_FUSED, True)[19] == 0
 
 
 # --------------------------------------------------------------------------
