@@ -83,6 +83,7 @@ int time_launch(qk_ctx* ctx, const qk_plan* P, int64_t i, qk_state* st, int reps
         rd.n_phases = 0;
         rd.uses_lds = 0;
         std::memcpy(rd.st_reg, rd.ld_reg, sizeof(rd.ld_reg));
+        std::memcpy(rd.st_lx, rd.ld_lx, sizeof(rd.ld_lx));
     }
     const int fused_k = (K.type == QK_KERNEL_FUSED && n_ops_override < 0) ? K.k : 0;
     std::vector<float> t;

@@ -828,6 +828,132 @@ __device__ __forceinline__ void rb_cswap(V (&v)[kRbAmps], uint32_t c)
     });
 }
 
+// Operations on a lane-pinned bit (register-form code 0x40 | j: the block bit
+// on lane bit 4 + j).  v_permlane16_swap / v_permlane32_swap with both
+// operands equal hand every lane the two amplitudes of its pair: the first
+// result holds the amplitude whose lane bit is clear, the second the one
+// whose lane bit is set.  A one-qubit gate then needs no LDS and no barrier.
+template <int J>
+__device__ __forceinline__ void lane_pair_u32(uint32_t x, uint32_t& lo, uint32_t& hi)
+{
+    if constexpr (J == 0) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        lo = r[0];
+        hi = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        lo = r[0];
+        hi = r[1];
+    }
+}
+
+template <int J, typename V>
+__device__ __forceinline__ void lane_pair(const V& x, V& x0, V& x1)
+{
+    using R = decltype(x.x);
+    constexpr int W = sizeof(R) / 4;
+    uint32_t a[W], b[W], a0[W], a1[W], b0[W], b1[W];
+    __builtin_memcpy(a, &x.x, sizeof(R));
+    __builtin_memcpy(b, &x.y, sizeof(R));
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        lane_pair_u32<J>(a[k], a0[k], a1[k]);
+        lane_pair_u32<J>(b[k], b0[k], b1[k]);
+    }
+    __builtin_memcpy(&x0.x, a0, sizeof(R));
+    __builtin_memcpy(&x0.y, b0, sizeof(R));
+    __builtin_memcpy(&x1.x, a1, sizeof(R));
+    __builtin_memcpy(&x1.y, b1, sizeof(R));
+}
+
+// this lane's value of lane bit 4 + J
+template <int J>
+__device__ __forceinline__ bool lane_hi() { return (threadIdx.x >> (4 + J)) & 1u; }
+
+// 2x2 matrix on lane bit 4 + J: the lane computes its own row
+template <int J, typename C, typename V>
+__device__ __forceinline__ void rb_lane_dense1(V (&v)[kRbAmps], const C* __restrict__ u)
+{
+    const bool hi = lane_hi<J>();
+    const V p = vsel(hi, ld_coef(u + 2), ld_coef(u)), q = vsel(hi, ld_coef(u + 3), ld_coef(u + 1));
+    static_for<0, kRbAmps>([&](auto I) QK_AI {
+        V x0, x1;
+        lane_pair<J>(v[I.value], x0, x1);
+        v[I.value] = cmadd(q, x1, cmul(p, x0));
+    });
+}
+
+// Hadamard on lane bit 4 + J: (x0 +- x1) * coef[0]
+template <int J, typename C, typename V>
+__device__ __forceinline__ void rb_lane_h(V (&v)[kRbAmps], const C* __restrict__ u)
+{
+    using R = decltype(v[0].x);
+    const R s = uniform_real(u[0].x);
+    const R sg = lane_hi<J>() ? R(-1) : R(1);
+    static_for<0, kRbAmps>([&](auto I) QK_AI {
+        V x0, x1;
+        lane_pair<J>(v[I.value], x0, x1);
+        v[I.value] = V{(x0.x + sg * x1.x) * s, (x0.y + sg * x1.y) * s};
+    });
+}
+
+// X on lane bit 4 + J for the registers selected by SEL (bit i <-> register
+// i) where the per-lane condition c holds: each such amplitude takes its
+// partner's value
+template <int J, typename V>
+__device__ __forceinline__ void rb_lane_x(V (&v)[kRbAmps], uint32_t sel, bool c)
+{
+    const bool hi = lane_hi<J>();
+    static_for<0, kRbAmps>([&](auto I) QK_AI {
+        if ((sel >> I.value) & 1u) {
+            V x0, x1;
+            lane_pair<J>(v[I.value], x0, x1);
+            v[I.value] = vsel(c, hi ? x0 : x1, v[I.value]);
+        }
+    });
+}
+
+// registers whose register bit K is set
+__host__ __device__ constexpr uint32_t reg_half_mask(int k)
+{
+    uint32_t m = 0;
+    for (int i = 0; i < kRbAmps; ++i)
+        if ((i >> k) & 1) m |= 1u << i;
+    return m;
+}
+
+template <typename C, typename V>
+__device__ __forceinline__ bool rb_apply_lane(V (&v)[kRbAmps], const Op& op, const C* u, uint32_t s2, uint32_t tb)
+{
+    // target bit: b[1] for CX, else b[0]
+    const uint8_t t = op.code == OP_CX ? op.b[1] : op.b[0];
+    if ((t & 0xc0u) != 0x40u) return false;
+    auto lane = [&](auto f) QK_AI {
+        if (t & 1u) f(IC<1>{});
+        else f(IC<0>{});
+    };
+    switch (op.code) {
+    case OP_DENSE1: lane([&](auto J) QK_AI { rb_lane_dense1<J.value>(v, u); }); break;
+    case OP_H: lane([&](auto J) QK_AI { rb_lane_h<J.value>(v, u); }); break;
+    case OP_X: lane([&](auto J) QK_AI { rb_lane_x<J.value>(v, 0xffffu, true); }); break;
+    case OP_XC:
+        if (s2) lane([&](auto J) QK_AI { rb_lane_x<J.value>(v, 0xffffu, true); });
+        break;
+    case OP_CX:
+        if (op.b[0] & 0x80u) {
+            const bool c = tbit(tb, op.b[0]) != 0;
+            if (__ballot(c)) lane([&](auto J) QK_AI { rb_lane_x<J.value>(v, 0xffffu, c); });
+        } else {
+            dispatch1(op.b[0], [&](auto K) QK_AI {
+                lane([&](auto J) QK_AI { rb_lane_x<J.value>(v, reg_half_mask(K.value), true); });
+            });
+        }
+        break;
+    default: break;
+    }
+    return true;
+}
+
 template <typename C, typename V>
 __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* coef, uint64_t bb, uint32_t tb)
 {
@@ -835,6 +961,7 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
     // values of the state qubits b[2], b[3] outside the block (uniform)
     const uint32_t s2 = (uint32_t)(bb >> op.b[2]) & 1u, s3 = (uint32_t)(bb >> op.b[3]) & 1u;
     const bool t0 = (op.b[0] & 0x80u) != 0, t1 = (op.b[1] & 0x80u) != 0;
+    if (rb_apply_lane(v, op, u, s2, tb)) return;
     if (op.code == OP_DIAG1 && t0) {
         rb_scale_sel(v, tbit(tb, op.b[0]), ld_coef(u), ld_coef(u + 1));
         return;
@@ -927,15 +1054,20 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
 template <int ESZ>
 __device__ __forceinline__ uint32_t lds_swz(uint32_t i) { return i ^ (((i >> 5) ^ (i >> 10)) & 31u); }
 
-// Block index of this thread's rho = 0 under register bits reg: the thread
-// index bits go, in order, to the block bits outside reg (ascending).
-__device__ __forceinline__ uint32_t thr_deposit(uint32_t t, const uint8_t* reg, int m)
+// Block index of this thread's rho = 0 in layout (reg, lx): thread-index bit
+// 4 + j goes to block bit lx[j] where that is pinned, the other thread-index
+// bits go, in order, to the remaining block bits (ascending).
+__device__ __forceinline__ uint32_t thr_deposit(uint32_t t, const uint8_t* reg, const uint8_t* lx, int m)
 {
-    const uint32_t rm = (1u << reg[0]) | (1u << reg[1]) | (1u << reg[2]) | (1u << reg[3]);
+    uint32_t used = (1u << reg[0]) | (1u << reg[1]) | (1u << reg[2]) | (1u << reg[3]);
+    if (lx[0] != kNoLane) used |= 1u << lx[0];
+    if (lx[1] != kNoLane) used |= 1u << lx[1];
     uint32_t out = 0;
     int j = 0;
     for (int q = 0; q < m; ++q) {
-        if ((rm >> q) & 1u) continue;
+        if ((used >> q) & 1u) continue;
+        if (j == 4 && lx[0] != kNoLane) out |= ((t >> j++) & 1u) << lx[0];
+        if (j == 5 && lx[1] != kNoLane) out |= ((t >> j++) & 1u) << lx[1];
         out |= ((t >> j) & 1u) << q;
         ++j;
     }
@@ -954,14 +1086,15 @@ __device__ __forceinline__ uint32_t reg_deposit(const uint8_t* reg)
 // consecutive 4-byte banks; 8- or 16-byte element accesses would pair up banks
 // and take twice the LDS cycles.
 template <typename V>
-__device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint8_t* from, const uint8_t* to, int m)
+__device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint8_t* from, const uint8_t* from_lx,
+                                              const uint8_t* to, const uint8_t* to_lx, int m)
 {
     constexpr int W = sizeof(V) / 4;             // 4-byte words per amplitude
     uint32_t* plane = reinterpret_cast<uint32_t*>(sm);
     const uint32_t P = 1u << m;                  // words per plane
     __syncthreads();   // earlier readers of the LDS block are done
     // swizzled thread part once per thread, swizzled register parts uniform
-    const uint32_t tf = lds_swz<4>(thr_deposit(threadIdx.x, from, m));
+    const uint32_t tf = lds_swz<4>(thr_deposit(threadIdx.x, from, from_lx, m));
     static_for<0, kRbAmps>([&](auto R) QK_AI {
         const uint32_t i = tf ^ lds_swz<4>(reg_deposit<R.value>(from));
         uint32_t w[W];
@@ -970,7 +1103,7 @@ __device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint
         for (int k = 0; k < W; ++k) plane[k * P + i] = w[k];
     });
     __syncthreads();
-    const uint32_t tt = lds_swz<4>(thr_deposit(threadIdx.x, to, m));
+    const uint32_t tt = lds_swz<4>(thr_deposit(threadIdx.x, to, to_lx, m));
     static_for<0, kRbAmps>([&](auto R) QK_AI {
         const uint32_t i = tt ^ lds_swz<4>(reg_deposit<R.value>(to));
         uint32_t w[W];
@@ -980,9 +1113,9 @@ __device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint
     });
 }
 
-__device__ __forceinline__ bool same_reg(const uint8_t* a, const uint8_t* b)
+__device__ __forceinline__ bool same_layout(const uint8_t* a, const uint8_t* alx, const uint8_t* b, const uint8_t* blx)
 {
-    return a[0] == b[0] && a[1] == b[1] && a[2] == b[2] && a[3] == b[3];
+    return a[0] == b[0] && a[1] == b[1] && a[2] == b[2] && a[3] == b[3] && alx[0] == blx[0] && alx[1] == blx[1];
 }
 
 // Offset of access I relative to the thread's amplitude 0: its register bits
@@ -1025,9 +1158,9 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     // default one), stores the last phase's.  Address of chunk I of this
     // thread = block base + thread part + chunk part; the chunk part is the
     // same for every thread.
-    const uint32_t tb_ld = thr_deposit(tid, d.ld_reg, m);
+    const uint32_t tb_ld = thr_deposit(tid, d.ld_reg, d.ld_lx, m);
     const uint64_t ld_t = deposit(tb_ld, d.b.act, m);
-    const uint64_t st_t = deposit(thr_deposit(tid, d.st_reg, m), d.b.act, m);
+    const uint64_t st_t = deposit(thr_deposit(tid, d.st_reg, d.st_lx, m), d.b.act, m);
     // amplitude offset of each register bit (uniform: selected with
     // compile-time indices into the active set, so it lives in scalar registers)
     uint64_t ld_b[kRbBits], st_b[kRbBits];
@@ -1087,23 +1220,39 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
             }
         });
     };
+    // Block bases inside the loop come from the run table in LDS: the loads
+    // cannot be hoisted, so the per-qubit masks of block_base do not stay
+    // live in scalar registers across the loop.
+    auto base_of = [&](uint64_t b) QK_AI {
+        const uint32_t* rw = reinterpret_cast<const uint32_t*>(prog + d.runs_off);
+        const uint32_t nr = lds_uniform(rw);
+        uint64_t o = 0;
+        for (uint32_t r = 0; r < nr; ++r) {
+            const uint32_t w = lds_uniform(rw + 1 + r);
+            o |= ((b >> (w & 0xffu)) & ((1ull << ((w >> 8) & 0xffu)) - 1)) << (w >> 16);
+        }
+        return o;
+    };
     load_all(base);
     __syncthreads();   // program in LDS
     unpack();
     for (;;) {
         const uint64_t next = blk + gridDim.x;
-        const uint64_t nbase = next < d.b.nblocks ? block_base(next, d.b.act, m) : 0;
+        const uint64_t nbase = next < d.b.nblocks ? base_of(next) : 0;
         if (next < d.b.nblocks) load_all(nbase);
         uint8_t cur[4] = {d.ld_reg[0], d.ld_reg[1], d.ld_reg[2], d.ld_reg[3]};
+        uint8_t clx[2] = {d.ld_lx[0], d.ld_lx[1]};
         uint32_t tb = tb_ld;   // block index of this thread's register 0 in layout cur
         for (int p = 0; p < d.n_phases; ++p) {
             const uint32_t* pw = reinterpret_cast<const uint32_t*>(prog + p * sizeof(Phase));
-            const uint32_t regw = lds_uniform(pw), rng = lds_uniform(pw + 1);
+            const uint32_t regw = lds_uniform(pw), lxw = lds_uniform(pw + 1), rng = lds_uniform(pw + 2);
             const uint8_t reg[4] = {(uint8_t)regw, (uint8_t)(regw >> 8), (uint8_t)(regw >> 16), (uint8_t)(regw >> 24)};
-            if (!same_reg(cur, reg) && d.uses_lds) {
-                rb_transition(sm, v, cur, reg, m);
+            const uint8_t lx[2] = {(uint8_t)lxw, (uint8_t)(lxw >> 8)};
+            if (!same_layout(cur, clx, reg, lx) && d.uses_lds) {
+                rb_transition(sm, v, cur, clx, reg, lx, m);
                 cur[0] = reg[0]; cur[1] = reg[1]; cur[2] = reg[2]; cur[3] = reg[3];
-                tb = thr_deposit(tid, cur, m);
+                clx[0] = lx[0]; clx[1] = lx[1];
+                tb = thr_deposit(tid, cur, clx, m);
             }
             for (uint32_t o = rng & 0xffffu; o < (rng >> 16); ++o) {
                 const uint32_t* ow = reinterpret_cast<const uint32_t*>(prog + d.ops_off + o * sizeof(Op));
@@ -1119,7 +1268,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
                 rb_apply(v, op, coef, base, tb);
             }
         }
-        if (!same_reg(cur, d.st_reg) && d.uses_lds) rb_transition(sm, v, cur, d.st_reg, m);
+        if (!same_layout(cur, clx, d.st_reg, d.st_lx) && d.uses_lds) rb_transition(sm, v, cur, clx, d.st_reg, d.st_lx, m);
         uint64_t s0 = base + st_t;
         asm volatile("" : "+v"(s0));
         if constexpr (CH == 2) {
@@ -1496,12 +1645,16 @@ int rb_threads(int dtype, int m)
     return m == 12 ? 256 : 0;
 }
 
-bool rb_io_friendly(int dtype, const uint8_t* reg)
+bool rb_io_friendly(int dtype, const uint8_t* reg, const uint8_t* lx)
 {
     // complex128: block bits 0..2 are lane bits.  complex64: either register
     // bit 0 is block bit 0 and block bits 1..3 are lane bits (16-byte pairs),
-    // or block bits 0..3 are all lane bits (8-byte amplitudes).
+    // or block bits 0..3 are all lane bits (8-byte amplitudes).  Lane-pinned
+    // bits sit on lane bits 4 and 5, above those groups, and must not take
+    // one of their block bits.
     const int lo = dtype == QK_C128 ? 3 : 4;
+    for (int j = 0; j < kRbLaneBits; ++j)
+        if (lx[j] != kNoLane && lx[j] < lo) return false;
     for (int k = 0; k < kRbBits; ++k) {
         if (reg[k] >= lo) continue;
         if (dtype == QK_C64 && k == 0 && reg[0] == 0) continue;
@@ -1536,7 +1689,19 @@ int launch_block_rb(int dtype, void* psi, const RbDesc& d, const void* prog, voi
 {
     hipStream_t s = (hipStream_t)stream;
     const int nt = rb_threads(dtype, d.b.m);
-    if (d.prog_bytes > kRbProgMax || d.prog_bytes % 16) return (int)hipErrorInvalidValue;
+    if (d.prog_bytes > kRbProgMax || d.prog_bytes % 16 || d.runs_off + 4 > d.prog_bytes) return (int)hipErrorInvalidValue;
+    // load and store layouts: distinct block bits below m (phase layouts are
+    // checked when the plan is built)
+    for (const uint8_t* L : {d.ld_reg, d.st_reg}) {
+        const uint8_t* lx = L == d.ld_reg ? d.ld_lx : d.st_lx;
+        uint32_t seen = 0;
+        for (int k = 0; k < kRbBits + kRbLaneBits; ++k) {
+            const uint8_t b = k < kRbBits ? L[k] : lx[k - kRbBits];
+            if (k >= kRbBits && b == kNoLane) continue;
+            if (b >= d.b.m || ((seen >> b) & 1u)) return (int)hipErrorInvalidValue;
+            seen |= 1u << b;
+        }
+    }
     if (dtype == QK_C64) {
         if (nt == 512) return launch_rb_typed<float2, 512>(psi, d, prog, s);
         if (nt == 256) return launch_rb_typed<float2, 256>(psi, d, prog, s);

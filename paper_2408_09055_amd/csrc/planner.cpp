@@ -264,6 +264,24 @@ unsigned op_reg_required(const Op& op)
     }
 }
 
+// Which required bits may instead sit on a lane-pinned bit (one-qubit gates
+// and the CX target: the kernel exchanges their pairs across lanes).
+unsigned op_lane_ok(const Op& op)
+{
+    switch (op.code) {
+    case OP_DENSE1: case OP_H: case OP_X: case OP_XC: return 1u;
+    case OP_CX: return 2u;
+    default: return 0u;
+    }
+}
+
+int lane_pos(const uint8_t* lx, int bit)
+{
+    for (int j = 0; j < kRbLaneBits; ++j)
+        if (lx[j] == bit) return j;
+    return -1;
+}
+
 int reg_pos(const uint8_t* reg, int bit)
 {
     for (int k = 0; k < kRbBits; ++k)
@@ -271,10 +289,12 @@ int reg_pos(const uint8_t* reg, int bit)
     return -1;
 }
 
-// Register-blocked form of kernel K: phases of at most kRbBits block bits.
-// A fused kernel of k <= 4 qubits is one phase whose first k register bits
-// are the kernel bits; an LDS kernel is split greedily, each new phase taking
-// the bits of as many upcoming operations as fit in four.
+// Register-blocked form of kernel K: phases of at most kRbBits register bits
+// and kRbLaneBits lane-pinned bits.  A fused kernel of k <= 4 qubits is one
+// phase whose first k register bits are the kernel bits; an LDS kernel is
+// split greedily, each new phase taking the bits of as many upcoming
+// operations as fit (bits that some operation needs in a register: at most
+// four; all bits: at most six).
 void build_rb(qk_plan* P, PKernel& K)
 {
     const int m = K.desc.m;
@@ -295,22 +315,25 @@ void build_rb(qk_plan* P, PKernel& K)
             if (reg[t] == b) return true;
         return false;
     };
-    // complete reg[0..nreg) to four bits, preferring bits that keep the
-    // layout directly loadable (above the 128-byte line), highest first
+    // complete reg[0..nreg) to four bits (none of them lane-pinned),
+    // preferring bits that keep the layout directly loadable (above the
+    // 128-byte line), highest first
     const int safe_lo = P->dtype == QK_C128 ? 3 : 4;
-    auto fill = [&](uint8_t* reg, int nreg) {
+    auto fill = [&](uint8_t* reg, int nreg, const uint8_t* lx) {
         for (int b = m - 1; b >= safe_lo && nreg < kRbBits; --b)
-            if (!has(reg, nreg, b)) reg[nreg++] = (uint8_t)b;
+            if (!has(reg, nreg, b) && lane_pos(lx, b) < 0) reg[nreg++] = (uint8_t)b;
         for (int b = 0; b < m && nreg < kRbBits; ++b)
-            if (!has(reg, nreg, b)) reg[nreg++] = (uint8_t)b;
+            if (!has(reg, nreg, b) && lane_pos(lx, b) < 0) reg[nreg++] = (uint8_t)b;
     };
+    const uint8_t no_lx[2] = {kNoLane, kNoLane};
     if (K.type == QK_KERNEL_FUSED) {
         // register bits 0..k-1 hold the kernel bits
         const Op& src = P->ops[K.op_off];
         Phase p{};
         int nreg = 0;
         for (int u = 0; u < src.k; ++u) p.reg[nreg++] = src.b[u];
-        fill(p.reg, nreg);
+        fill(p.reg, nreg, no_lx);
+        p.lx[0] = p.lx[1] = kNoLane;
         Op o = src;
         for (int u = 0; u < 7; ++u) o.b[u] = 0;
         lops.push_back(o);
@@ -319,62 +342,92 @@ void build_rb(qk_plan* P, PKernel& K)
         p.op_end = 1;
         ph.push_back(p);
     } else {
-        uint8_t cur[4];
+        uint8_t cur[4], clx[2] = {kNoLane, kNoLane};
         std::memcpy(cur, io_reg, 4);
         bool open = false;
         for (int o = 0; o < K.n_ops; ++o) {
             Op op = P->ops[K.op_off + o];
             const int nb = op_nbits(op);
-            const unsigned rq = op_reg_required(op);
-            bool fits = (!(rq & 1u) || reg_pos(cur, op.b[0]) >= 0) && (!(rq & 2u) || reg_pos(cur, op.b[1]) >= 0);
+            const unsigned rq = op_reg_required(op), lq = op_lane_ok(op);
+            bool fits = true;
+            for (int t = 0; t < 2; ++t)
+                if ((rq >> t) & 1u)
+                    fits &= reg_pos(cur, op.b[t]) >= 0 || (((lq >> t) & 1u) && lane_pos(clx, op.b[t]) >= 0);
             if (!fits) {
-                // required bits of this and the following operations while four suffice
-                uint8_t set[4];
+                // required bits of this and the following operations while
+                // they fit: the bits some operation needs in a register go to
+                // registers (at most four), the others fill the remaining
+                // registers first, then the two lane-pinned bits
+                uint8_t bits[kRbBits + kRbLaneBits];
+                bool need_reg[kRbBits + kRbLaneBits];
                 int ns = 0;
                 for (int o2 = o; o2 < K.n_ops; ++o2) {
                     const Op& q = P->ops[K.op_off + o2];
-                    const unsigned qr = op_reg_required(q);
-                    uint8_t nbits[2];
-                    int qn = 0;
-                    if (qr & 1u) nbits[qn++] = q.b[0];
-                    if (qr & 2u) nbits[qn++] = q.b[1];
-                    uint8_t tmp[4];
-                    std::memcpy(tmp, set, 4);
+                    const unsigned qr = op_reg_required(q), ql = op_lane_ok(q);
+                    uint8_t tb[kRbBits + kRbLaneBits];
+                    bool tr[kRbBits + kRbLaneBits];
+                    std::memcpy(tb, bits, sizeof(tb));
+                    std::memcpy(tr, need_reg, sizeof(tr));
                     int nt2 = ns;
-                    for (int t = 0; t < qn; ++t) {
-                        bool dup = false;
-                        for (int u = 0; u < nt2; ++u) dup |= tmp[u] == nbits[t];
-                        if (!dup) {
-                            if (nt2 == kRbBits) { nt2 = kRbBits + 1; break; }
-                            tmp[nt2++] = nbits[t];
+                    bool ok = true;
+                    for (int t = 0; t < 2 && ok; ++t) {
+                        if (!((qr >> t) & 1u)) continue;
+                        const bool nr = !((ql >> t) & 1u);
+                        int at = -1;
+                        for (int u = 0; u < nt2; ++u)
+                            if (tb[u] == q.b[t]) at = u;
+                        if (at < 0) {
+                            if (nt2 == kRbBits + kRbLaneBits) { ok = false; break; }
+                            tb[nt2] = q.b[t];
+                            tr[nt2++] = nr;
+                        } else {
+                            tr[at] = tr[at] || nr;
                         }
                     }
-                    if (nt2 > kRbBits) break;
-                    std::memcpy(set, tmp, 4);
+                    int nreg = 0;
+                    for (int u = 0; u < nt2; ++u) nreg += tr[u];
+                    if (!ok || nreg > kRbBits) break;
+                    std::memcpy(bits, tb, sizeof(tb));
+                    std::memcpy(need_reg, tr, sizeof(tr));
                     ns = nt2;
                 }
-                fill(set, ns);
+                uint8_t set[4], lx[2] = {kNoLane, kNoLane};
+                int nr = 0, nl = 0;
+                for (int u = 0; u < ns; ++u)
+                    if (need_reg[u]) set[nr++] = bits[u];
+                for (int u = 0; u < ns; ++u) {
+                    if (need_reg[u]) continue;
+                    if (nr < kRbBits) set[nr++] = bits[u];
+                    else lx[nl++] = bits[u];
+                }
+                fill(set, nr, lx);
                 std::sort(set, set + kRbBits);
+                if (lx[0] != kNoLane && lx[1] != kNoLane && lx[0] > lx[1]) std::swap(lx[0], lx[1]);
                 if (open) ph.back().op_end = (uint16_t)lops.size();
                 Phase p{};
                 std::memcpy(p.reg, set, 4);
+                std::memcpy(p.lx, lx, 2);
                 p.op_begin = (uint16_t)lops.size();
                 ph.push_back(p);
                 std::memcpy(cur, set, 4);
+                std::memcpy(clx, lx, 2);
                 open = true;
             } else if (!open) {
                 Phase p{};
                 std::memcpy(p.reg, cur, 4);
+                std::memcpy(p.lx, clx, 2);
                 p.op_begin = (uint16_t)lops.size();
                 ph.push_back(p);
                 open = true;
             }
-            // register form: a register position, or 0x80 | block bit for a
-            // bit the thread index supplies
+            // register form: a register position, 0x40 | j for a bit on lane
+            // bit 4 + j (operations that exchange across lanes), or 0x80 |
+            // block bit for a bit the thread index supplies
             Op lo = op;
             for (int t = 0; t < nb; ++t) {
                 const int rp = reg_pos(cur, op.b[t]);
-                lo.b[t] = (uint8_t)(rp >= 0 ? rp : (0x80 | op.b[t]));
+                const int lp = (((rq & lq) >> t) & 1u) ? lane_pos(clx, op.b[t]) : -1;
+                lo.b[t] = (uint8_t)(rp >= 0 ? rp : lp >= 0 ? (0x40 | lp) : (0x80 | op.b[t]));
             }
             if (op.code == OP_PHRUN) {
                 // partners held in registers leave the run as single phases
@@ -411,19 +464,32 @@ void build_rb(qk_plan* P, PKernel& K)
     // move whole lines; otherwise in the default layout, with a transition
     std::memcpy(d.ld_reg, io_reg, 4);
     std::memcpy(d.st_reg, io_reg, 4);
-    if (!ph.empty() && rb_io_friendly(P->dtype, ph.front().reg)) std::memcpy(d.ld_reg, ph.front().reg, 4);
-    if (!ph.empty() && rb_io_friendly(P->dtype, ph.back().reg)) std::memcpy(d.st_reg, ph.back().reg, 4);
+    std::memcpy(d.ld_lx, no_lx, 2);
+    std::memcpy(d.st_lx, no_lx, 2);
+    if (!ph.empty() && rb_io_friendly(P->dtype, ph.front().reg, ph.front().lx)) {
+        std::memcpy(d.ld_reg, ph.front().reg, 4);
+        std::memcpy(d.ld_lx, ph.front().lx, 2);
+    }
+    if (!ph.empty() && rb_io_friendly(P->dtype, ph.back().reg, ph.back().lx)) {
+        std::memcpy(d.st_reg, ph.back().reg, 4);
+        std::memcpy(d.st_lx, ph.back().lx, 2);
+    }
     // complex64 moves 16-byte amplitude pairs when register bit 0 is block bit 0
     d.ld_wide = (uint8_t)(P->dtype == QK_C64 && d.ld_reg[0] == 0);
     d.st_wide = (uint8_t)(P->dtype == QK_C64 && d.st_reg[0] == 0);
     // does the block change layout anywhere (then the kernel needs LDS)?
-    uint8_t cur[4];
+    uint8_t cur[4], clx[2];
     std::memcpy(cur, d.ld_reg, 4);
+    std::memcpy(clx, d.ld_lx, 2);
     int uses = 0;
     for (const Phase& p : ph) {
-        if (std::memcmp(cur, p.reg, 4) != 0) { ++uses; std::memcpy(cur, p.reg, 4); }
+        if (std::memcmp(cur, p.reg, 4) != 0 || std::memcmp(clx, p.lx, 2) != 0) {
+            ++uses;
+            std::memcpy(cur, p.reg, 4);
+            std::memcpy(clx, p.lx, 2);
+        }
     }
-    if (std::memcmp(cur, d.st_reg, 4) != 0) ++uses;
+    if (std::memcmp(cur, d.st_reg, 4) != 0 || std::memcmp(clx, d.st_lx, 2) != 0) ++uses;
     d.n_transposes = uses;
     uses = uses > 0;
     d.uses_lds = uses;
@@ -465,7 +531,35 @@ void build_rb(qk_plan* P, PKernel& K)
     }
     d.ops_off = (uint32_t)up16(ph.size() * sizeof(Phase));
     d.coef_off = d.ops_off + (uint32_t)(lops.size() * sizeof(Op));
-    const size_t bytes = up16(d.coef_off + kc.size() * csz);
+    d.runs_off = (uint32_t)up16(d.coef_off + kc.size() * csz);
+    // block-base table: the qubits outside the block in runs of consecutive
+    // qubits; block number bits fill them in ascending order
+    std::vector<uint32_t> runs;
+    {
+        bool in_act[64] = {};
+        for (int j = 0; j < m; ++j) in_act[d.b.act[j]] = true;
+        uint32_t src = 0;
+        for (int q = 0; q < d.b.n;) {
+            if (in_act[q]) { ++q; continue; }
+            int w = 0;
+            while (q + w < d.b.n && !in_act[q + w]) ++w;
+            runs.push_back(src | ((uint32_t)w << 8) | ((uint32_t)q << 16));
+            src += (uint32_t)w;
+            q += w;
+        }
+    }
+    if ((int)runs.size() > kRbMaxRuns) return;
+    // every phase layout: distinct block bits below m
+    for (const Phase& p : ph) {
+        uint32_t seen = 0;
+        for (int k = 0; k < kRbBits + kRbLaneBits; ++k) {
+            const uint8_t b = k < kRbBits ? p.reg[k] : p.lx[k - kRbBits];
+            if (k >= kRbBits && b == kNoLane) continue;
+            if (b >= m || ((seen >> b) & 1u)) return;
+            seen |= 1u << b;
+        }
+    }
+    const size_t bytes = up16(d.runs_off + 4 * (1 + runs.size()));
     if (bytes > kRbProgMax) return;   // stays on the staged-block kernels
     d.prog_bytes = (uint32_t)bytes;
     K.prog_off = (int64_t)P->rbprog.size();
@@ -482,6 +576,9 @@ void build_rb(qk_plan* P, PKernel& K)
             std::memcpy(dst + d.coef_off + t * csz, v, csz);
         }
     }
+    const uint32_t nruns = (uint32_t)runs.size();
+    std::memcpy(dst + d.runs_off, &nruns, 4);
+    std::memcpy(dst + d.runs_off + 4, runs.data(), 4 * runs.size());
     K.rb = true;
 }
 

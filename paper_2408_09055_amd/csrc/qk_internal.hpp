@@ -100,17 +100,26 @@ struct PermPairDesc {
 
 // Register-blocked execution of a staged block: every thread keeps
 // kRbAmps = 16 amplitudes in registers (kRbBits = 4 block bits); a phase is a
-// choice of those 4 bits plus the operations that act only on them.  Moving
-// between phases transposes the block through LDS.
+// choice of those 4 bits, of up to kRbLaneBits block bits on lane bits 4 and 5
+// (one-qubit gates there exchange amplitudes across lanes), and the
+// operations that act only on them.  Moving between phases transposes the
+// block through LDS.
 constexpr int kRbBits = 4;
 constexpr int kRbAmps = 1 << kRbBits;
+constexpr int kRbLaneBits = 2;
+constexpr uint8_t kNoLane = 0xff;
 
+// Layout of a block in a workgroup: register bit k <-> block bit reg[k];
+// thread-index bit 4 + j <-> block bit lx[j] (kNoLane: not pinned); the other
+// thread-index bits take the remaining block bits in ascending order.
 struct Phase {
-    uint8_t reg[4];      // block bits held in registers: register bit k <-> reg[k]
+    uint8_t reg[4];      // block bits held in registers
+    uint8_t lx[2];       // block bits pinned to lane bits 4 and 5
+    uint8_t pad[2];
     uint16_t op_begin;   // operations [op_begin, op_end) of the kernel's slice,
-    uint16_t op_end;     // with bits given as register positions 0..3
+    uint16_t op_end;     // with bits in register form
 };
-static_assert(sizeof(Phase) == 8, "Phase layout");
+static_assert(sizeof(Phase) == 12, "Phase layout");
 
 struct RbDesc {
     BlockDesc b;         // block geometry (act, ell0, m, nblocks)
@@ -126,8 +135,15 @@ struct RbDesc {
     // needs register bit 0 = block bit 0; 0 = single 8-byte amplitudes
     uint8_t ld_wide, st_wide, pad[2];
     int32_t n_transposes;   // layout changes per block (host statistics)
-    int32_t pad2;
+    uint8_t ld_lx[2];       // lane-pinned block bits of the load layout
+    uint8_t st_lx[2];       // lane-pinned block bits of the store layout
+    // offset in the program of the block-base table: a count, then one word
+    // per run of consecutive qubits outside the block (source bit of the
+    // block number | width << 8 | first qubit << 16)
+    uint32_t runs_off;
+    uint32_t pad3;
 };
+constexpr int kRbMaxRuns = 17;
 // Largest program a register-blocked kernel stages in LDS.
 constexpr uint32_t kRbProgMax = 16384;
 
@@ -139,7 +155,7 @@ void rb_io_reg(int dtype, int threads, uint8_t* reg);
 // True when a phase layout with these register bits can be loaded or stored
 // directly: every group of consecutive lanes then moves whole 128-byte lines
 // (complex64: 8 lanes of 16-byte pairs or 16 lanes of 8-byte amplitudes).
-bool rb_io_friendly(int dtype, const uint8_t* reg);
+bool rb_io_friendly(int dtype, const uint8_t* reg, const uint8_t* lx);
 
 
 // ---------------------------------------------------------------- launchers
