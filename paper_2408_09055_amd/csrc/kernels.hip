@@ -1085,16 +1085,39 @@ __device__ __forceinline__ uint32_t reg_deposit(const uint8_t* reg)
 // an imaginary plane, complex128 as four planes.  Consecutive lanes then touch
 // consecutive 4-byte banks; 8- or 16-byte element accesses would pair up banks
 // and take twice the LDS cycles.
+// Uniform copy of an LDS word (every lane reads the same address), so that
+// decisions on it are scalar branches.
+__device__ __forceinline__ uint32_t lds_uniform(const uint32_t* p) { return __builtin_amdgcn_readfirstlane(*p); }
+
+// Block index of thread t's register-0 amplitude in a layout given by its
+// thread-index bit map (uniform words tw[0..2] of a phase record in LDS):
+// two vector instructions per thread-index bit.
+template <int NT>
+__device__ __forceinline__ uint32_t thr_map(uint32_t t, const uint32_t* tw)
+{
+    constexpr int NB = NT == 512 ? 9 : 8;
+    const uint32_t w0 = lds_uniform(tw), w1 = lds_uniform(tw + 1), w2 = lds_uniform(tw + 2);
+    uint32_t out = 0;
+    static_for<0, NB>([&](auto J) QK_AI {
+        const uint32_t w = J.value < 4 ? w0 : J.value < 8 ? w1 : w2;
+        const uint32_t pos = (w >> (8 * (J.value & 3))) & 0xffu;
+        out |= ((t >> J.value) & 1u) << pos;
+    });
+    return out;
+}
+
+// Move the block from layout `from` to layout `to`; tb_from / tb_to are the
+// block indices of this thread's register-0 amplitude in each.
 template <typename V>
-__device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint8_t* from, const uint8_t* from_lx,
-                                              const uint8_t* to, const uint8_t* to_lx, int m)
+__device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], uint32_t tb_from, const uint8_t* from,
+                                              uint32_t tb_to, const uint8_t* to, int m)
 {
     constexpr int W = sizeof(V) / 4;             // 4-byte words per amplitude
     uint32_t* plane = reinterpret_cast<uint32_t*>(sm);
     const uint32_t P = 1u << m;                  // words per plane
     __syncthreads();   // earlier readers of the LDS block are done
     // swizzled thread part once per thread, swizzled register parts uniform
-    const uint32_t tf = lds_swz<4>(thr_deposit(threadIdx.x, from, from_lx, m));
+    const uint32_t tf = lds_swz<4>(tb_from);
     static_for<0, kRbAmps>([&](auto R) QK_AI {
         const uint32_t i = tf ^ lds_swz<4>(reg_deposit<R.value>(from));
         uint32_t w[W];
@@ -1103,7 +1126,7 @@ __device__ __forceinline__ void rb_transition(V* sm, V (&v)[kRbAmps], const uint
         for (int k = 0; k < W; ++k) plane[k * P + i] = w[k];
     });
     __syncthreads();
-    const uint32_t tt = lds_swz<4>(thr_deposit(threadIdx.x, to, to_lx, m));
+    const uint32_t tt = lds_swz<4>(tb_to);
     static_for<0, kRbAmps>([&](auto R) QK_AI {
         const uint32_t i = tt ^ lds_swz<4>(reg_deposit<R.value>(to));
         uint32_t w[W];
@@ -1130,9 +1153,6 @@ __device__ __forceinline__ uint64_t chunk_offset(int I, const uint64_t* rb)
 
 // Occupancy target: two workgroups of 512 (complex64) or 256 (complex128)
 // threads per compute unit, i.e. 4 or 2 waves per SIMD.
-// Uniform copy of an LDS word (every lane reads the same address), so that
-// decisions on it are scalar branches.
-__device__ __forceinline__ uint32_t lds_uniform(const uint32_t* p) { return __builtin_amdgcn_readfirstlane(*p); }
 
 template <typename C, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(C) == 8 ? 4 : 2)))
@@ -1144,8 +1164,17 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     // LDS: the kernel's program, then (when the layout changes) the block.
     // Reading the program from LDS keeps the loop free of vector-memory loads,
     // so waiting on one never waits for the next block's prefetch.
+    // LDS: the program, this thread's address offsets in the load and store
+    // layouts (kept in LDS, not registers), then the block
     const uint8_t* prog = smem;
-    V* sm = reinterpret_cast<V*>(smem + d.prog_bytes);
+    // this thread's offsets: the address is formed from the thread index at
+    // each use (the empty asm keeps it from being hoisted into a register)
+    auto offs = [&]() QK_AI {
+        uint32_t t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        return reinterpret_cast<uint64_t*>(smem + d.prog_bytes) + 2 * t;
+    };
+    V* sm = reinterpret_cast<V*>(smem + d.prog_bytes + NT * 16);
     const C* coef = reinterpret_cast<const C*>(smem + d.coef_off);
     constexpr int CH = 16 / sizeof(C);              // amplitudes per 16-byte access
     const int m = d.b.m;
@@ -1158,9 +1187,13 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     // default one), stores the last phase's.  Address of chunk I of this
     // thread = block base + thread part + chunk part; the chunk part is the
     // same for every thread.
-    const uint32_t tb_ld = thr_deposit(tid, d.ld_reg, d.ld_lx, m);
-    const uint64_t ld_t = deposit(tb_ld, d.b.act, m);
-    const uint64_t st_t = deposit(thr_deposit(tid, d.st_reg, d.st_lx, m), d.b.act, m);
+    {
+        uint64_t* o = offs();
+        o[0] = deposit(thr_deposit(tid, d.ld_reg, d.ld_lx, m), d.b.act, m);
+        o[1] = deposit(thr_deposit(tid, d.st_reg, d.st_lx, m), d.b.act, m);
+    }
+    // record of the load layout (after the phases and the store layout)
+    const uint32_t* ldw = reinterpret_cast<const uint32_t*>(prog + (d.n_phases + 1) * sizeof(Phase));
     // amplitude offset of each register bit (uniform: selected with
     // compile-time indices into the active set, so it lives in scalar registers)
     uint64_t ld_b[kRbBits], st_b[kRbBits];
@@ -1185,7 +1218,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     // offsets at each access instead of keeping 16 precomputed 64-bit
     // addresses live.
     auto load_all = [&](uint64_t b) {
-        uint64_t b0 = b + ld_t;
+        uint64_t b0 = b + offs()[0];
         asm volatile("" : "+v"(b0));
         if constexpr (CH == 2) {
             if (d.ld_wide) {
@@ -1242,17 +1275,18 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
         if (next < d.b.nblocks) load_all(nbase);
         uint8_t cur[4] = {d.ld_reg[0], d.ld_reg[1], d.ld_reg[2], d.ld_reg[3]};
         uint8_t clx[2] = {d.ld_lx[0], d.ld_lx[1]};
-        uint32_t tb = tb_ld;   // block index of this thread's register 0 in layout cur
+        uint32_t tb = thr_map<NT>(tid, ldw + 3);   // block index of this thread's register 0 in layout cur
         for (int p = 0; p < d.n_phases; ++p) {
             const uint32_t* pw = reinterpret_cast<const uint32_t*>(prog + p * sizeof(Phase));
             const uint32_t regw = lds_uniform(pw), lxw = lds_uniform(pw + 1), rng = lds_uniform(pw + 2);
             const uint8_t reg[4] = {(uint8_t)regw, (uint8_t)(regw >> 8), (uint8_t)(regw >> 16), (uint8_t)(regw >> 24)};
             const uint8_t lx[2] = {(uint8_t)lxw, (uint8_t)(lxw >> 8)};
             if (!same_layout(cur, clx, reg, lx) && d.uses_lds) {
-                rb_transition(sm, v, cur, clx, reg, lx, m);
+                const uint32_t tb_to = thr_map<NT>(tid, pw + 3);
+                rb_transition(sm, v, tb, cur, tb_to, reg, m);
                 cur[0] = reg[0]; cur[1] = reg[1]; cur[2] = reg[2]; cur[3] = reg[3];
                 clx[0] = lx[0]; clx[1] = lx[1];
-                tb = thr_deposit(tid, cur, clx, m);
+                tb = tb_to;
             }
             for (uint32_t o = rng & 0xffffu; o < (rng >> 16); ++o) {
                 const uint32_t* ow = reinterpret_cast<const uint32_t*>(prog + d.ops_off + o * sizeof(Op));
@@ -1268,8 +1302,12 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
                 rb_apply(v, op, coef, base, tb);
             }
         }
-        if (!same_layout(cur, clx, d.st_reg, d.st_lx) && d.uses_lds) rb_transition(sm, v, cur, clx, d.st_reg, d.st_lx, m);
-        uint64_t s0 = base + st_t;
+        if (!same_layout(cur, clx, d.st_reg, d.st_lx) && d.uses_lds) {
+            // the store layout's record follows the phases
+            const uint32_t* sw = reinterpret_cast<const uint32_t*>(prog + d.n_phases * sizeof(Phase));
+            rb_transition(sm, v, tb, cur, thr_map<NT>(tid, sw + 3), d.st_reg, m);
+        }
+        uint64_t s0 = base + offs()[1];
         asm volatile("" : "+v"(s0));
         if constexpr (CH == 2) {
             if (d.st_wide) {
@@ -1677,7 +1715,7 @@ void rb_io_reg(int dtype, int threads, uint8_t* reg)
 template <typename C, int NT>
 int launch_rb_typed(void* psi, const RbDesc& d, const void* prog, hipStream_t s)
 {
-    const size_t lds = d.prog_bytes + (d.uses_lds ? ((size_t)sizeof(C) << d.b.m) : 0);
+    const size_t lds = d.prog_bytes + (size_t)NT * 16 + (d.uses_lds ? ((size_t)sizeof(C) << d.b.m) : 0);
     auto f = k_block_rb<C, NT>;
     const uint64_t res = resident_groups(reinterpret_cast<const void*>(f), lds, NT);
     const dim3 grid((uint32_t)std::min<uint64_t>(d.b.nblocks, res)), block(NT);

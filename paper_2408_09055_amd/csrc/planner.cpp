@@ -529,6 +529,34 @@ void build_rb(qk_plan* P, PKernel& K)
         for (int t = 0; t < cnt; ++t) kc.push_back(P->coefs[o.coef + t]);
         o.coef = cnt ? first : 0;
     }
+    // thread-index bit maps of every phase layout, then records of the store
+    // and the load layouts
+    {
+        Phase st{}, ld{};
+        std::memcpy(st.reg, d.st_reg, 4);
+        std::memcpy(st.lx, d.st_lx, 2);
+        st.op_begin = st.op_end = (uint16_t)lops.size();
+        ph.push_back(st);
+        std::memcpy(ld.reg, d.ld_reg, 4);
+        std::memcpy(ld.lx, d.ld_lx, 2);
+        ld.op_begin = ld.op_end = (uint16_t)lops.size();
+        ph.push_back(ld);
+        const int tbits = nt == 512 ? 9 : 8;
+        for (Phase& p : ph) {
+            uint32_t used = 0;
+            for (int k = 0; k < kRbBits; ++k) used |= 1u << p.reg[k];
+            for (int j = 0; j < kRbLaneBits; ++j)
+                if (p.lx[j] != kNoLane) used |= 1u << p.lx[j];
+            int j = 0;
+            for (int q = 0; q < m && j < tbits; ++q) {
+                if ((used >> q) & 1u) continue;
+                if (j == 4 && p.lx[0] != kNoLane) p.tmap[j++] = p.lx[0];
+                if (j == 5 && p.lx[1] != kNoLane) p.tmap[j++] = p.lx[1];
+                p.tmap[j++] = (uint8_t)q;
+            }
+            if (j != tbits) return;   // not a layout of this block size
+        }
+    }
     d.ops_off = (uint32_t)up16(ph.size() * sizeof(Phase));
     d.coef_off = d.ops_off + (uint32_t)(lops.size() * sizeof(Op));
     d.runs_off = (uint32_t)up16(d.coef_off + kc.size() * csz);

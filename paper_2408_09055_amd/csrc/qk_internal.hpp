@@ -118,8 +118,9 @@ struct Phase {
     uint8_t pad[2];
     uint16_t op_begin;   // operations [op_begin, op_end) of the kernel's slice,
     uint16_t op_end;     // with bits in register form
+    uint8_t tmap[12];    // thread-index bit j -> block bit tmap[j] (j < log2 threads)
 };
-static_assert(sizeof(Phase) == 12, "Phase layout");
+static_assert(sizeof(Phase) == 24, "Phase layout");
 
 struct RbDesc {
     BlockDesc b;         // block geometry (act, ell0, m, nblocks)
@@ -127,7 +128,8 @@ struct RbDesc {
     int32_t uses_lds;    // 1 if the block changes layout through LDS
     uint8_t ld_reg[4];   // register bits of the HBM load layout
     uint8_t st_reg[4];   // register bits of the HBM store layout
-    // the kernel's program, copied to LDS at launch: n_phases Phase records,
+    // the kernel's program, copied to LDS at launch: n_phases Phase records
+    // and two more holding the store and the load layouts (no operations),
     // then (at ops_off) the operations in register form, then (at coef_off)
     // their coefficients in the state's precision; prog_bytes in total
     uint32_t prog_bytes, ops_off, coef_off;
