@@ -606,8 +606,8 @@ struct Cx {
 template <typename C>
 using CxOf = Cx<typename Real<C>::T>;
 
-// A coefficient of the kernel's program (in LDS, the same for every lane),
-// moved to scalar registers so that it costs no vector registers while used.
+// A coefficient of the kernel's program (the same for every lane), moved to
+// scalar registers so that it costs no vector registers while used.
 __device__ __forceinline__ float uniform_real(float x) { return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x))); }
 __device__ __forceinline__ double uniform_real(double x)
 {
@@ -1085,12 +1085,12 @@ __device__ __forceinline__ uint32_t reg_deposit(const uint8_t* reg)
 // an imaginary plane, complex128 as four planes.  Consecutive lanes then touch
 // consecutive 4-byte banks; 8- or 16-byte element accesses would pair up banks
 // and take twice the LDS cycles.
-// Uniform copy of an LDS word (every lane reads the same address), so that
-// decisions on it are scalar branches.
+// Uniform copy of a program word (every lane reads the same address), so
+// that decisions on it are scalar branches.
 __device__ __forceinline__ uint32_t lds_uniform(const uint32_t* p) { return __builtin_amdgcn_readfirstlane(*p); }
 
 // Block index of thread t's register-0 amplitude in a layout given by its
-// thread-index bit map (uniform words tw[0..2] of a phase record in LDS):
+// thread-index bit map (uniform words tw[0..2] of a phase record):
 // two vector instructions per thread-index bit.
 template <int NT>
 __device__ __forceinline__ uint32_t thr_map(uint32_t t, const uint32_t* tw)
@@ -1161,12 +1161,16 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     using V = CxOf<C>;
     using R = typename Real<C>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    // LDS: the kernel's program, then (when the layout changes) the block.
-    // Reading the program from LDS keeps the loop free of vector-memory loads,
-    // so waiting on one never waits for the next block's prefetch.
-    // LDS: the program, this thread's address offsets in the load and store
-    // layouts (kept in LDS, not registers), then the block
+    // LDS: the kernel's program, this thread's address offsets in the load
+    // and store layouts (kept in LDS, not registers), then (when the layout
+    // changes) the block.  Phase records and the block-base table are read
+    // from the LDS copy (loads that cannot be hoisted out of the block loop
+    // into scalar registers); operations and coefficients are read from the
+    // global copy with scalar loads, which land in scalar registers without
+    // vector instructions and are counted apart from vector-memory loads, so
+    // waiting on them never waits for the next block's prefetch.
     const uint8_t* prog = smem;
+    const uint8_t* gops = gprog + d.ops_off;
     // this thread's offsets: the address is formed from the thread index at
     // each use (the empty asm keeps it from being hoisted into a register)
     auto offs = [&]() QK_AI {
@@ -1175,7 +1179,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
         return reinterpret_cast<uint64_t*>(smem + d.prog_bytes) + 2 * t;
     };
     V* sm = reinterpret_cast<V*>(smem + d.prog_bytes + NT * 16);
-    const C* coef = reinterpret_cast<const C*>(smem + d.coef_off);
+    const C* coef = reinterpret_cast<const C*>(gprog + d.coef_off);
     constexpr int CH = 16 / sizeof(C);              // amplitudes per 16-byte access
     const int m = d.b.m;
     const int tid = threadIdx.x;
@@ -1289,7 +1293,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
                 tb = tb_to;
             }
             for (uint32_t o = rng & 0xffffu; o < (rng >> 16); ++o) {
-                const uint32_t* ow = reinterpret_cast<const uint32_t*>(prog + d.ops_off + o * sizeof(Op));
+                const uint32_t* ow = reinterpret_cast<const uint32_t*>(gops + o * sizeof(Op));
                 const uint32_t w0 = lds_uniform(ow), w1 = lds_uniform(ow + 1);
                 Op op{};
                 op.code = (uint8_t)w0;

@@ -179,10 +179,11 @@ void segment_features(const CGate* g, int count, int n, int type, int dtype, boo
     f[16] = (float)n;
     f[17] = dtype == QK_C128 ? 1.0f : 0.0f;
     f[18] = (float)k * f[14];
-    // LDS kernels: register phases beyond the first (four register bits per
-    // phase; each further phase costs an LDS transpose of the block)
+    // LDS kernels: register phases beyond the first (six gate bits per
+    // phase: four register bits and two lane-pinned bits; each further phase
+    // costs an LDS transpose of the block)
     const int kr = popcount64(regq);
-    f[19] = type == QK_KERNEL_LDS ? (float)std::max(0, (kr + 3) / 4 - 1) : 0.0f;
+    f[19] = type == QK_KERNEL_LDS ? (float)std::max(0, (kr + 5) / 6 - 1) : 0.0f;
 }
 
 // ------------------------------------------------------------------ kernelize
