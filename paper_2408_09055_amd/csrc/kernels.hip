@@ -816,6 +816,25 @@ __device__ __forceinline__ void rb_mul_half(V (&v)[kRbAmps], const V f)
     });
 }
 
+// negate x where the sign mask sm (0 or the sign bit) is set: one XOR per
+// 32-bit word that holds a sign
+__device__ __forceinline__ float neg_if(float x, uint32_t sm) { return __uint_as_float(__float_as_uint(x) ^ sm); }
+__device__ __forceinline__ double neg_if(double x, uint32_t sm)
+{
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, x) ^ ((uint64_t)sm << 32));
+}
+
+// amplitudes selected by SEL (bit i <-> register i) negated where c is set
+// (CZ with thread-index bits)
+template <uint32_t SEL, typename V>
+__device__ __forceinline__ void rb_neg_sel(V (&v)[kRbAmps], uint32_t c)
+{
+    const uint32_t sm = c ? 0x80000000u : 0u;
+    static_for<0, kRbAmps>([&](auto I) QK_AI {
+        if constexpr (((SEL >> I.value) & 1u) != 0) v[I.value] = V{neg_if(v[I.value].x, sm), neg_if(v[I.value].y, sm)};
+    });
+}
+
 // swap the halves of register bit K where c is set (CX with a thread-bit control)
 template <int K, typename V>
 __device__ __forceinline__ void rb_cswap(V (&v)[kRbAmps], uint32_t c)
@@ -828,15 +847,30 @@ __device__ __forceinline__ void rb_cswap(V (&v)[kRbAmps], uint32_t c)
     });
 }
 
-// Operations on a lane-pinned bit (register-form code 0x40 | j: the block bit
-// on lane bit 4 + j).  v_permlane16_swap / v_permlane32_swap with both
-// operands equal hand every lane the two amplitudes of its pair: the first
-// result holds the amplitude whose lane bit is clear, the second the one
-// whose lane bit is set.  A one-qubit gate then needs no LDS and no barrier.
+// Operations on a block bit held by lane bit j of the wave (register-form
+// code 0x40 | j, j = 0..5).  For j = 4, 5, v_permlane16_swap /
+// v_permlane32_swap with both operands equal hand every lane the two
+// amplitudes of its pair: the first result holds the amplitude whose lane bit
+// is clear, the second the one whose lane bit is set.  For j = 0..3 a DPP move
+// fetches the partner lane's value (lane l ^ 2^j): quad permutations for bits
+// 0 and 1, a half-row mirror after a quad reversal for bit 2 (l ^ 3 ^ 7), a
+// row rotation by 8 for bit 3.  A one-qubit gate then needs no LDS and no
+// barrier.
+template <int J>
+__device__ __forceinline__ uint32_t dpp_partner(uint32_t x)
+{
+    const int xi = (int)x;
+    if constexpr (J == 0) return (uint32_t)__builtin_amdgcn_mov_dpp(xi, 0xB1, 0xF, 0xF, true);
+    else if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(xi, 0x4E, 0xF, 0xF, true);
+    else if constexpr (J == 2)
+        return (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(xi, 0x1B, 0xF, 0xF, true), 0x141, 0xF, 0xF, true);
+    else return (uint32_t)__builtin_amdgcn_mov_dpp(xi, 0x128, 0xF, 0xF, true);
+}
+
 template <int J>
 __device__ __forceinline__ void lane_pair_u32(uint32_t x, uint32_t& lo, uint32_t& hi)
 {
-    if constexpr (J == 0) {
+    if constexpr (J == 4) {
         const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
         lo = r[0];
         hi = r[1];
@@ -847,6 +881,7 @@ __device__ __forceinline__ void lane_pair_u32(uint32_t x, uint32_t& lo, uint32_t
     }
 }
 
+// J = 4, 5: both amplitudes of the pair (x0: lane bit clear, x1: set)
 template <int J, typename V>
 __device__ __forceinline__ void lane_pair(const V& x, V& x0, V& x1)
 {
@@ -866,24 +901,54 @@ __device__ __forceinline__ void lane_pair(const V& x, V& x0, V& x1)
     __builtin_memcpy(&x1.y, b1, sizeof(R));
 }
 
-// this lane's value of lane bit 4 + J
-template <int J>
-__device__ __forceinline__ bool lane_hi() { return (threadIdx.x >> (4 + J)) & 1u; }
+// J = 0..3: the partner lane's amplitude
+template <int J, typename V>
+__device__ __forceinline__ V lane_partner(const V& x)
+{
+    using R = decltype(x.x);
+    constexpr int W = sizeof(R) / 4;
+    uint32_t a[W], b[W];
+    __builtin_memcpy(a, &x.x, sizeof(R));
+    __builtin_memcpy(b, &x.y, sizeof(R));
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        a[k] = dpp_partner<J>(a[k]);
+        b[k] = dpp_partner<J>(b[k]);
+    }
+    V y;
+    __builtin_memcpy(&y.x, a, sizeof(R));
+    __builtin_memcpy(&y.y, b, sizeof(R));
+    return y;
+}
 
-// 2x2 matrix on lane bit 4 + J: the lane computes its own row
+// this lane's value of lane bit J
+template <int J>
+__device__ __forceinline__ bool lane_hi() { return (threadIdx.x >> J) & 1u; }
+
+// 2x2 matrix on lane bit J: the lane computes its own row
 template <int J, typename C, typename V>
 __device__ __forceinline__ void rb_lane_dense1(V (&v)[kRbAmps], const C* __restrict__ u)
 {
     const bool hi = lane_hi<J>();
-    const V p = vsel(hi, ld_coef(u + 2), ld_coef(u)), q = vsel(hi, ld_coef(u + 3), ld_coef(u + 1));
-    static_for<0, kRbAmps>([&](auto I) QK_AI {
-        V x0, x1;
-        lane_pair<J>(v[I.value], x0, x1);
-        v[I.value] = cmadd(q, x1, cmul(p, x0));
-    });
+    if constexpr (J >= 4) {
+        // row coefficients on (x0, x1)
+        const V p = vsel(hi, ld_coef(u + 2), ld_coef(u)), q = vsel(hi, ld_coef(u + 3), ld_coef(u + 1));
+        static_for<0, kRbAmps>([&](auto I) QK_AI {
+            V x0, x1;
+            lane_pair<J>(v[I.value], x0, x1);
+            v[I.value] = cmadd(q, x1, cmul(p, x0));
+        });
+    } else {
+        // row coefficients on (own, partner)
+        const V a = vsel(hi, ld_coef(u + 3), ld_coef(u)), b = vsel(hi, ld_coef(u + 2), ld_coef(u + 1));
+        static_for<0, kRbAmps>([&](auto I) QK_AI {
+            const V y = lane_partner<J>(v[I.value]);
+            v[I.value] = cmadd(b, y, cmul(a, v[I.value]));
+        });
+    }
 }
 
-// Hadamard on lane bit 4 + J: (x0 +- x1) * coef[0]
+// Hadamard on lane bit J: (x0 +- x1) * coef[0]
 template <int J, typename C, typename V>
 __device__ __forceinline__ void rb_lane_h(V (&v)[kRbAmps], const C* __restrict__ u)
 {
@@ -891,14 +956,20 @@ __device__ __forceinline__ void rb_lane_h(V (&v)[kRbAmps], const C* __restrict__
     const R s = uniform_real(u[0].x);
     const R sg = lane_hi<J>() ? R(-1) : R(1);
     static_for<0, kRbAmps>([&](auto I) QK_AI {
-        V x0, x1;
-        lane_pair<J>(v[I.value], x0, x1);
-        v[I.value] = V{(x0.x + sg * x1.x) * s, (x0.y + sg * x1.y) * s};
+        if constexpr (J >= 4) {
+            V x0, x1;
+            lane_pair<J>(v[I.value], x0, x1);
+            v[I.value] = V{(x0.x + sg * x1.x) * s, (x0.y + sg * x1.y) * s};
+        } else {
+            // lane bit clear: own + partner; set: partner - own
+            const V y = lane_partner<J>(v[I.value]);
+            v[I.value] = V{(y.x + sg * v[I.value].x) * s, (y.y + sg * v[I.value].y) * s};
+        }
     });
 }
 
-// X on lane bit 4 + J for the registers selected by SEL (bit i <-> register
-// i) where the per-lane condition c holds: each such amplitude takes its
+// X on lane bit J for the registers selected by SEL (bit i <-> register i)
+// where the per-lane condition c holds: each such amplitude takes its
 // partner's value
 template <int J, typename V>
 __device__ __forceinline__ void rb_lane_x(V (&v)[kRbAmps], uint32_t sel, bool c)
@@ -906,9 +977,13 @@ __device__ __forceinline__ void rb_lane_x(V (&v)[kRbAmps], uint32_t sel, bool c)
     const bool hi = lane_hi<J>();
     static_for<0, kRbAmps>([&](auto I) QK_AI {
         if ((sel >> I.value) & 1u) {
-            V x0, x1;
-            lane_pair<J>(v[I.value], x0, x1);
-            v[I.value] = vsel(c, hi ? x0 : x1, v[I.value]);
+            if constexpr (J >= 4) {
+                V x0, x1;
+                lane_pair<J>(v[I.value], x0, x1);
+                v[I.value] = vsel(c, hi ? x0 : x1, v[I.value]);
+            } else {
+                v[I.value] = vsel(c, lane_partner<J>(v[I.value]), v[I.value]);
+            }
         }
     });
 }
@@ -929,8 +1004,14 @@ __device__ __forceinline__ bool rb_apply_lane(V (&v)[kRbAmps], const Op& op, con
     const uint8_t t = op.code == OP_CX ? op.b[1] : op.b[0];
     if ((t & 0xc0u) != 0x40u) return false;
     auto lane = [&](auto f) QK_AI {
-        if (t & 1u) f(IC<1>{});
-        else f(IC<0>{});
+        switch (t & 7u) {
+        case 0: f(IC<0>{}); break;
+        case 1: f(IC<1>{}); break;
+        case 2: f(IC<2>{}); break;
+        case 3: f(IC<3>{}); break;
+        case 4: f(IC<4>{}); break;
+        default: f(IC<5>{}); break;
+        }
     };
     switch (op.code) {
     case OP_DENSE1: lane([&](auto J) QK_AI { rb_lane_dense1<J.value>(v, u); }); break;
@@ -968,6 +1049,16 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
     }
     if (op.code == OP_DIAG1C && t0) {
         rb_scale_sel(v, tbit(tb, op.b[0]), ld_coef(u + 2 * s2), ld_coef(u + 2 * s2 + 1));
+        return;
+    }
+    if (op.code == OP_CZ && (t0 || t1)) {
+        if (t0 && t1) {
+            const uint32_t c = tbit(tb, op.b[0]) & tbit(tb, op.b[1]);
+            if (__ballot(c)) rb_neg_sel<0xffffu>(v, c);
+        } else {
+            const uint32_t c = tbit(tb, t0 ? op.b[0] : op.b[1]);
+            dispatch1(t0 ? op.b[1] : op.b[0], [&](auto K) QK_AI { rb_neg_sel<reg_half_mask(K.value)>(v, c); });
+        }
         return;
     }
     if ((op.code == OP_CZ || op.code == OP_CPHASE) && (t0 || t1)) {

@@ -283,6 +283,86 @@ int lane_pos(const uint8_t* lx, int bit)
     return -1;
 }
 
+// Thread-index bit map of layout (reg, lx) for a block of m bits: thread bit
+// 4 + j takes lx[j] where that is pinned, the other thread bits take the
+// remaining block bits in ascending order.  Returns the number of thread bits
+// filled (at most tbits).
+int layout_tmap(const uint8_t* reg, const uint8_t* lx, int m, int tbits, uint8_t* tmap)
+{
+    uint32_t used = 0;
+    for (int k = 0; k < kRbBits; ++k) used |= 1u << reg[k];
+    for (int j = 0; j < kRbLaneBits; ++j)
+        if (lx[j] != kNoLane) used |= 1u << lx[j];
+    int j = 0;
+    for (int q = 0; q < m && j < tbits; ++q) {
+        if ((used >> q) & 1u) continue;
+        if (j == 4 && lx[0] != kNoLane) tmap[j++] = lx[0];
+        if (j == 5 && lx[1] != kNoLane) tmap[j++] = lx[1];
+        if (j < tbits) tmap[j++] = (uint8_t)q;
+    }
+    return j;
+}
+
+// Lane bit (0..5) that holds block bit b in layout (reg, lx), or -1.
+int lane_of(const uint8_t* reg, const uint8_t* lx, int m, int b)
+{
+    uint8_t tm[16];
+    const int n = layout_tmap(reg, lx, m, 6, tm);
+    for (int j = 0; j < n; ++j)
+        if (tm[j] == b) return j;
+    return -1;
+}
+
+// A layout for a phase whose operations need bits[0..ns): need_reg[u] marks
+// a bit that some operation needs in a register, the others may also sit on
+// lane bits.  Registers take the register-only bits; the other bits stay on
+// lane bits 0..3 when they are among the four lowest block bits outside the
+// registers, else go to the remaining registers (highest first), and at most
+// two more are pinned to lane bits 4 and 5.  The registers are completed by
+// fill().  Returns false when the bits do not fit.
+template <typename Fill>
+bool make_layout(const uint8_t* bits, const bool* need_reg, int ns, int m, Fill fill, uint8_t* reg_out,
+                 uint8_t* lx_out)
+{
+    uint8_t reg[kRbBits];
+    int nr = 0;
+    auto in_reg = [&](int b) {
+        for (int k = 0; k < nr; ++k)
+            if (reg[k] == b) return true;
+        return false;
+    };
+    for (int u = 0; u < ns; ++u) {
+        if (!need_reg[u]) continue;
+        if (nr == kRbBits) return false;
+        reg[nr++] = bits[u];
+    }
+    for (;;) {
+        uint32_t low4 = 0;
+        for (int b = 0, c = 0; b < m && c < 4; ++b)
+            if (!in_reg(b)) { low4 |= 1u << b; ++c; }
+        uint8_t out[16];
+        int no = 0;
+        for (int u = 0; u < ns; ++u)
+            if (!need_reg[u] && !in_reg(bits[u]) && !((low4 >> bits[u]) & 1u)) out[no++] = bits[u];
+        if (no <= kRbLaneBits) {
+            uint8_t lx[2] = {kNoLane, kNoLane};
+            for (int t = 0; t < no; ++t) lx[t] = out[t];
+            if (no == 2 && lx[0] > lx[1]) std::swap(lx[0], lx[1]);
+            fill(reg, nr, lx);
+            std::sort(reg, reg + kRbBits);
+            std::memcpy(reg_out, reg, kRbBits);
+            std::memcpy(lx_out, lx, 2);
+            return true;
+        }
+        if (nr == kRbBits) return false;
+        // the highest of the bits that do not fit on lanes goes to a register
+        int hi = 0;
+        for (int t = 1; t < no; ++t)
+            if (out[t] > out[hi]) hi = t;
+        reg[nr++] = out[hi];
+    }
+}
+
 int reg_pos(const uint8_t* reg, int bit)
 {
     for (int k = 0; k < kRbBits; ++k)
@@ -353,20 +433,20 @@ void build_rb(qk_plan* P, PKernel& K)
             bool fits = true;
             for (int t = 0; t < 2; ++t)
                 if ((rq >> t) & 1u)
-                    fits &= reg_pos(cur, op.b[t]) >= 0 || (((lq >> t) & 1u) && lane_pos(clx, op.b[t]) >= 0);
+                    fits &= reg_pos(cur, op.b[t]) >= 0 || (((lq >> t) & 1u) && lane_of(cur, clx, m, op.b[t]) >= 0);
             if (!fits) {
-                // required bits of this and the following operations while
-                // they fit: the bits some operation needs in a register go to
-                // registers (at most four), the others fill the remaining
-                // registers first, then the two lane-pinned bits
-                uint8_t bits[kRbBits + kRbLaneBits];
-                bool need_reg[kRbBits + kRbLaneBits];
+                // required bits of this and the following operations while a
+                // layout holds them all (make_layout)
+                constexpr int kMaxBits = 16;
+                uint8_t bits[kMaxBits];
+                bool need_reg[kMaxBits];
+                uint8_t set[4], lx[2];
                 int ns = 0;
                 for (int o2 = o; o2 < K.n_ops; ++o2) {
                     const Op& q = P->ops[K.op_off + o2];
                     const unsigned qr = op_reg_required(q), ql = op_lane_ok(q);
-                    uint8_t tb[kRbBits + kRbLaneBits];
-                    bool tr[kRbBits + kRbLaneBits];
+                    uint8_t tb[kMaxBits];
+                    bool tr[kMaxBits];
                     std::memcpy(tb, bits, sizeof(tb));
                     std::memcpy(tr, need_reg, sizeof(tr));
                     int nt2 = ns;
@@ -378,32 +458,24 @@ void build_rb(qk_plan* P, PKernel& K)
                         for (int u = 0; u < nt2; ++u)
                             if (tb[u] == q.b[t]) at = u;
                         if (at < 0) {
-                            if (nt2 == kRbBits + kRbLaneBits) { ok = false; break; }
+                            if (nt2 == kMaxBits) { ok = false; break; }
                             tb[nt2] = q.b[t];
                             tr[nt2++] = nr;
                         } else {
                             tr[at] = tr[at] || nr;
                         }
                     }
-                    int nreg = 0;
-                    for (int u = 0; u < nt2; ++u) nreg += tr[u];
-                    if (!ok || nreg > kRbBits) break;
+                    uint8_t s2[4], l2[2];
+                    if (!ok || !make_layout(tb, tr, nt2, m, fill, s2, l2)) {
+                        if (o2 == o) return;   // a single operation that fits no layout
+                        break;
+                    }
                     std::memcpy(bits, tb, sizeof(tb));
                     std::memcpy(need_reg, tr, sizeof(tr));
+                    std::memcpy(set, s2, 4);
+                    std::memcpy(lx, l2, 2);
                     ns = nt2;
                 }
-                uint8_t set[4], lx[2] = {kNoLane, kNoLane};
-                int nr = 0, nl = 0;
-                for (int u = 0; u < ns; ++u)
-                    if (need_reg[u]) set[nr++] = bits[u];
-                for (int u = 0; u < ns; ++u) {
-                    if (need_reg[u]) continue;
-                    if (nr < kRbBits) set[nr++] = bits[u];
-                    else lx[nl++] = bits[u];
-                }
-                fill(set, nr, lx);
-                std::sort(set, set + kRbBits);
-                if (lx[0] != kNoLane && lx[1] != kNoLane && lx[0] > lx[1]) std::swap(lx[0], lx[1]);
                 if (open) ph.back().op_end = (uint16_t)lops.size();
                 Phase p{};
                 std::memcpy(p.reg, set, 4);
@@ -422,12 +494,12 @@ void build_rb(qk_plan* P, PKernel& K)
                 open = true;
             }
             // register form: a register position, 0x40 | j for a bit on lane
-            // bit 4 + j (operations that exchange across lanes), or 0x80 |
-            // block bit for a bit the thread index supplies
+            // bit j (operations that exchange across lanes), or 0x80 | block
+            // bit for a bit the thread index supplies
             Op lo = op;
             for (int t = 0; t < nb; ++t) {
                 const int rp = reg_pos(cur, op.b[t]);
-                const int lp = (((rq & lq) >> t) & 1u) ? lane_pos(clx, op.b[t]) : -1;
+                const int lp = (((rq & lq) >> t) & 1u) ? lane_of(cur, clx, m, op.b[t]) : -1;
                 lo.b[t] = (uint8_t)(rp >= 0 ? rp : lp >= 0 ? (0x40 | lp) : (0x80 | op.b[t]));
             }
             if (op.code == OP_PHRUN) {
@@ -543,20 +615,8 @@ void build_rb(qk_plan* P, PKernel& K)
         ld.op_begin = ld.op_end = (uint16_t)lops.size();
         ph.push_back(ld);
         const int tbits = nt == 512 ? 9 : 8;
-        for (Phase& p : ph) {
-            uint32_t used = 0;
-            for (int k = 0; k < kRbBits; ++k) used |= 1u << p.reg[k];
-            for (int j = 0; j < kRbLaneBits; ++j)
-                if (p.lx[j] != kNoLane) used |= 1u << p.lx[j];
-            int j = 0;
-            for (int q = 0; q < m && j < tbits; ++q) {
-                if ((used >> q) & 1u) continue;
-                if (j == 4 && p.lx[0] != kNoLane) p.tmap[j++] = p.lx[0];
-                if (j == 5 && p.lx[1] != kNoLane) p.tmap[j++] = p.lx[1];
-                p.tmap[j++] = (uint8_t)q;
-            }
-            if (j != tbits) return;   // not a layout of this block size
-        }
+        for (Phase& p : ph)
+            if (layout_tmap(p.reg, p.lx, m, tbits, p.tmap) != tbits) return;   // not a layout of this block size
     }
     d.ops_off = (uint32_t)up16(ph.size() * sizeof(Phase));
     d.coef_off = d.ops_off + (uint32_t)(lops.size() * sizeof(Op));
