@@ -1035,10 +1035,22 @@ __device__ __forceinline__ bool rb_apply_lane(V (&v)[kRbAmps], const Op& op, con
     return true;
 }
 
-template <typename C, typename V>
+// FUSED: the kernel is one 2^k x 2^k operation on register bits 0..k-1
+// (a separate instantiation, so that the up to 512 coefficient words it keeps
+// in scalar registers do not weigh on the gate-sequence kernels).
+template <bool FUSED, typename C, typename V>
 __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C* coef, uint64_t bb, uint32_t tb)
 {
     const C* u = coef + op.coef;
+    if constexpr (FUSED) {
+        switch (op.k) {
+        case 1: rb_densek<1>(v, u); break;
+        case 2: rb_densek<2>(v, u); break;
+        case 3: rb_densek<3>(v, u); break;
+        default: rb_densek<4>(v, u); break;
+        }
+        return;
+    }
     // values of the state qubits b[2], b[3] outside the block (uniform)
     const uint32_t s2 = (uint32_t)(bb >> op.b[2]) & 1u, s3 = (uint32_t)(bb >> op.b[3]) & 1u;
     const bool t0 = (op.b[0] & 0x80u) != 0, t1 = (op.b[1] & 0x80u) != 0;
@@ -1125,14 +1137,6 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
     case OP_CPHASE: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_cphase<A.value, B.value>(v, u); }); break;
     case OP_DIAG2: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_diag2<A.value, B.value>(v, u); }); break;
     case OP_SWAP: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_swap<A.value, B.value>(v); }); break;
-    case OP_DENSEK:
-        switch (op.k) {
-        case 1: rb_densek<1>(v, u); break;
-        case 2: rb_densek<2>(v, u); break;
-        case 3: rb_densek<3>(v, u); break;
-        default: rb_densek<4>(v, u); break;
-        }
-        break;
     default: break;
     }
 }
@@ -1245,7 +1249,7 @@ __device__ __forceinline__ uint64_t chunk_offset(int I, const uint64_t* rb)
 // Occupancy target: two workgroups of 512 (complex64) or 256 (complex128)
 // threads per compute unit, i.e. 4 or 2 waves per SIMD.
 
-template <typename C, int NT>
+template <typename C, int NT, bool FUSED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(C) == 8 ? 4 : 2)))
 void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog)
 {
@@ -1394,7 +1398,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
                 op.b[2] = (uint8_t)w1;
                 op.b[3] = (uint8_t)(w1 >> 8);
                 op.coef = lds_uniform(ow + 3);
-                rb_apply(v, op, coef, base, tb);
+                rb_apply<FUSED>(v, op, coef, base, tb);
             }
         }
         if (!same_layout(cur, clx, d.st_reg, d.st_lx) && d.uses_lds) {
@@ -1811,7 +1815,7 @@ template <typename C, int NT>
 int launch_rb_typed(void* psi, const RbDesc& d, const void* prog, hipStream_t s)
 {
     const size_t lds = d.prog_bytes + (size_t)NT * 16 + (d.uses_lds ? ((size_t)sizeof(C) << d.b.m) : 0);
-    auto f = k_block_rb<C, NT>;
+    auto f = d.fused ? k_block_rb<C, NT, true> : k_block_rb<C, NT, false>;
     const uint64_t res = resident_groups(reinterpret_cast<const void*>(f), lds, NT);
     const dim3 grid((uint32_t)std::min<uint64_t>(d.b.nblocks, res)), block(NT);
     hipLaunchKernelGGL(f, grid, block, lds, s, (C*)psi, d, (const uint8_t*)prog);

@@ -386,6 +386,7 @@ void build_rb(qk_plan* P, PKernel& K)
     RbDesc& d = K.rbd;
     std::memset(&d, 0, sizeof(d));
     d.b = K.desc;
+    d.fused = (uint8_t)(K.type == QK_KERNEL_FUSED);
     uint8_t io_reg[4];
     rb_io_reg(P->dtype, nt, io_reg);
     std::vector<Phase> ph;

@@ -135,7 +135,9 @@ struct RbDesc {
     uint32_t prog_bytes, ops_off, coef_off;
     // complex64 only: 1 = loads (stores) move 16-byte amplitude pairs, which
     // needs register bit 0 = block bit 0; 0 = single 8-byte amplitudes
-    uint8_t ld_wide, st_wide, pad[2];
+    uint8_t ld_wide, st_wide;
+    uint8_t fused;       // 1: one 2^k x 2^k operation (fused kernel); 0: a gate sequence
+    uint8_t pad;
     int32_t n_transposes;   // layout changes per block (host statistics)
     uint8_t ld_lx[2];       // lane-pinned block bits of the load layout
     uint8_t st_lx[2];       // lane-pinned block bits of the store layout
