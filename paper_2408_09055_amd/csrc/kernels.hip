@@ -1124,6 +1124,19 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
             static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], c); });
         break;
     }
+    case OP_BPHRUN: {
+        // product of the entries' factors selected by the block's bits
+        V f{1, 0};
+        for (int e = 0; e < op.k; ++e) {
+            const V h = ld_coef(u + 5 * e);
+            const uint32_t qa = (uint32_t)h.x, qb = (uint32_t)h.y;
+            const uint32_t s = (uint32_t)((bb >> qa) & 1u) + 2u * (uint32_t)((bb >> qb) & 1u);
+            const V c = ld_coef(u + 5 * e + 1 + s);
+            if (!is_one(c)) f = cmul(f, c);
+        }
+        if (!is_one(f)) static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], f); });
+        break;
+    }
     case OP_DIAG1C: dispatch1(op.b[0], [&](auto K) QK_AI { rb_diag1<K.value>(v, u + 2 * s2); }); break;
     case OP_XC:
         if (s2) dispatch1(op.b[0], [&](auto K) QK_AI { rb_x<K.value>(v); });

@@ -247,7 +247,7 @@ int canonicalize(const qk_circuit* c, const qk_kopts& ko, qk_plan* P)
 // Block bits an operation acts on (b[0], b[1]); OP_BPHASE acts on none.
 int op_nbits(const Op& op)
 {
-    if (op.code == OP_BPHASE) return 0;
+    if (op.code == OP_BPHASE || op.code == OP_BPHRUN) return 0;
     if (op.code == OP_CX || op.code == OP_CZ || op.code == OP_CPHASE || op.code == OP_DIAG2 || op.code == OP_SWAP)
         return 2;
     return 1;
@@ -259,7 +259,7 @@ int op_nbits(const Op& op)
 unsigned op_reg_required(const Op& op)
 {
     switch (op.code) {
-    case OP_BPHASE: case OP_DIAG1: case OP_DIAG1C: case OP_CZ: case OP_CPHASE: case OP_PHRUN: return 0u;
+    case OP_BPHASE: case OP_BPHRUN: case OP_DIAG1: case OP_DIAG1C: case OP_CZ: case OP_CPHASE: case OP_PHRUN: return 0u;
     case OP_CX: return 2u;
     default: return op_nbits(op) == 2 ? 3u : 1u;
     }
@@ -427,8 +427,30 @@ void build_rb(qk_plan* P, PKernel& K)
         uint8_t cur[4], clx[2] = {kNoLane, kNoLane};
         std::memcpy(cur, io_reg, 4);
         bool open = false;
+        // block phases (insular gates entirely outside the block) commute
+        // with every operation of the kernel: they are gathered into phase
+        // products applied once, after the other operations
+        std::vector<Op> bruns;
+        for (int o = 0; o < K.n_ops; ++o) {
+            const Op& op = P->ops[K.op_off + o];
+            if (op.code != OP_BPHASE) continue;
+            if (bruns.empty() || bruns.back().k == 255) {
+                Op r{};
+                r.code = OP_BPHRUN;
+                r.coef = (uint32_t)P->coefs.size();
+                bruns.push_back(r);
+            }
+            Op& r = bruns.back();
+            const int qa = op.b[2], qb = op.k == 2 ? op.b[3] : op.b[2];
+            P->coefs.push_back(cd((double)qa, (double)qb));
+            const cd* c = &P->coefs[op.coef];
+            const cd t[4] = {c[0], op.k == 2 ? c[1] : c[0], op.k == 2 ? c[2] : c[1], op.k == 2 ? c[3] : c[1]};
+            for (int i = 0; i < 4; ++i) P->coefs.push_back(t[i]);
+            ++r.k;
+        }
         for (int o = 0; o < K.n_ops; ++o) {
             Op op = P->ops[K.op_off + o];
+            if (op.code == OP_BPHASE) continue;
             const int nb = op_nbits(op);
             const unsigned rq = op_reg_required(op), lq = op_lane_ok(op);
             bool fits = true;
@@ -532,6 +554,18 @@ void build_rb(qk_plan* P, PKernel& K)
             lops.push_back(lo);
             lop_reg.push_back({cur[0], cur[1], cur[2], cur[3]});
         }
+        if (!bruns.empty() && !open) {
+            Phase p{};
+            std::memcpy(p.reg, cur, 4);
+            std::memcpy(p.lx, clx, 2);
+            p.op_begin = (uint16_t)lops.size();
+            ph.push_back(p);
+            open = true;
+        }
+        for (const Op& r : bruns) {
+            lops.push_back(r);
+            lop_reg.push_back({cur[0], cur[1], cur[2], cur[3]});
+        }
         if (open) ph.back().op_end = (uint16_t)lops.size();
     }
     // load in the first phase's layout and store in the last one's when they
@@ -595,6 +629,7 @@ void build_rb(qk_plan* P, PKernel& K)
         case OP_DENSE1: case OP_H: case OP_DIAG2: case OP_DIAG1C: cnt = 4; break;
         case OP_DIAG1: cnt = 2; break;
         case OP_BPHASE: cnt = 2 << (o.k - 1); break;
+        case OP_BPHRUN: cnt = 5 * o.k; break;
         case OP_CPHASE: cnt = 1; break;
         case OP_DENSEK: cnt = 1 << (2 * o.k); break;
         default: cnt = 0; break;

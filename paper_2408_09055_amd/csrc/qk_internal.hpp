@@ -55,6 +55,11 @@ enum OpCode : uint8_t {
     // form: register position 0..3, 0x80 | block bit for a thread-index bit,
     // 0x100 + state qubit outside the block).
     OP_PHRUN = 13,
+    // Register form only: all block phases of a kernel as one product.  They
+    // multiply whole blocks, so they commute with every other operation of
+    // the kernel.  Entry e (of k): coef[5 e] = (qubit a, qubit b) as real
+    // numbers, coef[5 e + 1 + s] the factor for s = bit(a) + 2 bit(b).
+    OP_BPHRUN = 14,
 };
 
 struct Op {
