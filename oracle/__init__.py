@@ -505,9 +505,10 @@ def features(seg, n: int, ktype: int, dtype_c128: bool, insular: bool = False) -
     [12] qubits below 6  [13] diagonal gates  [14] fused one-hot
     [15] LDS one-hot  [16] n  [17] complex128 flag
     [18] k * [fused]
-    [19] LDS only: register phases beyond the first, ceil(r / 4) - 1 (at
-         least 0), with r the qubits some gate needs in registers (all
-         qubits of non-diagonal gates except a CX control)
+    [19] LDS only: register phases beyond the first, ceil(r / 6) - 1 (at
+         least 0), with r the qubits some gate needs on register or
+         lane-exchange bits (all qubits of non-diagonal gates except a CX
+         control); a phase holds six such qubits
     """
     from workloads import Z, S, T, RZ, P, CZ, CP, RZZ
     diag_kinds = {Z, S, T, RZ, P, CZ, CP, RZZ}
@@ -536,7 +537,7 @@ def features(seg, n: int, ktype: int, dtype_c128: bool, insular: bool = False) -
     f[17] = 1.0 if dtype_c128 else 0.0
     f[18] = k * f[14]
     r = bin(regq).count("1")
-    f[19] = max(0, (r + 3) // 4 - 1) if ktype == TYPE_LDS else 0.0
+    f[19] = max(0, (r + 5) // 6 - 1) if ktype == TYPE_LDS else 0.0
     return f
 
 

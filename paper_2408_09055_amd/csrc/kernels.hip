@@ -1324,7 +1324,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     // 16 bytes.
     using Raw = typename std::conditional<CH == 2, u32x2, u32x4>::type;
     Raw w[kRbAmps];
-    uint64_t base = block_base(blk, d.b.act, m);
+    uint64_t base = 0;
     // The thread's amplitude-0 offset is materialised once per block (the
     // empty asm makes it opaque), so the compiler adds the uniform per-amplitude
     // offsets at each access instead of keeping 16 precomputed 64-bit
@@ -1378,8 +1378,10 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
         }
         return o;
     };
-    load_all(base);
     __syncthreads();   // program in LDS
+    // every block base, the first one included, comes from the run table
+    base = base_of(blk);
+    load_all(base);
     unpack();
     for (;;) {
         const uint64_t next = blk + gridDim.x;

@@ -658,19 +658,27 @@ void build_rb(qk_plan* P, PKernel& K)
     d.coef_off = d.ops_off + (uint32_t)(lops.size() * sizeof(Op));
     d.runs_off = (uint32_t)up16(d.coef_off + kc.size() * csz);
     // block-base table: the qubits outside the block in runs of consecutive
-    // qubits; block number bits fill them in ascending order
+    // qubits.  The block number's low bits fill the highest run first (bits
+    // ascending within a run), so that blocks processed at the same time
+    // differ in high address bits: with a block split at a large
+    // power-of-two stride, filling the runs from the lowest one instead
+    // measured 4.4 against 5.0 TB/s on a 32-qubit state.
     std::vector<uint32_t> runs;
     {
         bool in_act[64] = {};
         for (int j = 0; j < m; ++j) in_act[d.b.act[j]] = true;
-        uint32_t src = 0;
+        std::vector<std::pair<int, int>> rr;   // (first qubit, width)
         for (int q = 0; q < d.b.n;) {
             if (in_act[q]) { ++q; continue; }
             int w = 0;
             while (q + w < d.b.n && !in_act[q + w]) ++w;
-            runs.push_back(src | ((uint32_t)w << 8) | ((uint32_t)q << 16));
-            src += (uint32_t)w;
+            rr.push_back({q, w});
             q += w;
+        }
+        uint32_t src = 0;
+        for (auto it = rr.rbegin(); it != rr.rend(); ++it) {
+            runs.push_back(src | ((uint32_t)it->second << 8) | ((uint32_t)it->first << 16));
+            src += (uint32_t)it->second;
         }
     }
     if ((int)runs.size() > kRbMaxRuns) return;

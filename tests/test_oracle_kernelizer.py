@@ -109,12 +109,20 @@ def test_features_by_hand():
     exp[14] = 0; exp[15] = 1; exp[16] = 8; exp[17] = 0; exp[18] = 0; exp[19] = 0
     assert np.allclose(f, exp)
     # register phases: H on 1, U3 on 7 need registers (2 qubits: one phase);
-    # five more one-qubit gates and a CX target make 8 -> two phases
+    # H on 1..5, U3 on 7 and a CX target (8) make 7 -> two phases; the CX
+    # control (9) and the CZ (10, 11) need none
     c2 = W.from_list(12, [W.gate(W.H, [q]) for q in (1, 2, 3, 4, 5)] + [W.gate(W.U3, [7], [1, 2, 3]),
                                                                           W.gate(W.CX, [9, 8]), W.gate(W.CZ, [10, 11])])
     g2, _ = oracle.canonicalize(c2)
     assert oracle.features(g2, 12, oracle.TYPE_LDS, True)[19] == 1
     assert oracle.features(g2, 12, oracle.TYPE_FUSED, True)[19] == 0
+    # six such qubits still fit one phase; thirteen need three
+    c3 = W.from_list(14, [W.gate(W.H, [q]) for q in range(6)])
+    g3, _ = oracle.canonicalize(c3)
+    assert oracle.features(g3, 14, oracle.TYPE_LDS, True)[19] == 0
+    c4 = W.from_list(14, [W.gate(W.U3, [q], [0.1, 0.2, 0.3]) for q in range(13)])
+    g4, _ = oracle.canonicalize(c4)
+    assert oracle.features(g4, 14, oracle.TYPE_LDS, True)[19] == 2
 
 
 # --------------------------------------------------------------------------
