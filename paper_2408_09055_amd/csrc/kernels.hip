@@ -997,6 +997,12 @@ __host__ __device__ constexpr uint32_t reg_half_mask(int k)
     return m;
 }
 
+// integer code held in the raw bits of a program coefficient slot
+__device__ __forceinline__ uint32_t raw_code(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ uint32_t raw_code(double x) { return (uint32_t)__double_as_longlong(x); }
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+
 template <typename C, typename V>
 __device__ __forceinline__ bool rb_apply_lane(V (&v)[kRbAmps], const Op& op, const C* u, uint32_t s2, uint32_t tb)
 {
@@ -1094,21 +1100,27 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
         return;
     }
     if (op.code == OP_PHRUN) {
-        // product of the run's phases (partners: thread-index bits or qubits
-        // outside the block) as one factor per thread, then the target half
-        // is scaled once
+        // The run's factor is exp(i * sum of the angles of the partners that
+        // are set): partners outside the block first (b[1] of them; a state
+        // qubit, uniform per block), then partners on thread-index bits (a
+        // block bit, per lane).  Entry e holds the angle and the partner as
+        // raw integer bits.  One sincos per thread, then the target half is
+        // scaled once.
+        using RR = decltype(V{}.x);
         const V one{1, 0};
-        V f = one;
-        for (int e = 0; e < op.k; ++e) {
-            const V ph = ld_coef(u + 2 * e);
-            const uint32_t code = (uint32_t)ld_coef(u + 2 * e + 1).x;
-            if (code >= 0x100u) {
-                if ((bb >> (code - 0x100u)) & 1u) f = cmul(f, ph);
-            } else {
-                const V g = cmul(f, ph);
-                f = vsel(tbit(tb, (uint8_t)code) != 0, g, f);
-            }
+        RR ang = 0;
+        const int nout = op.b[1];
+        for (int e = 0; e < nout; ++e) {
+            const C c = u[e];
+            if ((bb >> raw_code(c.y)) & 1u) ang += c.x;
         }
+        for (int e = nout; e < op.k; ++e) {
+            const C c = u[e];
+            ang += ((tb >> raw_code(c.y)) & 1u) ? c.x : RR(0);
+        }
+        RR sn, cs;
+        sin_cos(ang, &sn, &cs);
+        const V f{cs, sn};
         if (t0) {
             const V g = vsel(tbit(tb, op.b[0]) != 0, f, one);
             static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], g); });

@@ -607,20 +607,30 @@ void build_rb(qk_plan* P, PKernel& K)
     const size_t csz = P->dtype == QK_C128 ? 16 : 8;
     auto up16 = [](size_t x) { return (x + 15) & ~size_t(15); };
     std::vector<cd> kc;
-    // phase runs: the partner codes become register form in the current
-    // phase's layout (recorded per operation while the phases were built)
+    // entries of kc whose imaginary slot holds an integer code (raw bits)
+    std::vector<int64_t> raw(0);
+    // Phase runs in register form: one entry per partner, its phase angle
+    // (FP64 arg of the unit factor, rounded once to the state's precision)
+    // and the partner as raw integer bits; partners outside the block (a
+    // state qubit) first, their count in b[1], then partners on thread-index
+    // bits (a block bit).  The kernel sums the angles and takes one sincos.
     for (size_t oi = 0; oi < lops.size(); ++oi) {
         Op& o = lops[oi];
         if (o.code == OP_PHRUN) {
+            (void)lop_reg;
             const uint32_t first = (uint32_t)kc.size();
-            for (int e = 0; e < o.k; ++e) {
-                kc.push_back(P->coefs[o.coef + 2 * e]);
-                const int code = (int)P->coefs[o.coef + 2 * e + 1].real();
-                // partners are thread-index bits or outside the block here
-                const int rcode = code >= 64 ? 0x100 + (code - 64) : (0x80 | code);
-                (void)lop_reg;
-                kc.push_back(cd((double)rcode, 0.0));
-            }
+            int nout = 0;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int e = 0; e < o.k; ++e) {
+                    const int code = (int)P->coefs[o.coef + 2 * e + 1].real();
+                    const bool outside = code >= 64;
+                    if (outside != (pass == 0)) continue;
+                    kc.push_back(cd(std::arg(P->coefs[o.coef + 2 * e]), 0.0));
+                    raw.resize(kc.size(), -1);
+                    raw.back() = outside ? code - 64 : code;
+                    nout += outside;
+                }
+            o.b[1] = (uint8_t)nout;
             o.coef = first;
             continue;
         }
@@ -702,10 +712,18 @@ void build_rb(qk_plan* P, PKernel& K)
     std::memcpy(dst + d.ops_off, lops.data(), lops.size() * sizeof(Op));
     for (size_t t = 0; t < kc.size(); ++t) {
         if (P->dtype == QK_C128) {
-            const double v[2] = {kc[t].real(), kc[t].imag()};
+            double v[2] = {kc[t].real(), kc[t].imag()};
+            if (t < raw.size() && raw[t] >= 0) {
+                const uint64_t r = (uint64_t)raw[t];
+                std::memcpy(&v[1], &r, 8);
+            }
             std::memcpy(dst + d.coef_off + t * csz, v, csz);
         } else {
-            const float v[2] = {(float)kc[t].real(), (float)kc[t].imag()};
+            float v[2] = {(float)kc[t].real(), (float)kc[t].imag()};
+            if (t < raw.size() && raw[t] >= 0) {
+                const uint32_t r = (uint32_t)raw[t];
+                std::memcpy(&v[1], &r, 4);
+            }
             std::memcpy(dst + d.coef_off + t * csz, v, csz);
         }
     }
