@@ -1110,11 +1110,27 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
         const V one{1, 0};
         RR ang = 0;
         const int nout = op.b[1];
-        for (int e = 0; e < nout; ++e) {
+        // four entries per step: their scalar loads are issued together
+        int e = 0;
+        for (; e + 4 <= nout; e += 4) {
+            const C c0 = u[e], c1 = u[e + 1], c2 = u[e + 2], c3 = u[e + 3];
+            if ((bb >> raw_code(c0.y)) & 1u) ang += c0.x;
+            if ((bb >> raw_code(c1.y)) & 1u) ang += c1.x;
+            if ((bb >> raw_code(c2.y)) & 1u) ang += c2.x;
+            if ((bb >> raw_code(c3.y)) & 1u) ang += c3.x;
+        }
+        for (; e < nout; ++e) {
             const C c = u[e];
             if ((bb >> raw_code(c.y)) & 1u) ang += c.x;
         }
-        for (int e = nout; e < op.k; ++e) {
+        for (; e + 4 <= op.k; e += 4) {
+            const C c0 = u[e], c1 = u[e + 1], c2 = u[e + 2], c3 = u[e + 3];
+            ang += ((tb >> raw_code(c0.y)) & 1u) ? c0.x : RR(0);
+            ang += ((tb >> raw_code(c1.y)) & 1u) ? c1.x : RR(0);
+            ang += ((tb >> raw_code(c2.y)) & 1u) ? c2.x : RR(0);
+            ang += ((tb >> raw_code(c3.y)) & 1u) ? c3.x : RR(0);
+        }
+        for (; e < op.k; ++e) {
             const C c = u[e];
             ang += ((tb >> raw_code(c.y)) & 1u) ? c.x : RR(0);
         }
