@@ -1363,18 +1363,18 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
         if constexpr (CH == 2) {
             if (d.ld_wide) {
                 static_for<0, kRbAmps / 2>([&](auto I) QK_AI {
-                    const u32x4 x = *reinterpret_cast<const u32x4*>(&psi[b0 + chunk_offset<2>(I.value, ld_b)]);
+                    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(&psi[b0 + chunk_offset<2>(I.value, ld_b)]));
                     w[2 * I.value] = u32x2{x.x, x.y};
                     w[2 * I.value + 1] = u32x2{x.z, x.w};
                 });
             } else {
                 static_for<0, kRbAmps>([&](auto I) QK_AI {
-                    w[I.value] = *reinterpret_cast<const u32x2*>(&psi[b0 + chunk_offset<1>(I.value, ld_b)]);
+                    w[I.value] = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(&psi[b0 + chunk_offset<1>(I.value, ld_b)]));
                 });
             }
         } else {
             static_for<0, kRbAmps>([&](auto I) QK_AI {
-                w[I.value] = *reinterpret_cast<const u32x4*>(&psi[b0 + chunk_offset<1>(I.value, ld_b)]);
+                w[I.value] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(&psi[b0 + chunk_offset<1>(I.value, ld_b)]));
             });
         }
     };
@@ -1456,13 +1456,13 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
                 static_for<0, kRbAmps / 2>([&](auto I) QK_AI {
                     const V a = v[2 * I.value], b = v[2 * I.value + 1];
                     const u32x4 x = {__float_as_uint(a.x), __float_as_uint(a.y), __float_as_uint(b.x), __float_as_uint(b.y)};
-                    *reinterpret_cast<u32x4*>(&psi[s0 + chunk_offset<2>(I.value, st_b)]) = x;
+                    __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(&psi[s0 + chunk_offset<2>(I.value, st_b)]));
                 });
             } else {
                 static_for<0, kRbAmps>([&](auto I) QK_AI {
                     const V a = v[I.value];
-                    *reinterpret_cast<u32x2*>(&psi[s0 + chunk_offset<1>(I.value, st_b)]) =
-                        u32x2{__float_as_uint(a.x), __float_as_uint(a.y)};
+                    __builtin_nontemporal_store(u32x2{__float_as_uint(a.x), __float_as_uint(a.y)},
+                                                reinterpret_cast<u32x2*>(&psi[s0 + chunk_offset<1>(I.value, st_b)]));
                 });
             }
         } else {
@@ -1470,7 +1470,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
                 const V a = v[I.value];
                 const uint64_t re = __builtin_bit_cast(uint64_t, a.x), im = __builtin_bit_cast(uint64_t, a.y);
                 const u32x4 x = {(uint32_t)re, (uint32_t)(re >> 32), (uint32_t)im, (uint32_t)(im >> 32)};
-                *reinterpret_cast<u32x4*>(&psi[s0 + chunk_offset<1>(I.value, st_b)]) = x;
+                __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(&psi[s0 + chunk_offset<1>(I.value, st_b)]));
             });
         }
         if (next >= d.b.nblocks) break;
