@@ -344,7 +344,9 @@ bool make_layout(const uint8_t* bits, const bool* need_reg, int ns, int m, Fill 
         int no = 0;
         for (int u = 0; u < ns; ++u)
             if (!need_reg[u] && !in_reg(bits[u]) && !((low4 >> bits[u]) & 1u)) out[no++] = bits[u];
-        if (no <= kRbLaneBits) {
+        // free registers take these bits first (a gate on a register bit is
+        // cheaper than a lane exchange); only the rest is pinned to lanes
+        if (no <= kRbLaneBits && (no == 0 || nr == kRbBits)) {
             uint8_t lx[2] = {kNoLane, kNoLane};
             for (int t = 0; t < no; ++t) lx[t] = out[t];
             if (no == 2 && lx[0] > lx[1]) std::swap(lx[0], lx[1]);
@@ -453,7 +455,9 @@ void build_rb(qk_plan* P, PKernel& K)
             if (op.code == OP_BPHASE) continue;
             const int nb = op_nbits(op);
             const unsigned rq = op_reg_required(op), lq = op_lane_ok(op);
-            bool fits = true;
+            // the first phase's layout is always chosen by the look-ahead
+            // below, not inherited from the default load layout
+            bool fits = open;
             for (int t = 0; t < 2; ++t)
                 if ((rq >> t) & 1u)
                     fits &= reg_pos(cur, op.b[t]) >= 0 || (((lq >> t) & 1u) && lane_of(cur, clx, m, op.b[t]) >= 0);

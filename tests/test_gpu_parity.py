@@ -409,3 +409,67 @@ def test_inplace_involution_pass_bit_exact(ctx, dtype):
     with pytest.raises(qk.QkError):
         st.permute_inplace(np.array([1, 2, 0, 3, 4, 5], np.int32))
     st.free()
+
+
+# ------------------------------------------------------- lane-exchange gates
+@pytest.mark.parametrize("dtype,m_max,ell", [(qk.QK_C64, 13, 7), (qk.QK_C64, 12, 6), (qk.QK_C128, 12, 6)])
+def test_lane_exchange_gates(ctx, dtype, m_max, ell):
+    """Register-blocked LDS kernels whose one-qubit gates and CX targets sit
+    on lane bits of the wave: qubits 0..5 on lane bits 0..5 (DPP partner moves
+    for 0..3, permlane swaps for 4, 5) and high qubits pinned to lane bits 4
+    and 5, with controls on registers, thread bits and qubits outside the
+    block (insular CX), against the oracle.  Layouts that fit one phase must
+    need no LDS transpose."""
+    n = 17
+    rng = np.random.default_rng(90 + m_max + 7 * dtype)
+    high = sorted(int(q) for q in rng.choice(np.arange(ell, n), m_max - ell, replace=False))
+
+    def kernel(pool, count, controls):
+        gates = []
+        for _ in range(count):
+            r = rng.random()
+            t = int(rng.choice(pool))
+            if r < 0.35:
+                gates.append(W.gate(W.U3, [t], list(rng.uniform(0, 6, 3))))
+            elif r < 0.5:
+                gates.append(W.gate(W.H, [t]))
+            elif r < 0.6:
+                gates.append(W.gate(W.X, [t]))
+            elif r < 0.85:
+                c = int(rng.choice([q for q in controls if q != t]))
+                gates.append(W.gate(W.CX, [c, t]))
+            else:
+                a, b = (int(x) for x in rng.choice(pool, 2, replace=False))
+                gates.append(W.gate(W.CZ, [a, b]))
+        return gates
+
+    everyone = list(range(n))
+    cases = [
+        # qubits 0..5 on lanes and four high qubits in registers: one phase
+        ("lanes 0..5 + 4 high", list(range(6)) + high[:4], everyone, True),
+        # four low qubits on lanes 0..3, six high qubits: two of them pinned
+        ("lanes 0..3 + 6 high", list(range(4)) + high[:6], everyone, True),
+        # controls only outside the pool (insular CX on lane targets)
+        ("insular controls", list(range(6)) + high[:2], [q for q in range(n) if q not in range(6) and q not in high[:2]], True),
+        # the whole block: several phases and transposes
+        ("whole block", list(range(ell)) + high, everyone, False),
+    ]
+    for name, pool, controls, one_phase in cases:
+        if len(set(pool)) > m_max:
+            continue
+        circ = W.from_list(n, kernel(pool, 60, controls))
+        psi = W.random_state(n, 5 + len(pool))
+        ref = oracle.run(circ, psi)
+        plan = qk.kernelize_single(ctx, circ, qk.kopts(dtype=dtype, m_max=m_max, ell=ell, insular=1),
+                                   qk.QK_KERNEL_LDS)
+        info = plan.kernel(0)
+        print(f"{name}: dtype={dtype} m={m_max} phases={info.n_phases} transposes={info.n_transposes}", flush=True)
+        if one_phase:
+            assert info.n_transposes == 0, name
+        st = qk.sv_alloc(ctx, n, dtype)
+        st.upload(psi.astype(st.np_dtype))
+        qk.execute_plan(ctx, plan, st)
+        got = st.download()
+        st.free()
+        plan.free()
+        _check(got, ref, dtype, f"lanes {name} m={m_max}")
