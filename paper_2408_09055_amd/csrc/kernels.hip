@@ -1003,43 +1003,6 @@ __device__ __forceinline__ uint32_t raw_code(double x) { return (uint32_t)__doub
 __device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
 
-template <typename C, typename V>
-__device__ __forceinline__ bool rb_apply_lane(V (&v)[kRbAmps], const Op& op, const C* u, uint32_t s2, uint32_t tb)
-{
-    // target bit: b[1] for CX, else b[0]
-    const uint8_t t = op.code == OP_CX ? op.b[1] : op.b[0];
-    if ((t & 0xc0u) != 0x40u) return false;
-    auto lane = [&](auto f) QK_AI {
-        switch (t & 7u) {
-        case 0: f(IC<0>{}); break;
-        case 1: f(IC<1>{}); break;
-        case 2: f(IC<2>{}); break;
-        case 3: f(IC<3>{}); break;
-        case 4: f(IC<4>{}); break;
-        default: f(IC<5>{}); break;
-        }
-    };
-    switch (op.code) {
-    case OP_DENSE1: lane([&](auto J) QK_AI { rb_lane_dense1<J.value>(v, u); }); break;
-    case OP_H: lane([&](auto J) QK_AI { rb_lane_h<J.value>(v, u); }); break;
-    case OP_X: lane([&](auto J) QK_AI { rb_lane_x<J.value>(v, 0xffffu, true); }); break;
-    case OP_XC:
-        if (s2) lane([&](auto J) QK_AI { rb_lane_x<J.value>(v, 0xffffu, true); });
-        break;
-    case OP_CX:
-        if (op.b[0] & 0x80u) {
-            const bool c = tbit(tb, op.b[0]) != 0;
-            if (__ballot(c)) lane([&](auto J) QK_AI { rb_lane_x<J.value>(v, 0xffffu, c); });
-        } else {
-            dispatch1(op.b[0], [&](auto K) QK_AI {
-                lane([&](auto J) QK_AI { rb_lane_x<J.value>(v, reg_half_mask(K.value), true); });
-            });
-        }
-        break;
-    default: break;
-    }
-    return true;
-}
 
 // FUSED: the kernel is one 2^k x 2^k operation on register bits 0..k-1
 // (a separate instantiation, so that the up to 512 coefficient words it keeps
@@ -1057,49 +1020,94 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
         }
         return;
     }
-    // values of the state qubits b[2], b[3] outside the block (uniform)
-    const uint32_t s2 = (uint32_t)(bb >> op.b[2]) & 1u, s3 = (uint32_t)(bb >> op.b[3]) & 1u;
-    const bool t0 = (op.b[0] & 0x80u) != 0, t1 = (op.b[1] & 0x80u) != 0;
-    if (rb_apply_lane(v, op, u, s2, tb)) return;
-    if (op.code == OP_DIAG1 && t0) {
-        rb_scale_sel(v, tbit(tb, op.b[0]), ld_coef(u), ld_coef(u + 1));
-        return;
-    }
-    if (op.code == OP_DIAG1C && t0) {
-        rb_scale_sel(v, tbit(tb, op.b[0]), ld_coef(u + 2 * s2), ld_coef(u + 2 * s2 + 1));
-        return;
-    }
-    if (op.code == OP_CZ && (t0 || t1)) {
-        if (t0 && t1) {
-            const uint32_t c = tbit(tb, op.b[0]) & tbit(tb, op.b[1]);
-            if (__ballot(c)) rb_neg_sel<0xffffu>(v, c);
-        } else {
-            const uint32_t c = tbit(tb, t0 ? op.b[0] : op.b[1]);
-            dispatch1(t0 ? op.b[1] : op.b[0], [&](auto K) QK_AI { rb_neg_sel<reg_half_mask(K.value)>(v, c); });
+    // One switch on the operation code; each case decodes only the fields it
+    // uses (the decode runs on the scalar unit, once per operation and block).
+    // Bit codes: 0..3 register bit, 0x40 | j lane bit j, 0x80 | b thread bit.
+    const uint8_t b0 = op.b[0], b1 = op.b[1];
+    auto thr = [](uint8_t c) { return (c & 0x80u) != 0; };
+    auto lanej = [](uint8_t c) { return (c & 0xc0u) == 0x40u; };
+    // value of state qubit b[2] outside the block (uniform)
+    auto s2f = [&]() QK_AI { return (uint32_t)(bb >> op.b[2]) & 1u; };
+    auto lane = [&](uint8_t c, auto f) QK_AI {
+        switch (c & 7u) {
+        case 0: f(IC<0>{}); break;
+        case 1: f(IC<1>{}); break;
+        case 2: f(IC<2>{}); break;
+        case 3: f(IC<3>{}); break;
+        case 4: f(IC<4>{}); break;
+        default: f(IC<5>{}); break;
         }
-        return;
+    };
+    const V one{1, 0};
+    switch (op.code) {
+    case OP_DENSE1:
+        if (lanej(b0)) lane(b0, [&](auto J) QK_AI { rb_lane_dense1<J.value>(v, u); });
+        else dispatch1(b0, [&](auto K) QK_AI { rb_dense1<K.value>(v, u); });
+        break;
+    case OP_H:
+        if (lanej(b0)) lane(b0, [&](auto J) QK_AI { rb_lane_h<J.value>(v, u); });
+        else dispatch1(b0, [&](auto K) QK_AI { rb_h<K.value>(v, u); });
+        break;
+    case OP_XC:
+        if (!s2f()) break;
+        [[fallthrough]];
+    case OP_X:
+        if (lanej(b0)) lane(b0, [&](auto J) QK_AI { rb_lane_x<J.value>(v, 0xffffu, true); });
+        else dispatch1(b0, [&](auto K) QK_AI { rb_x<K.value>(v); });
+        break;
+    case OP_CX:
+        if (lanej(b1)) {
+            if (thr(b0)) {
+                const bool c = tbit(tb, b0) != 0;
+                if (__ballot(c)) lane(b1, [&](auto J) QK_AI { rb_lane_x<J.value>(v, 0xffffu, c); });
+            } else {
+                dispatch1(b0, [&](auto K) QK_AI {
+                    lane(b1, [&](auto J) QK_AI { rb_lane_x<J.value>(v, reg_half_mask(K.value), true); });
+                });
+            }
+        } else if (thr(b0)) {
+            const uint32_t c = tbit(tb, b0);
+            dispatch1(b1, [&](auto K) QK_AI { rb_cswap<K.value>(v, c); });
+        } else {
+            dispatch2(b0, b1, [&](auto A, auto B) QK_AI { rb_cx<A.value, B.value>(v); });
+        }
+        break;
+    case OP_DIAG1:
+        if (thr(b0)) rb_scale_sel(v, tbit(tb, b0), ld_coef(u), ld_coef(u + 1));
+        else dispatch1(b0, [&](auto K) QK_AI { rb_diag1<K.value>(v, u); });
+        break;
+    case OP_DIAG1C: {
+        const uint32_t s2 = s2f();
+        if (thr(b0)) rb_scale_sel(v, tbit(tb, b0), ld_coef(u + 2 * s2), ld_coef(u + 2 * s2 + 1));
+        else dispatch1(b0, [&](auto K) QK_AI { rb_diag1<K.value>(v, u + 2 * s2); });
+        break;
     }
-    if ((op.code == OP_CZ || op.code == OP_CPHASE) && (t0 || t1)) {
-        const V ph = op.code == OP_CZ ? V{-1, 0} : ld_coef(u);
-        const V one{1, 0};
-        if (t0 && t1) {
-            const uint32_t c = tbit(tb, op.b[0]) & tbit(tb, op.b[1]);
+    case OP_CZ:
+        if (thr(b0) && thr(b1)) {
+            const uint32_t c = tbit(tb, b0) & tbit(tb, b1);
+            if (__ballot(c)) rb_neg_sel<0xffffu>(v, c);
+        } else if (thr(b0) || thr(b1)) {
+            const uint32_t c = tbit(tb, thr(b0) ? b0 : b1);
+            dispatch1(thr(b0) ? b1 : b0, [&](auto K) QK_AI { rb_neg_sel<reg_half_mask(K.value)>(v, c); });
+        } else {
+            dispatch2(b0, b1, [&](auto A, auto B) QK_AI { rb_cz<A.value, B.value>(v); });
+        }
+        break;
+    case OP_CPHASE:
+        if (thr(b0) && thr(b1)) {
+            const uint32_t c = tbit(tb, b0) & tbit(tb, b1);
             if (__ballot(c)) {
-                const V f = vsel(c != 0, ph, one);
+                const V f = vsel(c != 0, ld_coef(u), one);
                 static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], f); });
             }
+        } else if (thr(b0) || thr(b1)) {
+            const V f = vsel(tbit(tb, thr(b0) ? b0 : b1) != 0, ld_coef(u), one);
+            dispatch1(thr(b0) ? b1 : b0, [&](auto K) QK_AI { rb_mul_half<K.value>(v, f); });
         } else {
-            const V f = vsel(tbit(tb, t0 ? op.b[0] : op.b[1]) != 0, ph, one);
-            dispatch1(t0 ? op.b[1] : op.b[0], [&](auto K) QK_AI { rb_mul_half<K.value>(v, f); });
+            dispatch2(b0, b1, [&](auto A, auto B) QK_AI { rb_cphase<A.value, B.value>(v, u); });
         }
-        return;
-    }
-    if (op.code == OP_CX && t0) {
-        const uint32_t c = tbit(tb, op.b[0]);
-        dispatch1(op.b[1], [&](auto K) QK_AI { rb_cswap<K.value>(v, c); });
-        return;
-    }
-    if (op.code == OP_PHRUN) {
+        break;
+    case OP_PHRUN: {
         // The run's factor is exp(i * sum of the angles of the partners that
         // are set): partners outside the block first (b[1] of them; a state
         // qubit, uniform per block), then partners on thread-index bits (a
@@ -1107,9 +1115,8 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
         // raw integer bits.  One sincos per thread, then the target half is
         // scaled once.
         using RR = decltype(V{}.x);
-        const V one{1, 0};
         RR ang = 0;
-        const int nout = op.b[1];
+        const int nout = b1;
         // four entries per step: their scalar loads are issued together
         int e = 0;
         for (; e + 4 <= nout; e += 4) {
@@ -1137,47 +1144,39 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
         RR sn, cs;
         sin_cos(ang, &sn, &cs);
         const V f{cs, sn};
-        if (t0) {
-            const V g = vsel(tbit(tb, op.b[0]) != 0, f, one);
+        if (thr(b0)) {
+            const V g = vsel(tbit(tb, b0) != 0, f, one);
             static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], g); });
         } else {
-            dispatch1(op.b[0], [&](auto K) QK_AI { rb_mul_half<K.value>(v, f); });
+            dispatch1(b0, [&](auto K) QK_AI { rb_mul_half<K.value>(v, f); });
         }
-        return;
+        break;
     }
-    switch (op.code) {
     case OP_BPHASE: {
+        const uint32_t s2 = s2f(), s3 = (uint32_t)(bb >> op.b[3]) & 1u;
         const V c = ld_coef(u + (op.k == 2 ? s2 + 2 * s3 : s2));
-        if (!(c.x == 1 && c.y == 0))
-            static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], c); });
+        if (!is_one(c)) static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], c); });
         break;
     }
     case OP_BPHRUN: {
-        // product of the entries' factors selected by the block's bits
+        // product of the entries' factors selected by the block's bits; the
+        // entry header holds the two qubits as raw bits (a | b << 8); -1
+        // factors (CZ) only flip a sign
         V f{1, 0};
+        uint32_t neg = 0;
         for (int e = 0; e < op.k; ++e) {
-            const V h = ld_coef(u + 5 * e);
-            const uint32_t qa = (uint32_t)h.x, qb = (uint32_t)h.y;
-            const uint32_t s = (uint32_t)((bb >> qa) & 1u) + 2u * (uint32_t)((bb >> qb) & 1u);
+            const uint32_t h = raw_code(u[5 * e].y);
+            const uint32_t s = (uint32_t)((bb >> (h & 0xffu)) & 1u) + 2u * (uint32_t)((bb >> (h >> 8)) & 1u);
             const V c = ld_coef(u + 5 * e + 1 + s);
-            if (!is_one(c)) f = cmul(f, c);
+            if (c.x == -1 && c.y == 0) neg ^= 1u;
+            else if (!is_one(c)) f = cmul(f, c);
         }
+        if (neg) f = V{-f.x, -f.y};
         if (!is_one(f)) static_for<0, kRbAmps>([&](auto I) QK_AI { v[I.value] = cmul(v[I.value], f); });
         break;
     }
-    case OP_DIAG1C: dispatch1(op.b[0], [&](auto K) QK_AI { rb_diag1<K.value>(v, u + 2 * s2); }); break;
-    case OP_XC:
-        if (s2) dispatch1(op.b[0], [&](auto K) QK_AI { rb_x<K.value>(v); });
-        break;
-    case OP_DENSE1: dispatch1(op.b[0], [&](auto K) QK_AI { rb_dense1<K.value>(v, u); }); break;
-    case OP_H: dispatch1(op.b[0], [&](auto K) QK_AI { rb_h<K.value>(v, u); }); break;
-    case OP_DIAG1: dispatch1(op.b[0], [&](auto K) QK_AI { rb_diag1<K.value>(v, u); }); break;
-    case OP_X: dispatch1(op.b[0], [&](auto K) QK_AI { rb_x<K.value>(v); }); break;
-    case OP_CX: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_cx<A.value, B.value>(v); }); break;
-    case OP_CZ: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_cz<A.value, B.value>(v); }); break;
-    case OP_CPHASE: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_cphase<A.value, B.value>(v, u); }); break;
-    case OP_DIAG2: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_diag2<A.value, B.value>(v, u); }); break;
-    case OP_SWAP: dispatch2(op.b[0], op.b[1], [&](auto A, auto B) QK_AI { rb_swap<A.value, B.value>(v); }); break;
+    case OP_DIAG2: dispatch2(b0, b1, [&](auto A, auto B) QK_AI { rb_diag2<A.value, B.value>(v, u); }); break;
+    case OP_SWAP: dispatch2(b0, b1, [&](auto A, auto B) QK_AI { rb_swap<A.value, B.value>(v); }); break;
     default: break;
     }
 }

@@ -638,12 +638,24 @@ void build_rb(qk_plan* P, PKernel& K)
             o.coef = first;
             continue;
         }
+        if (o.code == OP_BPHRUN) {
+            // entry headers: the two qubits as raw bits (a | b << 8)
+            const uint32_t first = (uint32_t)kc.size();
+            for (int e = 0; e < o.k; ++e) {
+                const cd h = P->coefs[o.coef + 5 * e];
+                kc.push_back(cd(0.0, 0.0));
+                raw.resize(kc.size(), -1);
+                raw.back() = (int64_t)h.real() | ((int64_t)h.imag() << 8);
+                for (int t = 1; t < 5; ++t) kc.push_back(P->coefs[o.coef + 5 * e + t]);
+            }
+            o.coef = first;
+            continue;
+        }
         int cnt = 0;
         switch (o.code) {
         case OP_DENSE1: case OP_H: case OP_DIAG2: case OP_DIAG1C: cnt = 4; break;
         case OP_DIAG1: cnt = 2; break;
         case OP_BPHASE: cnt = 2 << (o.k - 1); break;
-        case OP_BPHRUN: cnt = 5 * o.k; break;
         case OP_CPHASE: cnt = 1; break;
         case OP_DENSEK: cnt = 1 << (2 * o.k); break;
         default: cnt = 0; break;
