@@ -1220,9 +1220,9 @@ __device__ __forceinline__ uint32_t reg_deposit(const uint8_t* reg)
 // an imaginary plane, complex128 as four planes.  Consecutive lanes then touch
 // consecutive 4-byte banks; 8- or 16-byte element accesses would pair up banks
 // and take twice the LDS cycles.
-// Uniform copy of a program word (every lane reads the same address), so
-// that decisions on it are scalar branches.
-__device__ __forceinline__ uint32_t lds_uniform(const uint32_t* p) { return __builtin_amdgcn_readfirstlane(*p); }
+// Uniform copy of a program word (every lane reads the same address, in
+// LDS or global memory), so that decisions on it are scalar branches.
+__device__ __forceinline__ uint32_t uniform_word(const uint32_t* p) { return __builtin_amdgcn_readfirstlane(*p); }
 
 // Block index of thread t's register-0 amplitude in a layout given by its
 // thread-index bit map (uniform words tw[0..2] of a phase record):
@@ -1231,7 +1231,7 @@ template <int NT>
 __device__ __forceinline__ uint32_t thr_map(uint32_t t, const uint32_t* tw)
 {
     constexpr int NB = NT == 512 ? 9 : 8;
-    const uint32_t w0 = lds_uniform(tw), w1 = lds_uniform(tw + 1), w2 = lds_uniform(tw + 2);
+    const uint32_t w0 = uniform_word(tw), w1 = uniform_word(tw + 1), w2 = uniform_word(tw + 2);
     uint32_t out = 0;
     static_for<0, NB>([&](auto J) QK_AI {
         const uint32_t w = J.value < 4 ? w0 : J.value < 8 ? w1 : w2;
@@ -1397,10 +1397,10 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     // live in scalar registers across the loop.
     auto base_of = [&](uint64_t b) QK_AI {
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(prog + d.runs_off);
-        const uint32_t nr = lds_uniform(rw);
+        const uint32_t nr = uniform_word(rw);
         uint64_t o = 0;
         for (uint32_t r = 0; r < nr; ++r) {
-            const uint32_t w = lds_uniform(rw + 1 + r);
+            const uint32_t w = uniform_word(rw + 1 + r);
             o |= ((b >> (w & 0xffu)) & ((1ull << ((w >> 8) & 0xffu)) - 1)) << (w >> 16);
         }
         return o;
@@ -1419,7 +1419,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
         uint32_t tb = thr_map<NT>(tid, ldw + 3);   // block index of this thread's register 0 in layout cur
         for (int p = 0; p < d.n_phases; ++p) {
             const uint32_t* pw = reinterpret_cast<const uint32_t*>(prog + p * sizeof(Phase));
-            const uint32_t regw = lds_uniform(pw), lxw = lds_uniform(pw + 1), rng = lds_uniform(pw + 2);
+            const uint32_t regw = uniform_word(pw), lxw = uniform_word(pw + 1), rng = uniform_word(pw + 2);
             const uint8_t reg[4] = {(uint8_t)regw, (uint8_t)(regw >> 8), (uint8_t)(regw >> 16), (uint8_t)(regw >> 24)};
             const uint8_t lx[2] = {(uint8_t)lxw, (uint8_t)(lxw >> 8)};
             if (!same_layout(cur, clx, reg, lx) && d.uses_lds) {
@@ -1431,7 +1431,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
             }
             for (uint32_t o = rng & 0xffffu; o < (rng >> 16); ++o) {
                 const uint32_t* ow = reinterpret_cast<const uint32_t*>(gops + o * sizeof(Op));
-                const uint32_t w0 = lds_uniform(ow), w1 = lds_uniform(ow + 1);
+                const uint32_t w0 = uniform_word(ow), w1 = uniform_word(ow + 1);
                 Op op{};
                 op.code = (uint8_t)w0;
                 op.k = (uint8_t)(w0 >> 8);
@@ -1439,7 +1439,7 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
                 op.b[1] = (uint8_t)(w0 >> 24);
                 op.b[2] = (uint8_t)w1;
                 op.b[3] = (uint8_t)(w1 >> 8);
-                op.coef = lds_uniform(ow + 3);
+                op.coef = uniform_word(ow + 3);
                 rb_apply<FUSED>(v, op, coef, base, tb);
             }
         }
