@@ -1182,8 +1182,6 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
 }
 
 // LDS index swizzle: XOR the low 5 bits with higher bits so that lanes whose
-// block index differs only in high bits land in different banks.
-// LDS index swizzle: XOR the low 5 bits with higher bits so that lanes whose
 // block index differs only in high bits land in different banks.  Linear over
 // XOR: swz(a | b) = swz(a) ^ swz(b) for disjoint a, b.
 template <int ESZ>

@@ -393,7 +393,6 @@ void build_rb(qk_plan* P, PKernel& K)
     rb_io_reg(P->dtype, nt, io_reg);
     std::vector<Phase> ph;
     std::vector<Op> lops;
-    std::vector<std::array<uint8_t, 4>> lop_reg;   // register layout each operation runs in
     auto has = [](const uint8_t* reg, int nreg, int b) {
         for (int t = 0; t < nreg; ++t)
             if (reg[t] == b) return true;
@@ -421,7 +420,6 @@ void build_rb(qk_plan* P, PKernel& K)
         Op o = src;
         for (int u = 0; u < 7; ++u) o.b[u] = 0;
         lops.push_back(o);
-        lop_reg.push_back({p.reg[0], p.reg[1], p.reg[2], p.reg[3]});
         p.op_begin = 0;
         p.op_end = 1;
         ph.push_back(p);
@@ -544,7 +542,6 @@ void build_rb(qk_plan* P, PKernel& K)
                         cp.b[1] = (uint8_t)rp;
                         cp.coef = op.coef + 2 * e;
                         lops.push_back(cp);
-                        lop_reg.push_back({cur[0], cur[1], cur[2], cur[3]});
                     } else {
                         rest.push_back(P->coefs[op.coef + 2 * e]);
                         rest.push_back(P->coefs[op.coef + 2 * e + 1]);
@@ -556,7 +553,6 @@ void build_rb(qk_plan* P, PKernel& K)
                 P->coefs.insert(P->coefs.end(), rest.begin(), rest.end());
             }
             lops.push_back(lo);
-            lop_reg.push_back({cur[0], cur[1], cur[2], cur[3]});
         }
         if (!bruns.empty() && !open) {
             Phase p{};
@@ -568,7 +564,6 @@ void build_rb(qk_plan* P, PKernel& K)
         }
         for (const Op& r : bruns) {
             lops.push_back(r);
-            lop_reg.push_back({cur[0], cur[1], cur[2], cur[3]});
         }
         if (open) ph.back().op_end = (uint16_t)lops.size();
     }
@@ -621,7 +616,6 @@ void build_rb(qk_plan* P, PKernel& K)
     for (size_t oi = 0; oi < lops.size(); ++oi) {
         Op& o = lops[oi];
         if (o.code == OP_PHRUN) {
-            (void)lop_reg;
             const uint32_t first = (uint32_t)kc.size();
             int nout = 0;
             for (int pass = 0; pass < 2; ++pass)
