@@ -248,14 +248,14 @@ int qk_autotune(qk_ctx* ctx, int dtype, int n_lo, int n_hi, int reps, const char
         best_ko.dtype = dtype;
         for (int k_max : {2, 3, 4, 5}) {
             for (int m : {std::min(n, mcap), std::min(n, mcap - 1), std::min(n, mcap - 2)}) {
-                for (int ell : {0, 4}) {
+                for (int ell : {0, 7}) {
                     if (rc) break;
                     qk_kopts ko;
                     qk_kopts_default(&ko);
                     ko.dtype = dtype;
                     ko.k_max = k_max;
                     ko.m_max = std::max(m, 2);
-                    ko.ell = ell == 0 ? std::min(ko.m_max, dtype == QK_C64 ? 7 : 6) : std::min(ell, ko.m_max);
+                    ko.ell = ell == 0 ? std::min(ko.m_max, dtype == QK_C64 ? 4 : 6) : std::min(ell, ko.m_max);
                     if (ko.m_max <= ko.k_max) continue;
                     std::vector<qk_kopts> kos(copies, ko);
                     std::vector<double> t;
