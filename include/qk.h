@@ -187,7 +187,7 @@ typedef struct qk_kopts {
     int32_t m_max;         /* LDS kernels: active set bound, ell..14;
                               0 = 13 for complex64, 12 for complex128 (64 KiB blocks) */
     int32_t ell;           /* lowest qubits forced into every LDS kernel, 1..m_max;
-                              0 = 4 for complex64 (128-byte runs), 6 for complex128 (1 KiB) */
+                              0 = 4 (128-byte runs for complex64, 256-byte for complex128) */
     int32_t absorb_swaps;  /* relabel SWAP gates into the layout instead of running them */
     int32_t allow_fused;
     int32_t allow_lds;

@@ -39,7 +39,7 @@ import workloads as W  # noqa: E402
 
 
 def _defaults(dtype):
-    return (13, 4) if dtype == QK_C64 else (12, 6)
+    return (13, 4) if dtype == QK_C64 else (12, 4)
 
 
 def _family(n, rng):

@@ -255,7 +255,7 @@ int qk_autotune(qk_ctx* ctx, int dtype, int n_lo, int n_hi, int reps, const char
                     ko.dtype = dtype;
                     ko.k_max = k_max;
                     ko.m_max = std::max(m, 2);
-                    ko.ell = ell == 0 ? std::min(ko.m_max, dtype == QK_C64 ? 4 : 6) : std::min(ell, ko.m_max);
+                    ko.ell = ell == 0 ? std::min(ko.m_max, 4) : std::min(ell, ko.m_max);
                     if (ko.m_max <= ko.k_max) continue;
                     std::vector<qk_kopts> kos(copies, ko);
                     std::vector<double> t;

@@ -248,7 +248,7 @@ int costmodel_calibrate(qk_ctx* ctx, int n, int dtype, int reps, qk_cost_tables*
     qk_kopts_default(&ko);
     ko.dtype = dtype;
     ko.k_max = 7;
-    const int m_max = dtype == QK_C64 ? 13 : 12, ell = dtype == QK_C64 ? 4 : 6;   // the automatic ell
+    const int m_max = dtype == QK_C64 ? 13 : 12, ell = 4;   // the automatic ell
     qk_cost_tables t{};
     uint64_t seed = 12345;
     auto ang = [&]() { return 2.0 * M_PI * uniform01(seed); };

@@ -199,10 +199,11 @@ int resolve_opts(const qk_kopts* ko_in, int n, qk_kopts& ko, int& mblk)
     // 0 selects the defaults: blocks of 64 KiB (2^13 complex64 or 2^12
     // complex128 amplitudes) whose low run is 1 KiB (7 or 6 low qubits)
     if (ko.m_max == 0) ko.m_max = ko.dtype == QK_C64 ? 13 : 12;
-    // automatic ell: complex64 forces the 4 lowest qubits (128-byte runs, one
-    // line per 16 lanes; measured faster on the 32-qubit step than 1 KiB runs,
-    // because more gate qubits fit a block), complex128 the 6 lowest (1 KiB)
-    if (ko.ell == 0) ko.ell = ko.dtype == QK_C64 ? 4 : 6;
+    // automatic ell: the 4 lowest qubits (128-byte runs for complex64, one
+    // line per 16 lanes; 256-byte runs for complex128).  Measured faster than
+    // 1 KiB runs on 32-qubit complex64 and 30-qubit complex128 circuits,
+    // because more gate qubits fit a block.
+    if (ko.ell == 0) ko.ell = 4;
     if (ko.m_max < 2 || ko.m_max > kMaxBlockQubits) return fail(QK_EINVAL, "kernelize: m_max must be 2..14");
     if (ko.ell < 1 || ko.ell > ko.m_max) return fail(QK_EINVAL, "kernelize: ell must be 1..m_max");
     if (!ko.allow_fused && !ko.allow_lds) return fail(QK_EINVAL, "kernelize: no kernel type allowed");
