@@ -197,7 +197,7 @@ int resolve_opts(const qk_kopts* ko_in, int n, qk_kopts& ko, int& mblk)
     if (ko.dtype != QK_C64 && ko.dtype != QK_C128) return fail(QK_EINVAL, "kernelize: bad dtype");
     if (ko.k_max < 1 || ko.k_max > kMaxFusedQubits) return fail(QK_EINVAL, "kernelize: k_max must be 1..7");
     // 0 selects the defaults: blocks of 64 KiB (2^13 complex64 or 2^12
-    // complex128 amplitudes) whose low run is 1 KiB (7 or 6 low qubits)
+    // complex128 amplitudes)
     if (ko.m_max == 0) ko.m_max = ko.dtype == QK_C64 ? 13 : 12;
     // automatic ell: the 4 lowest qubits (128-byte runs for complex64, one
     // line per 16 lanes; 256-byte runs for complex128).  Measured faster than
