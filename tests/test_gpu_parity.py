@@ -1,6 +1,6 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
-Tolerances (derived from the arithmetic; the spec fidelity bars are
+Tolerances (derived from the arithmetic; the target fidelity bars are
 1 - F <= 1e-12 for complex128 and <= 1e-6 for complex64):
 * complex128: every gate is applied in FP64 (fused matrices are FP64 products),
   so after G gates the per-amplitude error is a few G * 2^-53 relative to the
