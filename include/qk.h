@@ -288,8 +288,10 @@ int kernelize_single(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, int t
 #define QK_NUM_FEATURES 20
 /* Feature vector of kernel i (QK_NUM_FEATURES floats): k, gate count,
  * class histogram (7), min/max/mean physical qubit, qubits below 6, diagonal
- * gates, fused one-hot, LDS one-hot, n, complex128 flag, k * fused,
- * gate count * LDS. */
+ * gates, fused one-hot, LDS one-hot, n, complex128 flag, k * fused, and for
+ * LDS kernels the register phases beyond the first, max(0, ceil(r / 6) - 1)
+ * with r the qubits some non-diagonal gate needs active (a CX control
+ * excluded); 0 for fused kernels. */
 int plan_kernel_features(const qk_plan* p, int64_t i, float* out);
 /* Launch kernel i of p on st once untimed, then reps times between HIP events
  * on the context's stream; *median_ms = median duration.  The state's
