@@ -103,6 +103,13 @@ int qk_sync(qk_ctx* ctx);
 const char* qk_last_error(void);
 /* Library version string, static storage. */
 const char* qk_version(void);
+/* Test hook: bound the number of workgroups of every persistent block launch
+ * (staged-block, register-blocked, permutation) to `groups` for all later
+ * launches in the process; 0 restores the default (all resident workgroups).
+ * With a small bound each workgroup walks many blocks, which is the path
+ * large states take, so small states can exercise it.  Results do not
+ * depend on the bound; QK_EINVAL for a negative value. */
+int qk_debug_set_max_groups(int groups);
 
 /* ---- state vectors ------------------------------------------------------ */
 /* hipMalloc 2^n amplitudes of dtype (8 or 16 bytes each), uninitialised, in
@@ -247,7 +254,9 @@ int plan_gate_source(const qk_plan* p, int64_t i, int64_t* out);
 int plan_final_layout(const qk_plan* p, int32_t* perm);
 /* Which cost model priced the plan: learned_used = 1 if the learned model's
  * predictions were used, learned_fallback = 1 if the learned model was
- * requested but no weights were loaded (analytic costs were used instead). */
+ * requested but analytic costs were used instead: no weights were loaded, or
+ * the plan's qubit count lies outside the range of qubit counts the model was
+ * trained on. */
 int plan_cost_model(const qk_plan* p, int* learned_used, int* learned_fallback);
 int plan_free(qk_plan* p);
 
@@ -318,13 +327,19 @@ typedef struct qk_train_report {
  * NULL for defaults. */
 int costmodel_train(qk_ctx* ctx, int dtype, const float* feats, const float* targets, int64_t count,
                     const qk_train_opts* opts, qk_train_report* report);
-/* Text file with the standardisation, parameters and an FNV-1a checksum;
- * load rejects a malformed or corrupted file with QK_EINVAL (the context then
- * keeps whatever model it had). */
+/* Text file with the standardisation, parameters, the per-feature range of
+ * the training rows (format version 2; version 1 files carry no range and are
+ * still accepted) and an FNV-1a checksum; load rejects a malformed or
+ * corrupted file with QK_EINVAL (the context then keeps whatever model it
+ * had). */
 int costmodel_save(qk_ctx* ctx, int dtype, const char* path);
 int costmodel_load(qk_ctx* ctx, int dtype, const char* path);
 int costmodel_unload(qk_ctx* ctx, int dtype);
 int costmodel_loaded(qk_ctx* ctx, int dtype, int* out);
+/* Per-feature minimum and maximum over the rows the loaded model of dtype was
+ * trained on (QK_NUM_FEATURES floats each).  QK_ESTATE when no model is
+ * loaded or its file recorded no range. */
+int costmodel_training_range(qk_ctx* ctx, int dtype, float* x_min, float* x_max);
 /* Predicted log(ps per amplitude) for cnt feature rows (device forward pass). */
 int costmodel_predict(qk_ctx* ctx, int dtype, const float* feats, int64_t cnt, float* out);
 /* Raw network pieces, for checking the device gradients: parameter count, and

@@ -40,12 +40,16 @@ UNPINNED = {
 }
 
 
+BUILD_FLAGS = ["-O3", "-march=native", "-std=gnu11", "-fopenmp", "-fPIC", "-shared"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (plain -O2, OpenMP, no host-specific ISA)."""
+    """Compile the C oracle with gcc (-O3 -march=native, OpenMP).  The
+    library is rebuilt on each machine that runs it, so the native ISA is
+    that machine's."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-                        _SRC, "-o", tmp, "-lm"], check=True)
+        subprocess.run(["gcc"] + BUILD_FLAGS + [_SRC, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -66,12 +70,19 @@ def lib():
         L.oracle_inner.restype = None
         L.oracle_inner.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(t: int) -> None:
+    """Number of OpenMP threads of later oracle runs."""
+    lib().oracle_set_threads(int(t))
 
 
 # ---------------------------------------------------------------------------
@@ -100,6 +111,23 @@ def run(circuit, psi: np.ndarray) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle rejected gate {-1 - rc}")
     return out
+
+
+def run_inplace(circuit, psi: np.ndarray, first: int = 0, count: int | None = None) -> None:
+    """Apply gates [first, first + count) of ``circuit`` to ``psi`` in place
+    (complex128, C-contiguous, 2^n): the same gate-by-gate evolution as
+    ``run`` without a copy of the state, for states that fill host memory."""
+    n = circuit.n_qubits
+    assert psi.dtype == np.complex128 and psi.flags.c_contiguous and psi.shape == (1 << n,)
+    total = len(circuit.gates)
+    count = total - first if count is None else count
+    assert 0 <= first and first + count <= total
+    if count == 0:
+        return
+    g = circuit.gates[first:first + count]
+    rc = lib().oracle_run(n, psi.ctypes.data, g.ctypes.data, count)
+    if rc != 0:
+        raise ValueError(f"oracle rejected gate {first - 1 - rc}")
 
 
 def basis(n: int, x: int = 0) -> np.ndarray:
@@ -148,6 +176,31 @@ def qft_basis_amplitudes(n: int, x: int, idx: np.ndarray) -> np.ndarray:
     prod = (prod + ((xh * yl) << np.uint64(32)) + ((xl * yh) << np.uint64(32))) & mask
     ph = 2.0 * np.pi * (prod.astype(np.float64) / float(N))
     return np.exp(1j * ph) / math.sqrt(float(N))
+
+
+def qft_basis_overlap(n: int, x: int, chunks) -> complex:
+    """<QFT|x>, psi> over the full state, psi given as consecutive chunks
+    (offset, complex array) covering [0, 2^n) in any order: the closed form
+    sum_y exp(-2 pi i x y / 2^n) psi_y / 2^(n/2).
+
+    With y = y0 + j the phase factors as exp(2 pi i x y0 / 2^n) times
+    exp(2 pi i x j / 2^n); both factors come from ``qft_basis_amplitudes``
+    (exact integer phase reduction), the second computed once per chunk
+    length, so each chunk costs one inner product."""
+    N = 1 << n
+    total = 0j
+    seen = 0
+    base_cache = {}
+    for y0, part in chunks:
+        part = np.asarray(part)
+        L = part.size
+        if L not in base_cache:
+            base_cache[L] = qft_basis_amplitudes(n, x, np.arange(L, dtype=np.uint64)) * math.sqrt(float(N))
+        head = qft_basis_amplitudes(n, x, np.array([y0], np.uint64))[0]   # includes the 1/sqrt(N)
+        total += np.conj(head) * np.vdot(base_cache[L], part.astype(np.complex128, copy=False))
+        seen += L
+    assert seen == N, "chunks must cover the state once"
+    return complex(total)
 
 
 def qft_basis_state(n: int, x: int) -> np.ndarray:

@@ -153,3 +153,14 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads used by later parallel loops (1 = a single core). */
+void oracle_set_threads(int t)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}

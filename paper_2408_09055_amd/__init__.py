@@ -107,6 +107,7 @@ _dbl_p = ctypes.POINTER(ctypes.c_double)
 
 _SIGS = {
     "qk_ctx_create": [_P, _u32, _PP], "qk_ctx_free": [_P], "qk_sync": [_P],
+    "qk_debug_set_max_groups": [ctypes.c_int],
     "sv_alloc": [_P, ctypes.c_int, ctypes.c_int, _PP],
     "sv_wrap": [_P, _P, ctypes.c_int, ctypes.c_int, _PP], "sv_free": [_P],
     "sv_device_ptr": [_P, _PP], "sv_info": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
@@ -135,6 +136,7 @@ _SIGS = {
     "costmodel_train": [_P, ctypes.c_int, _P, _P, _i64, ctypes.POINTER(qk_train_opts), ctypes.POINTER(qk_train_report)],
     "costmodel_save": [_P, ctypes.c_int, ctypes.c_char_p], "costmodel_load": [_P, ctypes.c_int, ctypes.c_char_p],
     "costmodel_unload": [_P, ctypes.c_int], "costmodel_loaded": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "costmodel_training_range": [_P, ctypes.c_int, _P, _P],
     "costmodel_predict": [_P, ctypes.c_int, _P, _i64, _P],
     "mlp_forward_backward": [_P, _P, _P, _P, _i64, _P, _P, _P],
     "mlp_adam_step": [_P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int],
@@ -172,6 +174,11 @@ def _check(rc: int):
 
 def version() -> str:
     return _lib.qk_version().decode()
+
+
+def set_max_groups(groups: int):
+    """Test hook: bound the workgroups of persistent launches (0 = default)."""
+    _check(_lib.qk_debug_set_max_groups(int(groups)))
 
 
 # ---------------------------------------------------------------- options
@@ -282,6 +289,13 @@ class Context:
         v = ctypes.c_int()
         _check(_lib.costmodel_loaded(self.h, dtype, ctypes.byref(v)))
         return bool(v.value)
+
+    def training_range(self, dtype: int):
+        """(x_min, x_max) over the loaded model's training rows, per feature."""
+        lo = np.zeros(NUM_FEATURES, np.float32)
+        hi = np.zeros(NUM_FEATURES, np.float32)
+        _check(_lib.costmodel_training_range(self.h, dtype, lo.ctypes.data, hi.ctypes.data))
+        return lo, hi
 
     def predict(self, dtype: int, feats: np.ndarray) -> np.ndarray:
         f = np.ascontiguousarray(feats, np.float32).reshape(-1, NUM_FEATURES)

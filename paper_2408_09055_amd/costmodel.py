@@ -29,7 +29,7 @@ import time
 
 import numpy as np
 
-from . import (QK_C64, QK_C128, QK_KERNEL_FUSED, QK_KERNEL_LDS, Context, QkError, State, costmodel_path,
+from . import (NUM_FEATURES, QK_C64, QK_C128, QK_KERNEL_FUSED, QK_KERNEL_LDS, Context, QkError, State, costmodel_path,
                kernelize_single, kopts, lib, time_kernel)
 
 _ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -193,6 +193,47 @@ def analytic_prediction(feats: np.ndarray, tables_by_n: dict) -> np.ndarray:
     return out
 
 
+def _fnv1a(arr, h: int = 1469598103934665603) -> int:
+    """FNV-1a over the float32 bytes of arr (the model files' checksum)."""
+    for b in np.asarray(arr, np.float32).tobytes():
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def record_n_range(path: str, n_lo: int, n_hi: int):
+    """Rewrite a version-1 model file (no training range) as version 2 with
+    the range of state sizes it was trained on: feature 16 (n) in
+    [n_lo, n_hi]; the other features were not recorded and are left
+    unbounded.  The checksum is recomputed over the same numbers the library
+    hashes."""
+    rows = [l.split() for l in open(path) if l.strip()]
+    keys = {r[0]: r[1:] for r in rows}
+    if keys.get("qk-costmodel") != ["1"]:
+        raise ValueError(f"{path}: not a version-1 model file")
+    f32 = lambda k: np.array([np.float32(x) for x in keys[k]], np.float32)
+    big = np.float32(3.0e38)
+    lo = np.full(NUM_FEATURES, -big, np.float32)
+    hi = np.full(NUM_FEATURES, big, np.float32)
+    lo[16], hi[16] = n_lo, n_hi
+    h = 1469598103934665603
+    for k in ("x_mean", "x_std", "y_mean", "y_std", "params"):
+        h = _fnv1a(f32(k), h)
+    h = _fnv1a(lo, h)
+    h = _fnv1a(hi, h)
+    out = []
+    for r in rows:
+        if r[0] == "qk-costmodel":
+            out.append("qk-costmodel 2")
+        elif r[0] == "checksum":
+            out.append("x_min " + " ".join(f"{v:.9g}" for v in lo))
+            out.append("x_max " + " ".join(f"{v:.9g}" for v in hi))
+            out.append(f"checksum {h:016x}")
+        else:
+            out.append(" ".join(r))
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
@@ -203,7 +244,12 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--dump", default=None, help="save the dataset (.npz)")
     ap.add_argument("--budget", type=float, default=None, help="collection time limit in seconds")
+    ap.add_argument("--record-n-range", nargs=3, metavar=("FILE", "N_LO", "N_HI"), default=None,
+                    help="upgrade a version-1 model file with the n range it was trained on, then exit")
     args = ap.parse_args()
+    if args.record_n_range:
+        record_n_range(args.record_n_range[0], int(args.record_n_range[1]), int(args.record_n_range[2]))
+        return
     dtype = QK_C64 if args.dtype == "c64" else QK_C128
     ctx = Context()
     tables = {}

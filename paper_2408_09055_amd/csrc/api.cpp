@@ -245,7 +245,14 @@ extern "C" {
 
 const char* qk_last_error(void) { return g_err.c_str(); }
 
-const char* qk_version(void) { return "qk 0.1 (gfx950)"; }
+const char* qk_version(void) { return "qk 0.2 (gfx950)"; }
+
+int qk_debug_set_max_groups(int groups)
+{
+    if (groups < 0) return fail(QK_EINVAL, "qk_debug_set_max_groups: negative bound");
+    set_max_groups((uint32_t)groups);
+    return QK_OK;
+}
 
 void qk_kopts_default(qk_kopts* ko)
 {

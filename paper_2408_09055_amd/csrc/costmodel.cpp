@@ -68,6 +68,22 @@ uint64_t fnv1a(const float* p, size_t n, uint64_t h = 1469598103934665603ull)
     return h;
 }
 
+// FNV-1a over the model's numbers in file order (the training range only
+// when the file records one).
+uint64_t model_checksum(const MlpModel& M)
+{
+    uint64_t h = fnv1a(M.x_mean, kMlpF);
+    h = fnv1a(M.x_std, kMlpF, h);
+    h = fnv1a(&M.y_mean, 1, h);
+    h = fnv1a(&M.y_std, 1, h);
+    h = fnv1a(M.params.data(), kMlpParams, h);
+    if (M.has_range) {
+        h = fnv1a(M.x_min, kMlpF, h);
+        h = fnv1a(M.x_max, kMlpF, h);
+    }
+    return h;
+}
+
 // Time one launch of kernel i of P on st: warm-up, then the median of reps.
 int time_launch(qk_ctx* ctx, const qk_plan* P, int64_t i, qk_state* st, int reps, double* ms, int n_ops_override)
 {
@@ -170,6 +186,15 @@ int upload_model(qk_ctx* ctx, MlpModel& M)
 }  // namespace
 
 bool learned_available(qk_ctx* ctx, int dtype) { return mlp_ready(ctx, dtype); }
+
+bool learned_in_range(const qk_ctx* ctx, int dtype, int n)
+{
+    if (!mlp_ready(ctx, dtype)) return false;
+    const MlpModel& M = ctx->mlp[dtype];
+    if (!M.has_range) return true;
+    // feature 16 is n: the model has only seen states of these sizes
+    return (float)n >= M.x_min[16] && (float)n <= M.x_max[16];
+}
 
 int learned_predict(qk_ctx* ctx, int dtype, const float* feats, int64_t cnt, float* out)
 {
@@ -399,6 +424,17 @@ int costmodel_train(qk_ctx* ctx, int dtype, const float* feats, const float* tar
         M.x_mean[f] = (float)mean;
         M.x_std[f] = var > 1e-12 ? (float)std::sqrt(var) : 1.0f;
     }
+    for (int f = 0; f < kMlpF; ++f) {
+        float lo = feats[(int64_t)order[0] * kMlpF + f], hi = lo;
+        for (int64_t r = 1; r < n_tr; ++r) {
+            const float v = feats[(int64_t)order[r] * kMlpF + f];
+            lo = std::min(lo, v);
+            hi = std::max(hi, v);
+        }
+        M.x_min[f] = lo;
+        M.x_max[f] = hi;
+    }
+    M.has_range = true;
     {
         double s1 = 0, s2 = 0;
         for (int64_t r = 0; r < n_tr; ++r) { const double v = targets[order[r]]; s1 += v; s2 += v * v; }
@@ -526,6 +562,17 @@ int costmodel_predict(qk_ctx* ctx, int dtype, const float* feats, int64_t cnt, f
     return QK_OK;
 }
 
+int costmodel_training_range(qk_ctx* ctx, int dtype, float* x_min, float* x_max)
+{
+    if (!ctx || !x_min || !x_max || (dtype != QK_C64 && dtype != QK_C128))
+        return fail(QK_EINVAL, "costmodel_training_range: bad argument");
+    const MlpModel& M = ctx->mlp[dtype];
+    if (!M.loaded || !M.has_range) return fail(QK_ESTATE, "costmodel_training_range: no model with a recorded range");
+    std::memcpy(x_min, M.x_min, sizeof(float) * kMlpF);
+    std::memcpy(x_max, M.x_max, sizeof(float) * kMlpF);
+    return QK_OK;
+}
+
 int costmodel_loaded(qk_ctx* ctx, int dtype, int* out)
 {
     if (!ctx || !out) return fail(QK_EINVAL, "costmodel_loaded: null argument");
@@ -546,18 +593,18 @@ int costmodel_save(qk_ctx* ctx, int dtype, const char* path)
         for (int i = 0; i < n; ++i) { std::snprintf(buf, sizeof buf, " %.9g", v[i]); f << buf; }
         f << "\n";
     };
-    f << "qk-costmodel 1\narch gfx950\ndtype " << (dtype == QK_C64 ? "c64" : "c128") << "\n";
+    f << "qk-costmodel " << (M.has_range ? 2 : 1) << "\narch gfx950\ndtype " << (dtype == QK_C64 ? "c64" : "c128") << "\n";
     f << "features " << kMlpF << "\nhidden " << kMlpH << "\n";
     put("x_mean", M.x_mean, kMlpF);
     put("x_std", M.x_std, kMlpF);
     put("y_mean", &M.y_mean, 1);
     put("y_std", &M.y_std, 1);
     put("params", M.params.data(), kMlpParams);
-    uint64_t h = fnv1a(M.x_mean, kMlpF);
-    h = fnv1a(M.x_std, kMlpF, h);
-    h = fnv1a(&M.y_mean, 1, h);
-    h = fnv1a(&M.y_std, 1, h);
-    h = fnv1a(M.params.data(), kMlpParams, h);
+    if (M.has_range) {
+        put("x_min", M.x_min, kMlpF);
+        put("x_max", M.x_max, kMlpF);
+    }
+    const uint64_t h = model_checksum(M);
     std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
     f << "checksum " << buf << "\n";
     if (!f) return fail(QK_EINVAL, "costmodel_save: write failed");
@@ -576,7 +623,7 @@ int costmodel_load(qk_ctx* ctx, int dtype, const char* path)
     std::string line, key, dt;
     int feat = 0, hid = 0, version = 0;
     unsigned long long ck = 0;
-    bool have_ck = false, have_p = false;
+    bool have_ck = false, have_p = false, have_lo = false, have_hi = false;
     auto read_vals = [&](std::istringstream& is, float* v, int n) {
         for (int i = 0; i < n; ++i) if (!(is >> v[i])) return false;
         std::string extra;
@@ -586,7 +633,7 @@ int costmodel_load(qk_ctx* ctx, int dtype, const char* path)
     while (ok && std::getline(f, line)) {
         std::istringstream is(line);
         if (!(is >> key)) continue;
-        if (key == "qk-costmodel") ok = (bool)(is >> version) && version == 1;
+        if (key == "qk-costmodel") ok = (bool)(is >> version) && (version == 1 || version == 2);
         else if (key == "arch") { std::string a; ok = (bool)(is >> a) && a == "gfx950"; }
         else if (key == "dtype") ok = (bool)(is >> dt) && dt == (dtype == QK_C64 ? "c64" : "c128");
         else if (key == "features") ok = (bool)(is >> feat) && feat == kMlpF;
@@ -596,16 +643,18 @@ int costmodel_load(qk_ctx* ctx, int dtype, const char* path)
         else if (key == "y_mean") ok = read_vals(is, &M.y_mean, 1);
         else if (key == "y_std") ok = read_vals(is, &M.y_std, 1);
         else if (key == "params") { ok = read_vals(is, M.params.data(), kMlpParams); have_p = ok; }
+        else if (key == "x_min" && version == 2) { ok = read_vals(is, M.x_min, kMlpF); have_lo = ok; }
+        else if (key == "x_max" && version == 2) { ok = read_vals(is, M.x_max, kMlpF); have_hi = ok; }
         else if (key == "checksum") { std::string h; ok = (bool)(is >> h); if (ok) { ck = std::stoull(h, nullptr, 16); have_ck = true; } }
         else ok = false;
     }
-    if (!ok || version != 1 || !have_p || !have_ck || feat != kMlpF || hid != kMlpH)
+    if (!ok || (version != 1 && version != 2) || !have_p || !have_ck || feat != kMlpF || hid != kMlpH ||
+        (version == 2 && !(have_lo && have_hi)))
         return fail(QK_EINVAL, std::string("costmodel_load: malformed model file ") + path);
-    uint64_t h = fnv1a(M.x_mean, kMlpF);
-    h = fnv1a(M.x_std, kMlpF, h);
-    h = fnv1a(&M.y_mean, 1, h);
-    h = fnv1a(&M.y_std, 1, h);
-    h = fnv1a(M.params.data(), kMlpParams, h);
+    M.has_range = version == 2;
+    for (int i = 0; M.has_range && i < kMlpF; ++i)
+        if (!(M.x_min[i] <= M.x_max[i])) return fail(QK_EINVAL, "costmodel_load: bad training range");
+    const uint64_t h = model_checksum(M);
     if (h != ck) return fail(QK_EINVAL, std::string("costmodel_load: checksum mismatch in ") + path);
     for (int i = 0; i < kMlpF; ++i)
         if (!(M.x_std[i] > 0)) return fail(QK_EINVAL, "costmodel_load: bad standardisation");

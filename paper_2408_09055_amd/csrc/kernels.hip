@@ -1725,7 +1725,21 @@ uint32_t grid_for(uint64_t nblocks)
     return (uint32_t)(nblocks < (1ull << 30) ? nblocks : (1ull << 30));
 }
 
+// Upper bound on the workgroups of the persistent block launches (0 = none):
+// with a small bound each workgroup walks many blocks, which is the path the
+// launches take on large states.
+uint32_t g_max_groups = 0;
+
+uint32_t persistent_grid(uint64_t nblocks, uint64_t resident)
+{
+    uint64_t g = std::min<uint64_t>(nblocks, resident);
+    if (g_max_groups) g = std::min<uint64_t>(g, g_max_groups);
+    return (uint32_t)std::max<uint64_t>(g, 1);
+}
+
 }  // namespace
+
+void set_max_groups(uint32_t g) { g_max_groups = g; }
 
 size_t block_lds_bytes(int dtype, int m, int /*ell0*/)
 {
@@ -1768,7 +1782,7 @@ template <typename C, typename F>
 int launch_one(F* f, C* psi, const BlockDesc& d, const Op* ops, const void* coef, size_t lds, hipStream_t s)
 {
     const uint64_t res = resident_groups(reinterpret_cast<const void*>(f), lds);
-    const dim3 grid((uint32_t)std::min<uint64_t>(d.nblocks, res)), block(kNT);
+    const dim3 grid(persistent_grid(d.nblocks, res)), block(kNT);
     hipLaunchKernelGGL(f, grid, block, lds, s, psi, d, ops, (const C*)coef);
     return (int)hipGetLastError();
 }
@@ -1857,7 +1871,7 @@ int launch_rb_typed(void* psi, const RbDesc& d, const void* prog, hipStream_t s)
     const size_t lds = d.prog_bytes + (size_t)NT * 16 + (d.uses_lds ? ((size_t)sizeof(C) << d.b.m) : 0);
     auto f = d.fused ? k_block_rb<C, NT, true> : k_block_rb<C, NT, false>;
     const uint64_t res = resident_groups(reinterpret_cast<const void*>(f), lds, NT);
-    const dim3 grid((uint32_t)std::min<uint64_t>(d.b.nblocks, res)), block(NT);
+    const dim3 grid(persistent_grid(d.b.nblocks, res)), block(NT);
     hipLaunchKernelGGL(f, grid, block, lds, s, (C*)psi, d, (const uint8_t*)prog);
     return (int)hipGetLastError();
 }
@@ -1895,7 +1909,7 @@ int launch_permute_pairs(int dtype, void* psi, const PermPairDesc& d, void* stre
     const void* f = dtype == QK_C128 ? reinterpret_cast<const void*>(k_permute_pairs<double2>)
                                      : reinterpret_cast<const void*>(k_permute_pairs<float2>);
     const uint64_t res = resident_groups(f, lds);
-    const dim3 grid((uint32_t)std::min<uint64_t>(d.ntiles, res)), block(kNT);
+    const dim3 grid(persistent_grid(d.ntiles, res)), block(kNT);
     if (dtype == QK_C128) hipLaunchKernelGGL(k_permute_pairs<double2>, grid, block, lds, s, (double2*)psi, d);
     else hipLaunchKernelGGL(k_permute_pairs<float2>, grid, block, lds, s, (float2*)psi, d);
     return (int)hipGetLastError();
@@ -1907,11 +1921,11 @@ int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, voi
     hipStream_t s = (hipStream_t)stream;
     if (dtype == QK_C128) {
         const uint64_t res = resident_groups(reinterpret_cast<const void*>(k_permute<double2>), lds);
-        hipLaunchKernelGGL(k_permute<double2>, dim3((uint32_t)std::min<uint64_t>(d.nblocks, res)), dim3(kNT), lds, s,
+        hipLaunchKernelGGL(k_permute<double2>, dim3(persistent_grid(d.nblocks, res)), dim3(kNT), lds, s,
                            (const double2*)src, (double2*)dst, d);
     } else {
         const uint64_t res = resident_groups(reinterpret_cast<const void*>(k_permute<float2>), lds);
-        hipLaunchKernelGGL(k_permute<float2>, dim3((uint32_t)std::min<uint64_t>(d.nblocks, res)), dim3(kNT), lds, s,
+        hipLaunchKernelGGL(k_permute<float2>, dim3(persistent_grid(d.nblocks, res)), dim3(kNT), lds, s,
                            (const float2*)src, (float2*)dst, d);
     }
     return (int)hipGetLastError();

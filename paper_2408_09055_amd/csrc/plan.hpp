@@ -43,6 +43,10 @@ uint64_t need_mask(const CGate& g, bool insular);
 // Returns QK_OK or an error (then the planner falls back to analytic costs).
 int learned_predict(qk_ctx* ctx, int dtype, const float* feats, int64_t cnt, float* out);
 bool learned_available(qk_ctx* ctx, int dtype);
+// Whether an n-qubit plan lies inside the learned model's training range
+// (the state size is a feature; a model without a recorded range accepts
+// every n).  Outside it the planner falls back to the analytic model.
+bool learned_in_range(const qk_ctx* ctx, int dtype, int n);
 
 // Analytic tables used when a context has none for (n, dtype).
 qk_cost_tables default_tables(int n, int dtype);

@@ -996,7 +996,9 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
 
     // ---- learned costs replace the analytic ones for every feasible entry
     if (ko.cost_model == QK_COST_LEARNED) {
-        if (!learned_available(ctx, ko.dtype)) {
+        // the analytic model stands in when no model is loaded or the state
+        // size lies outside the sizes the model was trained on
+        if (!learned_available(ctx, ko.dtype) || !learned_in_range(ctx, ko.dtype, n)) {
             P->learned_fallback = true;
         } else {
             std::vector<float> feats;

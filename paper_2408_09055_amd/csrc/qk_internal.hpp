@@ -186,6 +186,8 @@ int launch_gather(int dtype, const void* psi, const uint64_t* idx, uint64_t cnt,
 size_t block_lds_bytes(int dtype, int m, int ell0);
 // Whether the matrix-core fused kernel handles K kernel bits in a 2^m block.
 bool mfma_ok(int K, int m);
+// Bound on the workgroups of every persistent block launch (0 = none).
+void set_max_groups(uint32_t g);
 
 }  // namespace qk
 
@@ -197,6 +199,11 @@ struct MlpModel {
     float x_std[20] = {0};
     float y_mean = 0.f;
     float y_std = 1.f;
+    // per-feature range of the rows the model was trained on (version 2
+    // model files); has_range = false for older files, which record none
+    bool has_range = false;
+    float x_min[20] = {0};
+    float x_max[20] = {0};
     std::vector<float> params;
     float* d_params = nullptr;   // device copy (owned by the context)
 };

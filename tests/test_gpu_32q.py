@@ -1,16 +1,22 @@
-"""Full-size parity on the benchmark workload (32 qubits, the launch
-configuration bench.py times): sampled amplitudes against closed forms (QFT
-of a basis state, GHZ) and against the exact MPS oracle (random layered),
-plus invariants that hold at any size (norm, C^dagger C = I).
+"""Full-size parity on the benchmark workload: the exact plans bench.py times
+(32 qubits; analytic costs calibrated on this device and the learned model;
+complex64 and complex128), run through the same entry points.
 
-Tolerances: complex64 -- sampled 1 - F <= 1e-6 and per-amplitude relative
-error <= 1e-4 (FP32 rounding over ~500 gates); complex128 -- sampled
-1 - F <= 1e-12 and relative error <= 1e-10."""
-import math
+* QFT-32 from a seeded basis state and GHZ-32: full-state 1 - F over all 2^32
+  amplitudes against the closed forms, streamed to the host in chunks
+  (``tests/fullstate.py``); GHZ also keeps every interior amplitude exactly 0.
+* RL-32 (20 layers, seed 31): 65,536 + 2 sampled amplitudes against the exact
+  MPS oracle (bond dimension 1024), computed once for all plans.
+* Invariants at any size: FP64 norm, and C^dagger C |0> = |0> for RL.
+
+Bars: complex64 1 - F <= 1e-6 (sampled for RL, and per-amplitude relative
+error <= 1e-4 there); complex128 1 - F <= 1e-12 (relative error <= 1e-10)."""
+import time
 
 import numpy as np
 import pytest
 
+import fullstate
 import oracle
 import workloads as W
 
@@ -18,6 +24,12 @@ pytestmark = pytest.mark.gpu
 qk = pytest.importorskip("paper_2408_09055_amd")
 
 N_Q = 32
+MODELS = [("analytic", qk.QK_COST_ANALYTIC), ("learned", qk.QK_COST_LEARNED)]
+DTYPES = [qk.QK_C64, qk.QK_C128]
+
+
+def _bar(dtype):
+    return (1e-12, 1e-10) if dtype == qk.QK_C128 else (1e-6, 1e-4)
 
 
 @pytest.fixture(scope="module")
@@ -25,60 +37,87 @@ def ctx():
     import torch
     assert torch.cuda.is_available()
     c = qk.Context()
+    for dt in DTYPES:
+        c.calibrate(N_Q, dt, reps=3)
+        c.load_costmodel(dt)
     yield c
     c.close()
 
 
-def _sampled_loss(got, ref):
-    ov = np.vdot(ref, got)
-    return 1.0 - abs(ov) ** 2 / (np.vdot(got, got).real * np.vdot(ref, ref).real)
+@pytest.fixture(scope="module")
+def rl_ref():
+    circ = W.random_layered(N_Q, 20, 31)
+    idx = W.sample_indices(N_Q, 65536, 9)
+    t0 = time.time()
+    parts = []
+    for s in range(0, idx.size, 8192):
+        parts.append(oracle.mps_amplitudes(circ, idx[s:s + 8192], chunk=8192))
+        print(f"mps rl32: {s + parts[-1].size}/{idx.size} samples, {time.time() - t0:.0f} s", flush=True)
+    return circ, idx, np.concatenate(parts)
 
 
-def _check(got, ref, dtype, what):
-    loss = _sampled_loss(got, ref)
-    rel = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300))
-    bar_f, bar_r = (1e-12, 1e-10) if dtype == qk.QK_C128 else (1e-6, 1e-4)
-    print(f"{what}: sampled 1-F={loss:.3e} max rel err={rel:.3e}", flush=True)
-    assert loss <= bar_f and rel <= bar_r, what
+def _plan(ctx, circ, dtype, cm):
+    plan = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, cost_model=cm))
+    if cm == qk.QK_COST_LEARNED and ctx.costmodel_loaded(dtype):
+        assert plan.cost_model()["learned_used"]
+    return plan
 
 
-@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
-def test_qft32_basis_sampled(ctx, dtype):
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("model,cm", MODELS)
+def test_qft32_full_state(ctx, dtype, model, cm):
     x = W.random_basis_index(N_Q, 30)
+    plan = _plan(ctx, W.qft(N_Q), dtype, cm)
     st = qk.sv_alloc(ctx, N_Q, dtype)
     st.init_basis(x)
-    qk.simulate(ctx, W.qft(N_Q), st, qk.kopts(dtype=dtype))
-    idx = W.sample_indices(N_Q, 65536, 7)
-    got = st.gather(idx)
-    _check(got, oracle.qft_basis_amplitudes(N_Q, x, idx), dtype, f"qft32 dtype={dtype}")
-    assert abs(st.norm2() - 1.0) <= (1e-12 if dtype == qk.QK_C128 else 1e-5)
+    qk.execute_plan(ctx, plan, st)
+    r = fullstate.qft_fidelity(st, x)
+    print(f"qft32 {model} dtype={dtype}: {len(plan)} kernels, full-state 1-F={r['one_minus_f']:.3e} "
+          f"norm2={r['norm2']:.15f}", flush=True)
+    assert r["one_minus_f"] <= _bar(dtype)[0]
+    assert abs(r["norm2"] - 1.0) <= (1e-12 if dtype == qk.QK_C128 else 1e-5)
     st.free()
 
 
-def test_ghz32_exact(ctx):
-    st = qk.sv_alloc(ctx, N_Q, qk.QK_C64)
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("model,cm", MODELS)
+def test_ghz32_full_state(ctx, dtype, model, cm):
+    plan = _plan(ctx, W.ghz(N_Q), dtype, cm)
+    st = qk.sv_alloc(ctx, N_Q, dtype)
     st.init_basis(0)
-    qk.simulate(ctx, W.ghz(N_Q), st, qk.kopts(dtype=qk.QK_C64))
-    idx = W.sample_indices(N_Q, 4096, 8)
-    got = st.gather(idx)
-    ref = oracle.ghz_amplitudes(N_Q, idx)
-    assert np.array_equal(got == 0, ref == 0)
-    assert np.max(np.abs(got - ref)) <= 1e-7
+    qk.execute_plan(ctx, plan, st)
+    r = fullstate.ghz_fidelity(st)
+    print(f"ghz32 {model} dtype={dtype}: {len(plan)} kernels, full-state 1-F={r['one_minus_f']:.3e} "
+          f"nonzero interior={r['nonzero_interior']}", flush=True)
+    assert r["nonzero_interior"] == 0
+    assert r["one_minus_f"] <= _bar(dtype)[0]
     st.free()
 
 
-def test_rl32_mps_sampled_and_inverse(ctx):
-    circ = W.random_layered(N_Q, 20, 31)
-    st = qk.sv_alloc(ctx, N_Q, qk.QK_C64)
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("model,cm", MODELS)
+def test_rl32_mps_sampled(ctx, rl_ref, dtype, model, cm):
+    circ, idx, ref = rl_ref
+    plan = _plan(ctx, circ, dtype, cm)
+    st = qk.sv_alloc(ctx, N_Q, dtype)
     st.init_basis(0)
-    qk.simulate(ctx, circ, st, qk.kopts(dtype=qk.QK_C64))
-    idx = W.sample_indices(N_Q, 2048, 9)
+    qk.execute_plan(ctx, plan, st)
     got = st.gather(idx)
-    ref = oracle.mps_amplitudes(circ, idx, chunk=1024)
-    _check(got, ref, qk.QK_C64, "rl32x20 (MPS)")
-    assert abs(st.norm2() - 1.0) <= 1e-5
-    # C^dagger C |0> = |0>
-    qk.simulate(ctx, circ.inverse(), st, qk.kopts(dtype=qk.QK_C64))
-    a0 = st.gather(np.array([0, 1, (1 << N_Q) - 1], np.uint64))
-    assert abs(a0[0] - 1.0) <= 1e-4 and np.max(np.abs(a0[1:])) <= 1e-4
+    loss = fullstate.sampled_fidelity(got, ref)
+    rel = float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)))
+    norm = st.norm2()
+    print(f"rl32x20 {model} dtype={dtype}: {len(plan)} kernels, sampled 1-F={loss:.3e} (65538 amplitudes) "
+          f"max rel err={rel:.3e} norm drift={abs(norm - 1):.2e}", flush=True)
+    bar_f, bar_r = _bar(dtype)
+    assert loss <= bar_f and rel <= bar_r
+    assert abs(norm - 1.0) <= (1e-12 if dtype == qk.QK_C128 else 1e-5)
+    if model == "learned":
+        # C^dagger C |0> = |0>
+        qk.simulate(ctx, circ.inverse(), st, qk.kopts(dtype=dtype))
+        a0 = st.gather(np.array([0, 1, (1 << N_Q) - 1], np.uint64))
+        tol = 1e-10 if dtype == qk.QK_C128 else 1e-4
+        assert abs(a0[0] - 1.0) <= tol and np.max(np.abs(a0[1:])) <= tol
     st.free()

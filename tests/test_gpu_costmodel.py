@@ -206,3 +206,63 @@ def test_learned_request_without_weights_falls_back(ctx):
     ctx.unload_costmodel(0)
     plan = qk.kernelize(ctx, W.qft(10), qk.kopts(dtype=0, cost_model=qk.QK_COST_LEARNED))
     assert plan.cost_model() == {"learned_used": False, "learned_fallback": True}
+
+
+def _append_range(path, lo, hi):
+    """Turn a version-1 file written by _write_model into version 2 with the
+    given per-feature training range (checksum extended over both arrays)."""
+    rows = [l.rstrip("\n") for l in open(path)]
+    h = int(rows[-1].split()[1], 16)
+    for arr in (lo, hi):
+        for v in np.asarray(arr, np.float32):
+            for byte in struct.pack("<f", float(v)):
+                h ^= byte
+                h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    fmt = lambda key, vals: key + "".join(f" {float(np.float32(v)):.9g}" for v in vals)
+    rows = ["qk-costmodel 2"] + rows[1:-1] + [fmt("x_min", lo), fmt("x_max", hi), f"checksum {h:016x}"]
+    open(path, "w").write("\n".join(rows) + "\n")
+
+
+def test_learned_model_outside_training_range_falls_back(ctx, tmp_path):
+    """A model trained on states of 20..24 qubits prices plans of those sizes
+    and hands 16- and 28-qubit plans to the analytic model, reporting the
+    fallback; the range round-trips through save/load."""
+    p = _rand_params(7)
+    path = str(tmp_path / "r.txt")
+    _write_model(path, "c64", np.zeros(F, np.float32), np.full(F, 8.0, np.float32), 2.0, 0.3, p)
+    lo = np.full(F, -1e30, np.float32)
+    hi = np.full(F, 1e30, np.float32)
+    lo[16], hi[16] = 20, 24
+    _append_range(path, lo, hi)
+    ctx.load_costmodel(0, path)
+    got_lo, got_hi = ctx.training_range(0)
+    assert got_lo[16] == 20 and got_hi[16] == 24
+    for n, inside in ((16, False), (20, True), (24, True), (28, False)):
+        plan = qk.kernelize(ctx, W.qft(n), qk.kopts(dtype=0, cost_model=qk.QK_COST_LEARNED))
+        assert plan.cost_model() == {"learned_used": inside, "learned_fallback": not inside}, n
+        if not inside:   # the analytic plan, exactly
+            ref = qk.kernelize(ctx, W.qft(n), qk.kopts(dtype=0))
+            assert [k.as_tuple() for k in plan.kernels()] == [k.as_tuple() for k in ref.kernels()]
+    p2 = str(tmp_path / "r2.txt")
+    ctx.save_costmodel(0, p2)
+    ctx.unload_costmodel(0)
+    ctx.load_costmodel(0, p2)
+    assert np.array_equal(ctx.training_range(0)[0], got_lo)
+    ctx.unload_costmodel(0)
+
+
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_shipped_models_record_their_training_range(ctx, dtype):
+    """The shipped weights were trained on 24..32-qubit kernels: a 34-qubit
+    and a 16-qubit request fall back to the analytic model, 32 does not."""
+    import os
+    if not os.path.exists(qk.costmodel_path(dtype)):
+        pytest.skip("no shipped model for this dtype")
+    assert ctx.load_costmodel(dtype)
+    lo, hi = ctx.training_range(dtype)
+    assert lo[16] >= 24 and hi[16] <= 32
+    for n, inside in ((16, False), (32, True), (34, False)):
+        plan = qk.kernelize(ctx, W.ghz(n), qk.kopts(dtype=dtype, cost_model=qk.QK_COST_LEARNED))
+        assert plan.cost_model()["learned_fallback"] == (not inside), n
+        plan.free()
+    ctx.unload_costmodel(dtype)
