@@ -274,6 +274,24 @@ int plan_finish(qk_ctx* ctx, const qk_plan* p, qk_state* st);
 int simulate(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_state* st);
 /* Enqueue all kernels of p and plan_finish, without re-planning. */
 int execute_plan(qk_ctx* ctx, const qk_plan* p, qk_state* st);
+/* Allocation-free simulate, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same result as simulate with the same options (same plan and
+ * kernels), but no hipMalloc, hipFree or other allocating call is made:
+ *  - the plan's device tables go into a static device array of
+ *    QK_NOALLOC_SCRATCH_BYTES (4 MiB) per GPU, held until the process ends;
+ *    QK_ENOMEM (with the needed size in qk_last_error) when they do not fit;
+ *  - the final permutation runs in place (one pass for an involution, two for
+ *    any other permutation);
+ *  - only the analytic cost model is used: a QK_COST_LEARNED request returns
+ *    QK_EUNSUPPORTED (learned inference needs device buffers).
+ * n_qubits must be >= 4 (QK_EUNSUPPORTED otherwise).  The state must be in
+ * logical order on entry (QK_ESTATE) and is on return; the call returns after
+ * the stream has drained.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other threads or streams) race and must be
+ * serialised by the caller. */
+#define QK_NOALLOC_SCRATCH_BYTES (4u << 20)
+int simulate_noalloc(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_state* st);
 
 /* ---- cost models -----------------------------------------------------------
  * Analytic tables are kept per (n_qubits, dtype) in the context; kernelize uses

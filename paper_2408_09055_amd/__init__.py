@@ -36,6 +36,7 @@ QK_C64, QK_C128 = 0, 1
 QK_COST_ANALYTIC, QK_COST_LEARNED = 0, 1
 QK_KERNEL_FUSED, QK_KERNEL_LDS = 0, 1
 QK_CTX_HOST_ONLY = 1
+QK_NOALLOC_SCRATCH_BYTES = 4 << 20
 QK_IMPL_LDS_SEQUENCE, QK_IMPL_REGISTER, QK_IMPL_LDS_DENSE, QK_IMPL_MFMA_DENSE = 0, 1, 2, 3
 IMPL_NAMES = ["lds_sequence", "register", "lds_dense", "mfma_dense"]
 NUM_CLASSES = 7
@@ -125,6 +126,7 @@ _SIGS = {
     "plan_free": [_P],
     "apply_kernel": [_P, _P, _i64, _P], "plan_finish": [_P, _P, _P],
     "simulate": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _P],
+    "simulate_noalloc": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _P],
     "execute_plan": [_P, _P, _P],
     "plan_cost_model": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
     "qk_ctx_set_tables": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qk_cost_tables)],
@@ -532,6 +534,11 @@ def execute_plan(ctx: Context, plan: Plan, state: State):
 def simulate(ctx: Context, circuit, state: State, ko: qk_kopts | None = None):
     c = _circuit_struct(circuit)
     _check(_lib.simulate(ctx.h, ctypes.byref(c), ctypes.byref(ko) if ko is not None else None, state.h))
+
+
+def simulate_noalloc(ctx: Context, circuit, state: State, ko: qk_kopts | None = None):
+    c = _circuit_struct(circuit)
+    _check(_lib.simulate_noalloc(ctx.h, ctypes.byref(c), ctypes.byref(ko) if ko is not None else None, state.h))
 
 
 def kernelize_single(ctx: Context, circuit, ko: qk_kopts | None, ktype: int) -> Plan:

@@ -8,6 +8,8 @@
 
 #include "plan.hpp"
 
+static_assert(qk::kNoallocScratchBytes == QK_NOALLOC_SCRATCH_BYTES, "scratch size differs from the header's");
+
 namespace qk {
 
 static thread_local std::string g_err;
@@ -289,6 +291,9 @@ int qk_ctx_create(void* hip_stream, uint32_t flags, qk_ctx** out)
             return fail(QK_EDEVICE, std::string("qk_ctx_create: libqk is built for gfx950, device is ") + prop.gcnArchName);
         }
         c->device = dev;
+        // device address of the allocation-free entry point's scratch array
+        e = (hipError_t)scratch_setup(dev);
+        if (e != hipSuccess) { delete c; return hip_fail(e, "qk_ctx_create: scratch symbol lookup"); }
         if (hipMalloc((void**)&c->d_partials, sizeof(double) * (2 * reduce_partials() + 8)) != hipSuccess) {
             delete c;
             return fail(QK_ENOMEM, "qk_ctx_create: partials allocation failed");
@@ -670,7 +675,7 @@ int plan_final_layout(const qk_plan* p, int32_t* perm)
 int plan_free(qk_plan* p)
 {
     if (!p) return QK_OK;
-    if (p->ctx && !p->ctx->host_only && (p->d_ops || p->d_coef || p->d_rbprog)) {
+    if (p->ctx && !p->ctx->host_only && !p->scratch_backed && (p->d_ops || p->d_coef || p->d_rbprog)) {
         (void)hipStreamSynchronize((hipStream_t)p->ctx->stream);
         if (p->d_ops) (void)hipFree(p->d_ops);
         if (p->d_coef) (void)hipFree(p->d_coef);
@@ -730,6 +735,112 @@ int simulate(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_state* st)
     if (rc) return rc;
     rc = execute_plan(ctx, p, st);
     plan_free(p);
+    return rc;
+}
+
+// ---------------------------------------------------------------- allocation-free variant
+}  // extern "C"
+
+namespace qk {
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Back to logical order without a second state buffer: an involution is one
+// in-place pass; any other permutation is the product of two involutions
+// (each cycle c_0 -> c_1 -> ... of length L as the reflection c_j <-> c_{-j}
+// followed by the reflection c_j <-> c_{1-j}), so two in-place passes.
+int restore_in_place(qk_state* st, void* stream)
+{
+    if (is_identity(st->layout)) return QK_OK;
+    const int n = st->n;
+    std::vector<int32_t> p(n);
+    for (int q = 0; q < n; ++q) p[st->layout[q]] = q;
+    if (is_involution(p)) return permute_pairs_pass(st, p, stream);
+    std::vector<int32_t> r1(n), r2(n);
+    std::vector<char> seen(n, 0);
+    for (int b = 0; b < n; ++b) {
+        if (seen[b]) continue;
+        std::vector<int32_t> cyc;
+        for (int x = b; !seen[x]; x = p[x]) { seen[x] = 1; cyc.push_back(x); }
+        const int L = (int)cyc.size();
+        for (int j = 0; j < L; ++j) {
+            r1[cyc[j]] = cyc[(L - j) % L];
+            r2[cyc[j]] = cyc[(L + 1 - j) % L];
+        }
+    }
+    int rc = permute_pairs_pass(st, r1, stream);
+    if (rc) return rc;
+    return permute_pairs_pass(st, r2, stream);
+}
+
+}  // namespace
+}  // namespace qk
+
+extern "C" {
+
+int simulate_noalloc(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_state* st)
+{
+    int rc = need_device(ctx);
+    if (rc) return rc;
+    if (!c || !st) return fail(QK_EINVAL, "simulate_noalloc: null argument");
+    if (c->n_qubits != st->n) return fail(QK_EINVAL, "simulate_noalloc: circuit and state sizes differ");
+    if (st->n < 4) return fail(QK_EUNSUPPORTED, "simulate_noalloc: needs at least 4 qubits (in-place permutation tiles)");
+    qk_kopts k;
+    if (ko) k = *ko; else qk_kopts_default(&k);
+    k.dtype = st->dtype;
+    if (k.cost_model == QK_COST_LEARNED)
+        return fail(QK_EUNSUPPORTED, "simulate_noalloc: learned-model inference allocates device buffers; "
+                                     "use the analytic cost model");
+    void* base = scratch_ptr(ctx->device);
+    if (!base) return fail(QK_EDEVICE, "simulate_noalloc: scratch not set up on this device");
+    qk_plan* P = nullptr;
+    rc = build_plan(ctx, c, &k, &P);
+    if (rc) return rc;
+    // table layout in the scratch array: ops | coefficients | register programs
+    const size_t s = amp_bytes(P->dtype);
+    const size_t ob = P->ops.size() * sizeof(Op);
+    const size_t cb = std::max<size_t>(P->coefs.size(), 1) * s;
+    const size_t off_coef = align_up(ob, 256), off_prog = align_up(off_coef + cb, 256);
+    const size_t need = off_prog + P->rbprog.size();
+    if (need > kNoallocScratchBytes) {
+        plan_free(P);
+        return fail(QK_ENOMEM, "simulate_noalloc: plan tables need " + std::to_string(need) +
+                                   " bytes, more than the " + std::to_string(kNoallocScratchBytes) +
+                                   "-byte scratch array");
+    }
+    P->scratch_backed = true;
+    P->d_ops = base;
+    P->d_coef = (char*)base + off_coef;
+    P->d_rbprog = P->rbprog.empty() ? nullptr : (char*)base + off_prog;
+    std::vector<char> hc(cb, 0);
+    if (P->dtype == QK_C128) {
+        std::memcpy(hc.data(), P->coefs.data(), P->coefs.size() * 16);
+    } else {
+        float* f = (float*)hc.data();
+        for (size_t i = 0; i < P->coefs.size(); ++i) {
+            f[2 * i] = (float)P->coefs[i].real();
+            f[2 * i + 1] = (float)P->coefs[i].imag();
+        }
+    }
+    hipStream_t hs = (hipStream_t)ctx->stream;
+    hipError_t e = hipSuccess;
+    if (ob) e = hipMemcpyAsync(P->d_ops, P->ops.data(), ob, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->d_coef, hc.data(), cb, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && P->d_rbprog)
+        e = hipMemcpyAsync(P->d_rbprog, P->rbprog.data(), P->rbprog.size(), hipMemcpyHostToDevice, hs);
+    // the host copies must outlive the transfers
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) { plan_free(P); return hip_fail(e, "simulate_noalloc: table upload"); }
+    if (!is_identity(st->layout)) { plan_free(P); return fail(QK_ESTATE, "simulate_noalloc: state is not in logical order"); }
+    for (int64_t i = 0; i < (int64_t)P->kernels.size() && rc == QK_OK; ++i)
+        rc = launch_plan_kernel(P, i, st, ctx->stream);
+    if (rc == QK_OK) {
+        st->layout = P->final_layout;
+        rc = restore_in_place(st, ctx->stream);
+    }
+    plan_free(P);   // host side only: the tables stay in the scratch array
+    if (rc == QK_OK) rc = sync_stream(ctx, "simulate_noalloc");
     return rc;
 }
 

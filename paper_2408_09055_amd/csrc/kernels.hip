@@ -16,6 +16,7 @@
 //                 reductions with compensated sums and a fixed-order tree.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "qk_internal.hpp"
@@ -1983,6 +1984,42 @@ int launch_gather(int dtype, const void* psi, const uint64_t* idx, uint64_t cnt,
         hipLaunchKernelGGL(k_gather<float2>, dim3((uint32_t)blocks), dim3(kNT), 0, s, (const float2*)psi, idx, cnt,
                            (double2*)out);
     return (int)hipGetLastError();
+}
+
+// ----------------------------------------------------------- allocation-free scratch
+// Device memory of simulate_noalloc: one plan's operation, coefficient and
+// register-program tables are copied here instead of into hipMalloc'd
+// buffers.  One copy of the array exists on every device the library runs on
+// and lives until the process ends.  Host code never passes the array's name
+// to a kernel or a copy: the name is a host-side stand-in.  Its device address
+// is looked up once per device by scratch_setup (called by qk_ctx_create with
+// that device current) and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+int scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return 0;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!p || ((uintptr_t)p & 255) != 0) return (int)hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return 0;
+}
+
+void* scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace qk

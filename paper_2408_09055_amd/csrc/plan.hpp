@@ -72,5 +72,6 @@ struct qk_plan {
     void* d_ops = nullptr;
     void* d_coef = nullptr;
     void* d_rbprog = nullptr;
+    bool scratch_backed = false;         // tables live in the static scratch array (not freed)
     ~qk_plan() { qk::ctx_unref(ctx); }
 };

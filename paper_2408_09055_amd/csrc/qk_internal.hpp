@@ -189,6 +189,14 @@ bool mfma_ok(int K, int m);
 // Bound on the workgroups of every persistent block launch (0 = none).
 void set_max_groups(uint32_t g);
 
+// Allocation-free scratch (kernels.hip): a static device array of
+// kNoallocScratchBytes per device.  scratch_setup(device) looks up its device
+// address once per device (that device current; returns a hipError_t value);
+// scratch_ptr(device) returns it, or nullptr before setup.
+constexpr size_t kNoallocScratchBytes = 4u << 20;
+int scratch_setup(int device);
+void* scratch_ptr(int device);
+
 }  // namespace qk
 
 // ---------------------------------------------------------------- handles
