@@ -91,7 +91,8 @@ def run_dtype(qk, torch, ctx, n, dtype, models, steps, warmup, record_kernels, a
         for name, circ, _ in circuits:
             t0 = time.perf_counter()
             plans[(model, name)] = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, cost_model=cm, k_max=args.k_max,
-                                                                    m_max=args.m_max, ell=args.ell))
+                                                                    m_max=args.m_max, ell=args.ell,
+                                                                    kernelizer=KERNELIZERS[args.kernelizer]))
             kern_s[(model, name)] = time.perf_counter() - t0
             if model == "learned":
                 assert plans[(model, name)].cost_model()["learned_used"], "learned model not used"
@@ -272,6 +273,8 @@ def dominant_kernel(r, pass_bytes):
     return dom, kms, by_impl
 
 
+KERNELIZERS = {"ordered": 0, "full": 1}
+
 KERNEL_NAMES = {"register": "k_block_rb", "lds_sequence": "k_block_seq", "lds_dense": "k_block_dense",
                 "mfma_dense": "k_block_mfma"}
 
@@ -291,6 +294,8 @@ def main():
     ap.add_argument("--m-max", type=int, default=None)
     ap.add_argument("--ell", type=int, default=None)
     ap.add_argument("--cpu-gates", type=int, default=2)
+    ap.add_argument("--kernelizer", default="full", choices=["ordered", "full"],
+                    help="full: Kernelize fixes the gate order, OrderedKernelize partitions it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this simulator runs on one GPU; multi-GPU sharding is not built "

@@ -207,12 +207,53 @@ typedef struct qk_kopts {
                               the block become per-block phases, selections or
                               conditions read from the block index.  0: every
                               qubit of every gate must be active. */
+    int32_t kernelizer;    /* QK_KERNELIZE_*: which dynamic program partitions the circuit */
+    int32_t dp_prune;      /* Kernelize: prune to T/2 states whenever T are reached
+                              (appendix, "Pruning DP states"); 0 = exact (tiny circuits only) */
+    int32_t dp_flags;      /* Kernelize: QK_DP_* options */
     const qk_cost_tables* tables;  /* explicit analytic tables, or NULL for the
                                       context's tables for (n, dtype) */
 } qk_kopts;
 
+/* kernelizer:
+ *  ORDERED -- OrderedKernelize (appendix, Algorithm alg:dp-simple): optimal
+ *             partition into contiguous segments of the input gate order.
+ *  FULL    -- Kernelize (Algorithm alg:dp with alg:extensible) finds kernels
+ *             that need not be contiguous, with analytic costs; its kernel
+ *             sequence fixes a topologically equivalent gate order
+ *             (theorem thm:dp-correct).  OrderedKernelize with the requested
+ *             cost model then partitions both that order and the input order,
+ *             and the cheaper plan is kept, so a FULL plan never costs more
+ *             than an ORDERED one under the same model.
+ *  DP      -- Kernelize's own kernel sequence (analytic costs; the cost model
+ *             field is ignored).
+ * In FULL and DP plans the canonical gate list is in the chosen order
+ * (plan_gate_source maps it back to the input). */
+#define QK_KERNELIZE_ORDERED 0
+#define QK_KERNELIZE_FULL 1
+#define QK_KERNELIZE_DP 2
+/* dp_flags (appendix, "Optimizations to the Kernelize Algorithm"):
+ *  ATTACH_1Q -- each one-qubit gate travels with the next multi-qubit gate on
+ *               its qubit (else the previous one);
+ *  SUBSUME   -- a gate whose qubits contain or are contained in an open
+ *               kernel's joins it with no other option ("Optimizing DP
+ *               transition");
+ *  PACK      -- adjacent open kernels of one type are merged greedily when
+ *               that costs no more, before pruning and at the end
+ *               ("Post-processing");
+ *  FUSED     -- a new kernel forks a fusion copy besides the shared-memory
+ *               copy (section "Cost Function in Kernelize").  Off by default:
+ *               with pruning, small fusion kernels look cheap early and crowd
+ *               out states whose shared-memory kernels later grow; the
+ *               OrderedKernelize pass of FULL still prices both types. */
+#define QK_DP_ATTACH_1Q 1u
+#define QK_DP_SUBSUME 2u
+#define QK_DP_PACK 4u
+#define QK_DP_FUSED 8u
+
 /* Defaults: complex64, analytic, k_max 5, m_max 0 (auto), ell 0 (auto), swaps absorbed,
- * both kernel types, block_qubits 0, insular 1, tables NULL. */
+ * both kernel types, block_qubits 0, insular 1, kernelizer ORDERED, dp_prune 500,
+ * dp_flags ATTACH_1Q | SUBSUME | PACK, tables NULL. */
 void qk_kopts_default(qk_kopts* ko);
 
 typedef struct qk_kernel_info {

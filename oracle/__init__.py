@@ -16,6 +16,10 @@ Contents (each function cites the passage of the paper it follows):
                         kernelization problem and the OrderedKernelize
                         dynamic program of the paper's appendix, plus the
                         brute force over all contiguous partitions.
+* ``kernelize_full``  -- Kernelize, the DP over ordered kernel sets with
+                        extensible qubit sets, its kernel-constraint and
+                        topological-order checkers, and the brute force over
+                        all constraint-satisfying partitions.
 * ``features``, ``mlp_*`` -- FP64 reference of the learned cost model.
 
 Parity-unpinned parts are listed in ``UNPINNED``.

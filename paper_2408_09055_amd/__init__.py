@@ -38,6 +38,8 @@ QK_KERNEL_FUSED, QK_KERNEL_LDS = 0, 1
 QK_CTX_HOST_ONLY = 1
 QK_NOALLOC_SCRATCH_BYTES = 4 << 20
 QK_IMPL_LDS_SEQUENCE, QK_IMPL_REGISTER, QK_IMPL_LDS_DENSE, QK_IMPL_MFMA_DENSE = 0, 1, 2, 3
+QK_KERNELIZE_ORDERED, QK_KERNELIZE_FULL, QK_KERNELIZE_DP = 0, 1, 2
+QK_DP_ATTACH_1Q, QK_DP_SUBSUME, QK_DP_PACK, QK_DP_FUSED = 1, 2, 4, 8
 IMPL_NAMES = ["lds_sequence", "register", "lds_dense", "mfma_dense"]
 NUM_CLASSES = 7
 
@@ -67,6 +69,7 @@ class qk_kopts(ctypes.Structure):
                 ("m_max", ctypes.c_int32), ("ell", ctypes.c_int32), ("absorb_swaps", ctypes.c_int32),
                 ("allow_fused", ctypes.c_int32), ("allow_lds", ctypes.c_int32),
                 ("block_qubits", ctypes.c_int32), ("insular", ctypes.c_int32),
+                ("kernelizer", ctypes.c_int32), ("dp_prune", ctypes.c_int32), ("dp_flags", ctypes.c_int32),
                 ("tables", ctypes.POINTER(qk_cost_tables))]
 
 
@@ -186,14 +189,15 @@ def set_max_groups(groups: int):
 # ---------------------------------------------------------------- options
 def kopts(dtype=QK_C64, cost_model=QK_COST_ANALYTIC, k_max=None, m_max=None, ell=None,
           absorb_swaps=None, allow_fused=None, allow_lds=None, block_qubits=None, tables=None,
-          insular=None) -> qk_kopts:
+          insular=None, kernelizer=None, dp_prune=None, dp_flags=None) -> qk_kopts:
     ko = qk_kopts()
     _lib.qk_kopts_default(ctypes.byref(ko))
     ko.dtype = int(dtype)
     ko.cost_model = int(cost_model)
     for name, val in (("k_max", k_max), ("m_max", m_max), ("ell", ell), ("absorb_swaps", absorb_swaps),
                       ("allow_fused", allow_fused), ("allow_lds", allow_lds), ("block_qubits", block_qubits),
-                      ("insular", insular)):
+                      ("insular", insular), ("kernelizer", kernelizer), ("dp_prune", dp_prune),
+                      ("dp_flags", dp_flags)):
         if val is not None:
             setattr(ko, name, int(val))
     if tables is not None:

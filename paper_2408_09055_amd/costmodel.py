@@ -13,8 +13,9 @@ Sample distribution (n uniform on [24, 32]):
   forced to touch a qubit below 6; half of the LDS kernels also get 1..64
   insular gates (diagonal gates on any qubit, CX with any control);
 * 40 %: random contiguous segments of the evaluation families (QFT, random
-  layered, GHZ, hardware-efficient ansatz), which is what OrderedKernelize
-  queries on those circuits.
+  layered, GHZ, hardware-efficient ansatz), half in the circuit's own order
+  and half in the order Kernelize fixes for it: what OrderedKernelize queries
+  on those circuits in the ORDERED and FULL kernelizers.
 
 Usage:  python -m paper_2408_09055_amd.costmodel --dtype c64 --count 10000
 """
@@ -29,8 +30,8 @@ import time
 
 import numpy as np
 
-from . import (NUM_FEATURES, QK_C64, QK_C128, QK_KERNEL_FUSED, QK_KERNEL_LDS, Context, QkError, State, costmodel_path,
-               kernelize_single, kopts, lib, time_kernel)
+from . import (NUM_FEATURES, QK_C64, QK_C128, QK_KERNEL_FUSED, QK_KERNEL_LDS, QK_KERNELIZE_DP, Context, QkError, State,
+               costmodel_path, kernelize, kernelize_single, kopts, lib, time_kernel)
 
 _ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if _ROOT not in sys.path:
@@ -69,9 +70,28 @@ def _need(kind, qs):
     return tuple(qs)
 
 
-def _segment(n, ktype, rng, k_max, m_max, ell):
-    """A random contiguous gate segment of a family circuit that fits ktype."""
+_HOST_CTX = None
+
+
+def _kernelize_order(c, dtype):
+    """The gate order Kernelize fixes for circuit c (its kernels laid end to
+    end), from a host-only plan; SWAP gates stay absorbed (dropped)."""
+    global _HOST_CTX
+    if _HOST_CTX is None:
+        _HOST_CTX = Context(host_only=True)
+    plan = kernelize(_HOST_CTX, c, kopts(dtype=dtype, kernelizer=QK_KERNELIZE_DP))
+    src = [plan.gate_source(t) for t in range(plan.num_gates())]
+    plan.free()
+    return W.Circuit(c.n_qubits, c.gates[np.array(src, np.int64)], c.name + "/kernelize")
+
+
+def _segment(n, ktype, rng, k_max, m_max, ell, dtype=QK_C64):
+    """A random contiguous gate segment of a family circuit that fits ktype,
+    in the circuit's own gate order or (half the time) in the order
+    Kernelize fixes for it, whose segments the FULL kernelizer prices."""
     c = _family(n, rng)
+    if rng.random() < 0.5:
+        c = _kernelize_order(c, dtype)
     g = c.gates[c.gates["kind"] != W.SWAP]
     start = int(rng.integers(len(g)))
     limit = int(rng.integers(1, 65))
@@ -137,7 +157,7 @@ def sample_kernels(count, dtype, seed, n_lo=24, n_hi=32, k_max=7):
         if rng.random() < 0.6:
             c = W.random_kernel(n, rng, k_max) if ktype == QK_KERNEL_FUSED else _lds_kernel(n, rng, m_max, ell)
         else:
-            c = _segment(n, ktype, rng, k_max, m_max, ell)
+            c = _segment(n, ktype, rng, k_max, m_max, ell, dtype)
         if c is None or len(c) == 0:
             continue
         made += 1

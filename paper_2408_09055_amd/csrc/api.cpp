@@ -270,6 +270,9 @@ void qk_kopts_default(qk_kopts* ko)
     ko->allow_lds = 1;
     ko->block_qubits = 0;
     ko->insular = 1;
+    ko->kernelizer = QK_KERNELIZE_ORDERED;
+    ko->dp_prune = 500;
+    ko->dp_flags = QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK;
     ko->tables = nullptr;
 }
 

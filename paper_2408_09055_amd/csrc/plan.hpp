@@ -48,6 +48,19 @@ bool learned_available(qk_ctx* ctx, int dtype);
 // every n).  Outside it the planner falls back to the analytic model.
 bool learned_in_range(const qk_ctx* ctx, int dtype, int n);
 
+// Kernelize (Algorithm alg:dp with alg:extensible) on canonical gates with
+// analytic costs and the options in ko (dp_prune, dp_flags).  order: the
+// gate indices in kernel-sequence order (topologically equivalent to G);
+// kernels: [begin, end) ranges of that order with type and cost; total: the
+// sequence's cost.
+struct DPKernel {
+    int type;
+    int64_t begin, end;
+    int64_t cost;
+};
+int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_tables& tab,
+                 std::vector<int64_t>& order, std::vector<DPKernel>& kernels, int64_t& total);
+
 // Analytic tables used when a context has none for (n, dtype).
 qk_cost_tables default_tables(int n, int dtype);
 bool ctx_lookup_tables(const qk_ctx* ctx, int n, int dtype, qk_cost_tables* out);

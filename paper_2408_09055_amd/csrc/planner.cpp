@@ -207,6 +207,11 @@ int resolve_opts(const qk_kopts* ko_in, int n, qk_kopts& ko, int& mblk)
     if (ko.m_max < 2 || ko.m_max > kMaxBlockQubits) return fail(QK_EINVAL, "kernelize: m_max must be 2..14");
     if (ko.ell < 1 || ko.ell > ko.m_max) return fail(QK_EINVAL, "kernelize: ell must be 1..m_max");
     if (!ko.allow_fused && !ko.allow_lds) return fail(QK_EINVAL, "kernelize: no kernel type allowed");
+    if (ko.kernelizer < QK_KERNELIZE_ORDERED || ko.kernelizer > QK_KERNELIZE_DP)
+        return fail(QK_EINVAL, "kernelize: kernelizer must be ORDERED, FULL or DP");
+    if (ko.dp_prune < 0 || ko.dp_prune == 1) return fail(QK_EINVAL, "kernelize: dp_prune must be 0 or >= 2");
+    if ((uint32_t)ko.dp_flags & ~(QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK | QK_DP_FUSED))
+        return fail(QK_EINVAL, "kernelize: unknown dp_flags bits");
     mblk = ko.block_qubits ? ko.block_qubits : ko.m_max;
     if (mblk < ko.m_max || mblk <= ko.k_max || mblk > kMaxBlockQubits)
         return fail(QK_EINVAL, "kernelize: block_qubits must be >= m_max, > k_max and <= 14");
@@ -947,29 +952,21 @@ int emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m_
 
 }  // namespace
 
-int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan** out)
+// OrderedKernelize (Algorithm alg:dp-simple) over P->gates in their current
+// order with the requested cost model: DP[i+1] = min_j DP[j] + Cost(C[j..i]),
+// ties to fewer kernels, then to the larger j.  Sets the plan's learned-model
+// flags.
+struct OrderedResult {
+    int64_t total = 0;
+    std::vector<int64_t> cuts, costs;   // kernel ends and costs, in order
+    std::vector<int> types;
+};
+
+int ordered_partition(qk_ctx* ctx, qk_plan* P, const qk_kopts& ko, OrderedResult& R)
 {
-    if (!c || !out) return fail(QK_EINVAL, "kernelize: null argument");
-    const int n = c->n_qubits;
-    qk_kopts ko;
-    int mblk = 0;
-    int rc = resolve_opts(ko_in, n, ko, mblk);
-    if (rc) return rc;
-    if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) return fail(QK_EINVAL, "kernelize: bad gate array");
-
-    qk_plan* P = new qk_plan();
-    P->n = n;
-    P->dtype = ko.dtype;
-    P->ko = ko;
-    P->ctx = ctx;
-    ctx_ref(ctx);
-    if (ko.tables) P->tab = *ko.tables;
-    else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
-
-    rc = canonicalize(c, ko, P);
-    if (rc) { delete P; return rc; }
     const int64_t m = (int64_t)P->gates.size();
     const std::vector<CGate>& G = P->gates;
+    const int n = P->n;
 
     // ---- enumerate feasible segments (early exit is exact: see header)
     const uint64_t lowmask = (1ull << ko.ell) - 1;
@@ -1060,20 +1057,89 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
                 back_cost[i + 1] = cst;
             }
         }
-        if (best_c[i + 1] >= kInf) { delete P; return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " fits no kernel type"); }
+        if (best_c[i + 1] >= kInf) return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " fits no kernel type");
     }
-    P->total_cost = best_c[m];
-    std::vector<int64_t> cuts;
-    for (int64_t i = m; i > 0; i = back_j[i]) cuts.push_back(i);
-    std::reverse(cuts.begin(), cuts.end());
+    R.total = best_c[m];
+    R.cuts.clear();
+    R.types.clear();
+    R.costs.clear();
+    for (int64_t i = m; i > 0; i = back_j[i]) {
+        R.cuts.push_back(i);
+        R.types.push_back(back_t[i]);
+        R.costs.push_back(back_cost[i]);
+    }
+    std::reverse(R.cuts.begin(), R.cuts.end());
+    std::reverse(R.types.begin(), R.types.end());
+    std::reverse(R.costs.begin(), R.costs.end());
+    return QK_OK;
+
+}
+
+int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan** out)
+{
+    if (!c || !out) return fail(QK_EINVAL, "kernelize: null argument");
+    const int n = c->n_qubits;
+    qk_kopts ko;
+    int mblk = 0;
+    int rc = resolve_opts(ko_in, n, ko, mblk);
+    if (rc) return rc;
+    if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) return fail(QK_EINVAL, "kernelize: bad gate array");
+
+    qk_plan* P = new qk_plan();
+    P->n = n;
+    P->dtype = ko.dtype;
+    P->ko = ko;
+    P->ctx = ctx;
+    ctx_ref(ctx);
+    if (ko.tables) P->tab = *ko.tables;
+    else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
+
+    rc = canonicalize(c, ko, P);
+    if (rc) { delete P; return rc; }
+    const int64_t m = (int64_t)P->gates.size();
+    OrderedResult R;
+    if (ko.kernelizer == QK_KERNELIZE_DP || ko.kernelizer == QK_KERNELIZE_FULL) {
+        // Kernelize fixes a topologically equivalent gate order (thm:dp-correct)
+        std::vector<int64_t> order;
+        std::vector<DPKernel> dks;
+        int64_t dtot = 0;
+        rc = kernelize_dp(P->gates, ko, P->tab, order, dks, dtot);
+        if (rc) { delete P; return rc; }
+        std::vector<CGate> orig = P->gates, re(m);
+        for (int64_t t = 0; t < m; ++t) re[t] = orig[order[t]];
+        if (ko.kernelizer == QK_KERNELIZE_DP) {
+            P->gates = re;
+            R.total = dtot;
+            for (const DPKernel& k : dks) {
+                R.cuts.push_back(k.end);
+                R.types.push_back(k.type);
+                R.costs.push_back(k.cost);
+            }
+        } else {
+            // OrderedKernelize on the input order and on Kernelize's order;
+            // the cheaper partition (the input order on a tie) is kept
+            rc = ordered_partition(ctx, P, ko, R);
+            if (rc) { delete P; return rc; }
+            P->gates = re;
+            OrderedResult R2;
+            rc = ordered_partition(ctx, P, ko, R2);
+            if (rc) { delete P; return rc; }
+            if (R2.total < R.total || (R2.total == R.total && R2.cuts.size() < R.cuts.size())) R = std::move(R2);
+            else P->gates = orig;
+        }
+    } else {
+        rc = ordered_partition(ctx, P, ko, R);
+        if (rc) { delete P; return rc; }
+    }
+    P->total_cost = R.total;
 
     // ---- plan build
     const int m_exec = std::min(n, mblk);
     int64_t j = 0;
-    for (int64_t i : cuts) {
-        rc = emit_kernel(P, j, i, back_t[i], back_cost[i], m_exec);
+    for (size_t t = 0; t < R.cuts.size(); ++t) {
+        rc = emit_kernel(P, j, R.cuts[t], R.types[t], R.costs[t], m_exec);
         if (rc) { delete P; return rc; }
-        j = i;
+        j = R.cuts[t];
     }
     *out = P;
     return QK_OK;

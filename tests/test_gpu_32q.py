@@ -1,5 +1,6 @@
 """Full-size parity on the benchmark workload: the exact plans bench.py times
-(32 qubits; analytic costs calibrated on this device and the learned model;
+(32 qubits; Kernelize's gate order partitioned by OrderedKernelize with
+analytic costs calibrated on this device and with the learned model;
 complex64 and complex128), run through the same entry points.
 
 * QFT-32 from a seeded basis state and GHZ-32: full-state 1 - F over all 2^32
@@ -9,8 +10,14 @@ complex64 and complex128), run through the same entry points.
   MPS oracle (bond dimension 1024), computed once for all plans.
 * Invariants at any size: FP64 norm, and C^dagger C |0> = |0> for RL.
 
-Bars: complex64 1 - F <= 1e-6 (sampled for RL, and per-amplitude relative
-error <= 1e-4 there); complex128 1 - F <= 1e-12 (relative error <= 1e-10)."""
+Bars: complex64 1 - F <= 1e-6, complex128 1 - F <= 1e-12 (the target
+fidelities).  For RL each sampled amplitude is also bounded, in units of the
+root-mean-square amplitude 2^(-n/2) of the whole state rather than of the
+amplitude itself: rounding errors enter every amplitude at the scale of the
+amplitudes they are combined with, and a sampled amplitude far below the
+mean is the result of cancellation, so its own magnitude says nothing about
+its error.  Bars: 1e-4 (complex64, FP32: ~2^-24 per gate over 950 gates,
+with margin) and 1e-10 (complex128)."""
 import time
 
 import numpy as np
@@ -57,7 +64,7 @@ def rl_ref():
 
 
 def _plan(ctx, circ, dtype, cm):
-    plan = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, cost_model=cm))
+    plan = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, cost_model=cm, kernelizer=qk.QK_KERNELIZE_FULL))
     if cm == qk.QK_COST_LEARNED and ctx.costmodel_loaded(dtype):
         assert plan.cost_model()["learned_used"]
     return plan
@@ -107,10 +114,10 @@ def test_rl32_mps_sampled(ctx, rl_ref, dtype, model, cm):
     qk.execute_plan(ctx, plan, st)
     got = st.gather(idx)
     loss = fullstate.sampled_fidelity(got, ref)
-    rel = float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)))
+    rel = float(np.max(np.abs(got - ref))) * 2.0 ** (N_Q / 2)
     norm = st.norm2()
     print(f"rl32x20 {model} dtype={dtype}: {len(plan)} kernels, sampled 1-F={loss:.3e} (65538 amplitudes) "
-          f"max rel err={rel:.3e} norm drift={abs(norm - 1):.2e}", flush=True)
+          f"max err/rms={rel:.3e} norm drift={abs(norm - 1):.2e}", flush=True)
     bar_f, bar_r = _bar(dtype)
     assert loss <= bar_f and rel <= bar_r
     assert abs(norm - 1.0) <= (1e-12 if dtype == qk.QK_C128 else 1e-5)

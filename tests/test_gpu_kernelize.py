@@ -1,0 +1,84 @@
+"""GPU parity of plans made by Kernelize (Algorithm alg:dp with the
+extensible-qubit bookkeeping of alg:extensible), whose kernels need not be
+contiguous in the input order: the plan's gate order is topologically
+equivalent to the input (theorem thm:dp-correct), so the final state equals
+the oracle's gate-by-gate result up to rounding.
+
+Cases: random circuits (all gate kinds), random layered (U3 + CZ brickwork)
+and QFT, at 18-20 qubits in complex64 and complex128, with Kernelize's own
+kernels (DP) and with OrderedKernelize over Kernelize's order (FULL); the
+register-kernel grid is also bounded so that every workgroup walks several
+blocks.  Bars as in the other parity tests (complex128: 1 - F and max error
+<= 1e-12; complex64: 1 - F <= 1e-6, max error <= 2e-5 of the largest
+amplitude + 1e-7); each plan must also be valid for its gate order, which the
+oracle's checker verifies from plan_gate_source."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import kernelize_full as KF
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+qk = pytest.importorskip("paper_2408_09055_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = qk.Context()
+    yield c
+    qk.set_max_groups(0)
+    c.close()
+
+
+def _circuits():
+    rng = np.random.default_rng(41)
+    return [
+        ("random18", W.random_circuit(18, 160, rng), W.random_state(18, 3)),
+        ("rl20x8", W.random_layered(20, 8, 4), None),
+        ("qft19", W.qft(19), W.random_state(19, 5)),
+    ]
+
+
+def _check(gpu, ref, dtype, what):
+    gpu = np.asarray(gpu, np.complex128)
+    loss = oracle.fidelity_loss(gpu, ref)
+    err = float(np.max(np.abs(gpu - ref)))
+    scale = float(np.max(np.abs(ref)))
+    if dtype == qk.QK_C128:
+        assert loss <= 1e-12 and err <= 1e-12, f"{what}: 1-F={loss:.3e} maxerr={err:.3e}"
+    else:
+        assert loss <= 1e-6 and err <= 2e-5 * scale + 1e-7, f"{what}: 1-F={loss:.3e} maxerr={err:.3e}"
+    return loss
+
+
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+@pytest.mark.parametrize("kernelizer", [qk.QK_KERNELIZE_FULL, qk.QK_KERNELIZE_DP])
+def test_kernelize_plans_match_oracle(ctx, dtype, kernelizer):
+    for name, circ, psi in _circuits():
+        n = circ.n_qubits
+        if psi is None:
+            psi = oracle.basis(n, 0)
+        ref = oracle.run(circ, psi)
+        ko = qk.kopts(dtype=dtype, kernelizer=kernelizer)
+        plan = qk.kernelize(ctx, circ, ko)
+        ko0 = qk.kopts(dtype=dtype, kernelizer=qk.QK_KERNELIZE_ORDERED)
+        n_ordered = len(qk.kernelize(ctx, circ, ko0))
+        # the plan's gate order is topologically equivalent to the input
+        gates, _ = oracle.canonicalize(circ, True)
+        by_src = {g[2]: t for t, g in enumerate(gates)}
+        order = [by_src[plan.gate_source(t)] for t in range(len(gates))]
+        assert KF.is_topologically_equivalent(gates, order), name
+        for groups in (0, 7):
+            qk.set_max_groups(groups)
+            st = qk.sv_alloc(ctx, n, dtype)
+            st.upload(psi.astype(st.np_dtype))
+            qk.execute_plan(ctx, plan, st)
+            out = st.download()
+            st.free()
+            loss = _check(out, ref, dtype, f"{name} kernelizer={kernelizer} groups={groups}")
+        qk.set_max_groups(0)
+        print(f"{name} dtype={dtype} kernelizer={kernelizer}: {len(plan)} kernels (ordered: {n_ordered}) "
+              f"1-F={loss:.3e}", flush=True)

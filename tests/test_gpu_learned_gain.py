@@ -54,7 +54,8 @@ def test_learned_plans_faster_32q(dtype):
                 ("ghz", W.ghz(N_Q), 0)]
     plans = {}
     for model, cm in (("analytic", qk.QK_COST_ANALYTIC), ("learned", qk.QK_COST_LEARNED)):
-        plans[model] = {name: qk.kernelize(ctx, c, qk.kopts(dtype=dtype, cost_model=cm)) for name, c, _ in circuits}
+        plans[model] = {name: qk.kernelize(ctx, c, qk.kopts(dtype=dtype, cost_model=cm, kernelizer=qk.QK_KERNELIZE_FULL))
+                        for name, c, _ in circuits}
         if model == "learned":
             assert all(p.cost_model()["learned_used"] for p in plans[model].values())
         print(f"{model}: " + ", ".join(f"{k} {len(p)} kernels" for k, p in plans[model].items()), flush=True)

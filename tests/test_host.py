@@ -216,3 +216,76 @@ def test_context_outlives_its_plans():
     ctx.close()
     assert len(plan) > 0 and plan.total_cost() > 0
     plan.free()
+
+
+# ---------------------------------------------------------------- Kernelize
+from oracle import kernelize_full as KF  # noqa: E402
+
+
+def _kz_native(hctx, circ, opts, tab, kernelizer, T, flags):
+    ko = qk.kopts(dtype=qk.QK_C64, k_max=opts.k_max, m_max=opts.m_max, ell=opts.ell, insular=int(opts.insular),
+                  kernelizer=kernelizer, dp_prune=T, dp_flags=flags, tables=(tab.fused, tab.alpha, tab.gate),
+                  block_qubits=max(opts.m_max, opts.k_max + 1))
+    return qk.kernelize(hctx, circ, ko)
+
+
+def _dp_opts(flags, T):
+    return KF.DPOpts(attach_1q=bool(flags & qk.QK_DP_ATTACH_1Q), subsume=bool(flags & qk.QK_DP_SUBSUME),
+                     pack=bool(flags & qk.QK_DP_PACK), fork_fused=bool(flags & qk.QK_DP_FUSED), prune_T=T)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_native_kernelize_equals_oracle(seed, hctx):
+    """Native Kernelize (DP mode: its own kernels) and Kernelize followed by
+    OrderedKernelize (FULL mode) return exactly the oracle's kernels, gate
+    order and costs, with every option combination, exact or pruned."""
+    rng = np.random.default_rng(3000 + seed)
+    n = int(rng.integers(2, 12))
+    m = int(rng.integers(1, 9 if seed % 4 == 0 else 60))
+    circ = (W.random_layered(n, int(rng.integers(1, 4)), seed) if seed % 3 == 1 else W.random_circuit(n, m, rng))
+    flags = int(rng.integers(16))
+    T = 0 if (seed % 4 == 0 and len(circ) <= 8) else int(rng.choice([2, 6, 20, 100]))
+    k_max = int(rng.integers(1, 6))
+    m_max = int(rng.integers(2, 9))
+    opts = oracle.KOpts(k_max=k_max, m_max=m_max, ell=int(rng.integers(1, min(3, m_max) + 1)),
+                        insular=bool(rng.integers(2)))
+    tab = _rand_tables(rng, int(rng.choice([10, 1000, 10 ** 9])))
+    gates, _ = oracle.canonicalize(circ, True)
+    if not gates:
+        return
+    dp = _dp_opts(flags, T)
+    try:
+        oc, oks = KF.kernelize(gates, opts, tab, dp)
+    except ValueError:
+        _expect(qk.QK_EINVAL, _kz_native, hctx, circ, opts, tab, qk.QK_KERNELIZE_DP, T, flags)
+        return
+    plan = _kz_native(hctx, circ, opts, tab, qk.QK_KERNELIZE_DP, T, flags)
+    got = [(k.type, tuple(plan.gate_source(t) for t in range(k.gate_begin, k.gate_end)), k.cost_ps)
+           for k in plan.kernels()]
+    assert got == [(t, tuple(gates[g][2] for g in gl), c) for t, gl, c in oks]
+    assert plan.total_cost() == oc
+    c2, order, k2 = KF.kernelize_then_order(gates, opts, tab, dp)
+    plan = _kz_native(hctx, circ, opts, tab, qk.QK_KERNELIZE_FULL, T, flags)
+    assert plan.total_cost() == c2
+    assert [plan.gate_source(t) for t in range(plan.num_gates())] == [gates[g][2] for g in order]
+    assert [k.as_tuple() for k in plan.kernels()] == k2
+
+
+def test_native_kernelize_benchmark_circuits(hctx):
+    """On the 32-qubit benchmark circuits with the default options (pruning
+    at T = 500), FULL plans are valid gate orders and never cost more than
+    OrderedKernelize; on RL-32 they need far fewer kernels."""
+    tab = oracle.CostTables(fused=[0] + [26_000_000_000] * 4 + [95_000_000_000, 175_000_000_000, 176_000_000_000],
+                            alpha=26_300_000_000, gate=[75_000_000, 99_000_000, 220_000_000, 774_000_000,
+                                                        47_000_000, 49_000_000, 1_343_000_000])
+    for circ in (W.random_layered(32, 20, 31), W.qft(32), W.ghz(32)):
+        ko = dict(dtype=qk.QK_C128, tables=(tab.fused, tab.alpha, tab.gate))
+        p0 = qk.kernelize(hctx, circ, qk.kopts(kernelizer=qk.QK_KERNELIZE_ORDERED, **ko))
+        p1 = qk.kernelize(hctx, circ, qk.kopts(kernelizer=qk.QK_KERNELIZE_FULL, **ko))
+        assert p1.total_cost() <= p0.total_cost()
+        gates, _ = oracle.canonicalize(circ, True)
+        by_src = {g[2]: t for t, g in enumerate(gates)}
+        order = [by_src[p1.gate_source(t)] for t in range(p1.num_gates())]
+        assert KF.is_topologically_equivalent(gates, order)
+        if circ.name.startswith("rl"):
+            assert len(p1) <= 0.7 * len(p0), (len(p1), len(p0))

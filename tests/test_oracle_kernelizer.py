@@ -250,3 +250,125 @@ def test_insular_qft_needs_one_pass_per_few_hadamards():
     c_plain, _ = oracle.ordered_kernelize(gates, KOpts(k_max=1, m_max=m, ell=ell, allow_fused=False), tab)
     assert len(k_ins) <= math.ceil((n - ell) / (m - ell)) + 1
     assert c_ins < c_plain
+
+
+# ---------------------------------------------------------------------------
+# Kernelize (Algorithm alg:dp with alg:extensible)
+# ---------------------------------------------------------------------------
+from oracle import kernelize_full as KF  # noqa: E402
+
+
+def _kz_case(seed, m_hi=8):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 6))
+    m = int(rng.integers(1, m_hi))
+    gates = _rand_gates(n, m, rng)
+    opts = KOpts(k_max=int(rng.integers(1, 4)), m_max=int(rng.integers(2, 5)), ell=int(rng.integers(0, 2)),
+                 insular=bool(rng.integers(2)))
+    return gates, opts, _rand_tables(rng)
+
+
+@pytest.mark.parametrize("seed", range(50))
+def test_kernelize_exact_equals_brute_force_over_constrained_partitions(seed):
+    """Without pruning or heuristics, Kernelize reaches every partition whose
+    kernels satisfy the kernel constraint (the extensible sets characterise
+    it exactly, theorem thm:extensible-correct), so its cost equals the
+    minimum over all set partitions of the gates into constraint-satisfying
+    kernels, each priced at its cheaper feasible type."""
+    gates, opts, tab = _kz_case(seed)
+    try:
+        oc, _ = oracle.ordered_kernelize(gates, opts, tab)
+    except ValueError:
+        return
+    c, ks = KF.kernelize(gates, opts, tab)
+    assert c == KF.brute_force_constrained(gates, opts, tab)
+    # theorem thm:dp-optimal: never worse than OrderedKernelize
+    assert c <= oc
+    # theorem thm:dp-correct: the kernel sequence is a topological order of
+    # the circuit, and every kernel satisfies the constraint
+    order = [g for _, gl, _ in ks for g in gl]
+    assert KF.is_topologically_equivalent(gates, order)
+    for t, gl, cost in ks:
+        assert KF.satisfies_constraint(gates, gl)
+        kc, _ = KF.kernel_cost(gates, gl, opts, tab)
+        assert kc <= cost < oracle.INF
+
+
+def test_constraint_checker_on_the_papers_examples():
+    """The two rejected kernels described with the kernel-constraint figure:
+    a kernel that skips a middle gate sharing a qubit with its neighbours
+    (weak convexity), and one that grows its qubit set after excluding a gate
+    that shares a qubit with it (monotonicity).  Contiguous kernels always
+    pass (theorem thm:contiguous)."""
+    g = lambda k, qs, i: (k, tuple(qs), i)   # noqa: E731
+    # C[0] on q2, C[1] on q2, C[2] on q2: {C[0], C[2]} violates weak convexity
+    gates = [g(W.H, [2], 0), g(W.X, [2], 1), g(W.H, [2], 2)]
+    assert not KF.satisfies_constraint(gates, [0, 2])
+    assert KF.satisfies_constraint(gates, [0, 1]) and KF.satisfies_constraint(gates, [1, 2])
+    # K = {C[0] on (q0,q1), C[2] on (q1,q3)} with C[1] on q1 excluded: the
+    # qubit set grew from {0,1} after C[1] shared q1 -> monotonicity fails
+    gates = [g(W.CX, [0, 1], 0), g(W.H, [1], 1), g(W.CZ, [1, 3], 2)]
+    assert not KF.satisfies_constraint(gates, [0, 2])
+    # ... but a gate on the kernel's fixed qubits only is allowed after it
+    gates = [g(W.CX, [0, 1], 0), g(W.H, [2], 1), g(W.CZ, [0, 1], 2)]
+    assert KF.satisfies_constraint(gates, [0, 2])
+    rng = np.random.default_rng(5)
+    gates = _rand_gates(5, 12, rng)
+    for j in range(len(gates)):
+        for i in range(j + 1, len(gates) + 1):
+            assert KF.satisfies_constraint(gates, list(range(j, i)))
+
+
+def test_topological_checker_rejects_a_swapped_dependent_pair():
+    gates = [(W.H, (0,), 0), (W.CX, (0, 1), 1), (W.H, (2,), 2)]
+    assert KF.is_topologically_equivalent(gates, [2, 0, 1])
+    assert not KF.is_topologically_equivalent(gates, [1, 0, 2])
+    assert not KF.is_topologically_equivalent(gates, [0, 1])
+
+
+def test_kernelize_finds_a_non_contiguous_kernel():
+    """Gates interleaved on two disjoint qubit groups: OrderedKernelize must
+    cut at every switch, Kernelize puts each group in one kernel."""
+    gates = []
+    for r in range(4):
+        gates.append((W.CX, (0, 1), 2 * r))
+        gates.append((W.CX, (2, 3), 2 * r + 1))
+    opts = KOpts(k_max=2, m_max=2, ell=0)
+    tab = CostTables(fused=[0] + [10] * 7, alpha=10, gate=[1] * 7)
+    oc, ok = oracle.ordered_kernelize(gates, opts, tab)
+    c, ks = KF.kernelize(gates, opts, tab)
+    assert len(ok) == 8 and len(ks) == 2 and c == 20 < oc
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_kernelize_options_keep_validity(seed):
+    """Attaching one-qubit gates, subsumption, packing and pruning (the
+    appendix's optimisations) may change the cost, but every result is a
+    valid kernel sequence, and Kernelize's order partitioned by
+    OrderedKernelize never costs more than OrderedKernelize on the input."""
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(3, 9))
+    c = W.random_layered(n, int(rng.integers(1, 5)), seed) if seed % 2 else W.random_circuit(n, 40, rng)
+    gates, _ = oracle.canonicalize(c)
+    opts = KOpts(k_max=3, m_max=int(rng.integers(3, 6)), ell=1, insular=bool(seed % 3))
+    tab = _rand_tables(rng)
+    dp = KF.DPOpts(attach_1q=True, subsume=True, prune_T=20, pack=True, fork_fused=bool(seed % 2))
+    c1, ks = KF.kernelize(gates, opts, tab, dp)
+    order = [g for _, gl, _ in ks for g in gl]
+    assert KF.is_topologically_equivalent(gates, order)
+    assert c1 == sum(cost for _, _, cost in ks)
+    c2, order2, k2 = KF.kernelize_then_order(gates, opts, tab, dp)
+    assert KF.is_topologically_equivalent(gates, order2)
+    assert c2 <= oracle.ordered_kernelize(gates, opts, tab)[0]
+    assert oracle.check_plan([gates[g] for g in order2], k2, opts, tab) == c2
+
+
+def test_attached_units_stand_at_their_anchor():
+    """Each one-qubit gate joins the next multi-qubit gate on its qubit, else
+    the previous one; a qubit without multi-qubit gates forms one unit."""
+    gates = [(W.H, (0,), 0), (W.H, (1,), 1), (W.CZ, (0, 1), 2), (W.U3, (1,), 3), (W.H, (2,), 4),
+             (W.X, (2,), 5), (W.CX, (1, 3), 6), (W.H, (3,), 7)]
+    units = KF.make_units(gates, KOpts(), attach_1q=True)
+    assert [u[0] for u in units] == [(0, 1, 2), (4, 5), (3, 6, 7)]
+    order = [g for u in units for g in u[0]]
+    assert KF.is_topologically_equivalent(gates, order)
