@@ -211,6 +211,10 @@ typedef struct qk_kopts {
     int32_t dp_prune;      /* Kernelize: prune to T/2 states whenever T are reached
                               (appendix, "Pruning DP states"); 0 = exact (tiny circuits only) */
     int32_t dp_flags;      /* Kernelize: QK_DP_* options */
+    int32_t fuse_gates;    /* 1: inside an LDS kernel, a run of gates on the same
+                              one or two qubits with no other gate on them in
+                              between becomes one 2x2 or 4x4 operation (product in
+                              FP64, rounded once) when that saves arithmetic */
     const qk_cost_tables* tables;  /* explicit analytic tables, or NULL for the
                                       context's tables for (n, dtype) */
 } qk_kopts;
@@ -253,7 +257,7 @@ typedef struct qk_kopts {
 
 /* Defaults: complex64, analytic, k_max 5, m_max 0 (auto), ell 0 (auto), swaps absorbed,
  * both kernel types, block_qubits 0, insular 1, kernelizer ORDERED, dp_prune 500,
- * dp_flags ATTACH_1Q | SUBSUME | PACK, tables NULL. */
+ * dp_flags ATTACH_1Q | SUBSUME | PACK, fuse_gates 1, tables NULL. */
 void qk_kopts_default(qk_kopts* ko);
 
 typedef struct qk_kernel_info {
@@ -344,7 +348,7 @@ int qk_ctx_get_tables(qk_ctx* ctx, int n_qubits, int dtype, qk_cost_tables* out,
 /* Measure the analytic constants on the device following the paper's
  * experimental setup: fused kernels timed per qubit count k = 1..7 (three
  * qubit placements averaged), an empty LDS kernel for alpha, and each gate
- * class inside an LDS kernel (16 gates, alpha subtracted).  Allocates and
+ * class inside an LDS kernel (16 gates, alpha subtracted, gate-run fusion off).  Allocates and
  * frees a temporary 2^n state; stores the tables in the context and copies
  * them to out (may be NULL).  n must be 14..34; reps = timed repetitions. */
 int costmodel_calibrate(qk_ctx* ctx, int n_qubits, int dtype, int reps, qk_cost_tables* out);

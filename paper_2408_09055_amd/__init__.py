@@ -70,7 +70,7 @@ class qk_kopts(ctypes.Structure):
                 ("allow_fused", ctypes.c_int32), ("allow_lds", ctypes.c_int32),
                 ("block_qubits", ctypes.c_int32), ("insular", ctypes.c_int32),
                 ("kernelizer", ctypes.c_int32), ("dp_prune", ctypes.c_int32), ("dp_flags", ctypes.c_int32),
-                ("tables", ctypes.POINTER(qk_cost_tables))]
+                ("fuse_gates", ctypes.c_int32), ("tables", ctypes.POINTER(qk_cost_tables))]
 
 
 class qk_kernel_info(ctypes.Structure):
@@ -189,7 +189,7 @@ def set_max_groups(groups: int):
 # ---------------------------------------------------------------- options
 def kopts(dtype=QK_C64, cost_model=QK_COST_ANALYTIC, k_max=None, m_max=None, ell=None,
           absorb_swaps=None, allow_fused=None, allow_lds=None, block_qubits=None, tables=None,
-          insular=None, kernelizer=None, dp_prune=None, dp_flags=None) -> qk_kopts:
+          insular=None, kernelizer=None, dp_prune=None, dp_flags=None, fuse_gates=None) -> qk_kopts:
     ko = qk_kopts()
     _lib.qk_kopts_default(ctypes.byref(ko))
     ko.dtype = int(dtype)
@@ -197,7 +197,7 @@ def kopts(dtype=QK_C64, cost_model=QK_COST_ANALYTIC, k_max=None, m_max=None, ell
     for name, val in (("k_max", k_max), ("m_max", m_max), ("ell", ell), ("absorb_swaps", absorb_swaps),
                       ("allow_fused", allow_fused), ("allow_lds", allow_lds), ("block_qubits", block_qubits),
                       ("insular", insular), ("kernelizer", kernelizer), ("dp_prune", dp_prune),
-                      ("dp_flags", dp_flags)):
+                      ("dp_flags", dp_flags), ("fuse_gates", fuse_gates)):
         if val is not None:
             setattr(ko, name, int(val))
     if tables is not None:

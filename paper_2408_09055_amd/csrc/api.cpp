@@ -273,6 +273,7 @@ void qk_kopts_default(qk_kopts* ko)
     ko->kernelizer = QK_KERNELIZE_ORDERED;
     ko->dp_prune = 500;
     ko->dp_flags = QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK;
+    ko->fuse_gates = 1;
     ko->tables = nullptr;
 }
 

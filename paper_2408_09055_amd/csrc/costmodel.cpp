@@ -273,6 +273,9 @@ int costmodel_calibrate(qk_ctx* ctx, int n, int dtype, int reps, qk_cost_tables*
     qk_kopts_default(&ko);
     ko.dtype = dtype;
     ko.k_max = 7;
+    // each gate is timed on its own: gate-run fusion would merge the repeated
+    // gates of one class into a single product and price them near zero
+    ko.fuse_gates = 0;
     const int m_max = dtype == QK_C64 ? 13 : 12, ell = 4;   // the automatic ell
     qk_cost_tables t{};
     uint64_t seed = 12345;

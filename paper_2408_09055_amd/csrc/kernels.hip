@@ -186,6 +186,28 @@ __device__ void op_cphase(C* sm, int m, int a, int b, const C* __restrict__ u)
     }
 }
 
+// 4x4 matrix on bits a < b: coef row-major, index bit(a) + 2 bit(b)
+template <typename C>
+__device__ void op_dense2(C* sm, int m, int a, int b, const C* __restrict__ u)
+{
+    for (uint32_t p = threadIdx.x; p < (1u << (m - 2)); p += kNT) {
+        const uint32_t r0 = ins00(p, a, b);
+        const uint32_t r[4] = {r0, r0 | (1u << a), r0 | (1u << b), r0 | (1u << a) | (1u << b)};
+        C x[4], y[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) x[s] = sm[r[s]];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            C acc = cmul(u[4 * s], x[0]);
+#pragma unroll
+            for (int t = 1; t < 4; ++t) acc = cmadd(u[4 * s + t], x[t], acc);
+            y[s] = acc;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) sm[r[s]] = y[s];
+    }
+}
+
 template <typename C>
 __device__ void op_diag2(C* sm, int m, int a, int b, const C* __restrict__ u)
 {
@@ -425,6 +447,7 @@ __global__ __launch_bounds__(kNT) void k_block_seq(C* __restrict__ psi, BlockDes
             case OP_CPHASE: op_cphase(s, m, op.b[0], op.b[1], u); break;
             case OP_DIAG2: op_diag2(s, m, op.b[0], op.b[1], u); break;
             case OP_SWAP: op_swap(s, m, op.b[0], op.b[1]); break;
+            case OP_DENSE2: op_dense2(s, m, op.b[0], op.b[1], u); break;
             default: break;
             }
             __syncthreads();
@@ -766,6 +789,25 @@ __device__ __forceinline__ void rb_swap(V (&v)[kRbAmps])
         const V a = v[i0];
         v[i0] = v[i1];
         v[i1] = a;
+    });
+}
+
+// 4x4 matrix on register bits A and B (row-major U, index bit(A) + 2 bit(B)):
+// the four quads (i, i | 2^A, i | 2^B, i | 2^A | 2^B) one after another
+template <int A, int B, typename C, typename V>
+__device__ __forceinline__ void rb_dense2(V (&v)[kRbAmps], const C* __restrict__ U)
+{
+    constexpr int lo = A < B ? A : B, hi = A < B ? B : A;
+    static_for<0, kRbAmps / 4>([&](auto G) QK_AI {
+        constexpr int i0 = cins0(cins0(G.value, lo), hi);
+        constexpr int idx[4] = {i0, i0 | (1 << A), i0 | (1 << B), i0 | (1 << A) | (1 << B)};
+        V in[4];
+        static_for<0, 4>([&](auto S) QK_AI { in[S.value] = v[idx[S.value]]; });
+        static_for<0, 4>([&](auto R) QK_AI {
+            V acc = cmul(ld_coef(U + 4 * R.value), in[0]);
+            static_for<1, 4>([&](auto Cc) QK_AI { acc = cmadd(ld_coef(U + 4 * R.value + Cc.value), in[Cc.value], acc); });
+            v[idx[R.value]] = acc;
+        });
     });
 }
 
@@ -1178,6 +1220,7 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
     }
     case OP_DIAG2: dispatch2(b0, b1, [&](auto A, auto B) QK_AI { rb_diag2<A.value, B.value>(v, u); }); break;
     case OP_SWAP: dispatch2(b0, b1, [&](auto A, auto B) QK_AI { rb_swap<A.value, B.value>(v); }); break;
+    case OP_DENSE2: dispatch2(b0, b1, [&](auto A, auto B) QK_AI { rb_dense2<A.value, B.value>(v, u); }); break;
     default: break;
     }
 }

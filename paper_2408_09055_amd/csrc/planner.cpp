@@ -257,7 +257,8 @@ int canonicalize(const qk_circuit* c, const qk_kopts& ko, qk_plan* P)
 int op_nbits(const Op& op)
 {
     if (op.code == OP_BPHASE || op.code == OP_BPHRUN) return 0;
-    if (op.code == OP_CX || op.code == OP_CZ || op.code == OP_CPHASE || op.code == OP_DIAG2 || op.code == OP_SWAP)
+    if (op.code == OP_CX || op.code == OP_CZ || op.code == OP_CPHASE || op.code == OP_DIAG2 || op.code == OP_SWAP ||
+        op.code == OP_DENSE2)
         return 2;
     return 1;
 }
@@ -661,6 +662,7 @@ void build_rb(qk_plan* P, PKernel& K)
         case OP_BPHASE: cnt = 2 << (o.k - 1); break;
         case OP_CPHASE: cnt = 1; break;
         case OP_DENSEK: cnt = 1 << (2 * o.k); break;
+        case OP_DENSE2: cnt = 16; break;
         default: cnt = 0; break;
         }
         const uint32_t first = (uint32_t)kc.size();
@@ -775,6 +777,195 @@ bool cp_form(const qk_plan* P, const Op& op, CPForm& f)
     }
     default: return false;
     }
+}
+
+// 4x4 action of an operation on the block bits (a, b), a < b, index
+// bit(a) + 2 bit(b): a one-bit operation on a or b is embedded, a two-bit one
+// is re-indexed when its bits come in the order (b, a).
+void op_matrix4(const qk_plan* P, const Op& op, int a, int b, cd E[16])
+{
+    for (int t = 0; t < 16; ++t) E[t] = 0.0;
+    const cd* c = &P->coefs[op.coef];
+    if (op_nbits(op) == 1) {
+        cd M[4] = {1.0, 0.0, 0.0, 1.0};
+        if (op.code == OP_DENSE1 || op.code == OP_H) { M[0] = c[0]; M[1] = c[1]; M[2] = c[2]; M[3] = c[3]; }
+        else if (op.code == OP_DIAG1) { M[0] = c[0]; M[3] = c[1]; }
+        else { M[0] = 0.0; M[1] = 1.0; M[2] = 1.0; M[3] = 0.0; }   // OP_X
+        const int sh = op.b[0] == a ? 0 : 1;
+        for (int r = 0; r < 4; ++r)
+            for (int q = 0; q < 4; ++q)
+                if (((r >> (1 - sh)) & 1) == ((q >> (1 - sh)) & 1))
+                    E[r * 4 + q] = M[((r >> sh) & 1) * 2 + ((q >> sh) & 1)];
+        return;
+    }
+    // own index s = bit(b0) + 2 bit(b1)
+    cd F[16];
+    for (int t = 0; t < 16; ++t) F[t] = 0.0;
+    switch (op.code) {
+    case OP_CZ: F[0] = F[5] = F[10] = 1.0; F[15] = -1.0; break;
+    case OP_CPHASE: F[0] = F[5] = F[10] = 1.0; F[15] = c[0]; break;
+    case OP_DIAG2: for (int s2 = 0; s2 < 4; ++s2) F[s2 * 5] = c[s2]; break;
+    case OP_CX: F[0] = F[10] = 1.0; F[1 * 4 + 3] = F[3 * 4 + 1] = 1.0; break;   // s -> s ^ 2 where bit(b0)
+    case OP_SWAP: F[0] = F[15] = 1.0; F[1 * 4 + 2] = F[2 * 4 + 1] = 1.0; break;
+    default: for (int t = 0; t < 16; ++t) F[t] = c[t]; break;   // OP_DENSE2 (own bits ascending)
+    }
+    const bool same = op.b[0] == a;
+    auto re = [&](int s2) { return same ? s2 : ((s2 & 1) << 1) | (s2 >> 1); };
+    for (int r = 0; r < 4; ++r)
+        for (int q = 0; q < 4; ++q) E[re(r) * 4 + re(q)] = F[r * 4 + q];
+}
+
+// Gate fusion inside an LDS kernel: a run of operations that act only on
+// the same one or two active block bits, with no other operation on those
+// bits in between, is replaced by its product (FP64, later operations on the
+// left; rounded once to the state's precision on upload), placed where the
+// run's last operation was.  Runs on two bits are fused when they hold at
+// least three dense one-qubit gates (a 4x4 product costs about two of them),
+// runs on one bit when they hold two operations of which one is dense.
+// Operations on insular qubits outside the block, phase runs and block
+// phases end the runs on the bits they touch.
+void fuse_runs(qk_plan* P, int op_off)
+{
+    const int nops = (int)P->ops.size() - op_off;
+    if (nops < 2) return;
+    auto fusable = [](const Op& op) {
+        switch (op.code) {
+        case OP_DENSE1: case OP_H: case OP_DIAG1: case OP_X: case OP_CZ: case OP_CPHASE: case OP_DIAG2: case OP_CX:
+        case OP_SWAP: return true;
+        default: return false;
+        }
+    };
+    auto dense = [](const Op& op) { return op.code == OP_DENSE1 || op.code == OP_H; };
+    struct Run { int a, b; std::vector<int> mem; bool open; };
+    std::vector<Run> runs;
+    std::vector<int> open_of(kMaxBlockQubits + 1, -1);   // block bit -> open run
+    std::vector<int> run_of(nops, -1);
+    auto close = [&](int r) {
+        if (r < 0 || !runs[r].open) return;
+        runs[r].open = false;
+        if (runs[r].a >= 0) open_of[runs[r].a] = -1;
+        if (runs[r].b >= 0) open_of[runs[r].b] = -1;
+    };
+    for (int o = 0; o < nops; ++o) {
+        const Op& op = P->ops[op_off + o];
+        if (!fusable(op)) {
+            // close the runs of every active bit it touches
+            if (op.code == OP_PHRUN) {
+                close(open_of[op.b[0]]);
+                const cd* c = &P->coefs[op.coef];
+                for (int e = 0; e < op.k; ++e) {
+                    const int code = (int)c[2 * e + 1].real();
+                    if (code < 64) close(open_of[code]);
+                }
+            } else if (op.code == OP_DIAG1C || op.code == OP_XC) {
+                close(open_of[op.b[0]]);
+            }
+            continue;
+        }
+        const int nb = op_nbits(op);
+        if (nb == 1) {
+            const int x = op.b[0];
+            int r = open_of[x];
+            if (r < 0) {
+                runs.push_back({x, -1, {}, true});
+                r = (int)runs.size() - 1;
+                open_of[x] = r;
+            }
+            runs[r].mem.push_back(o);
+            run_of[o] = r;
+            continue;
+        }
+        const int x = std::min(op.b[0], op.b[1]), y = std::max(op.b[0], op.b[1]);
+        int rx = open_of[x], ry = open_of[y];
+        if (rx >= 0 && rx == ry) {
+            runs[rx].mem.push_back(o);
+            run_of[o] = rx;
+            continue;
+        }
+        auto single = [&](int r) { return r >= 0 && runs[r].b < 0; };
+        if ((rx < 0 || single(rx)) && (ry < 0 || single(ry))) {
+            // the two one-bit runs (if any) and this operation form one run
+            Run nr{x, y, {}, true};
+            for (int r : {rx, ry}) {
+                if (r < 0) continue;
+                nr.mem.insert(nr.mem.end(), runs[r].mem.begin(), runs[r].mem.end());
+                runs[r].open = false;
+                runs[r].mem.clear();
+            }
+            std::sort(nr.mem.begin(), nr.mem.end());
+            nr.mem.push_back(o);
+            runs.push_back(nr);
+            const int r = (int)runs.size() - 1;
+            for (int t : runs[r].mem) run_of[t] = r;
+            open_of[x] = open_of[y] = r;
+            continue;
+        }
+        close(rx);
+        close(ry);
+        runs.push_back({x, y, {o}, true});
+        run_of[o] = (int)runs.size() - 1;
+        open_of[x] = open_of[y] = run_of[o];
+    }
+    // which runs are fused, and their products
+    std::vector<char> fuse(runs.size(), 0);
+    std::vector<Op> fused_op(runs.size());
+    for (size_t r = 0; r < runs.size(); ++r) {
+        const Run& R = runs[r];
+        if (R.mem.size() < 2) continue;
+        int nd = 0;
+        for (int t : R.mem) nd += dense(P->ops[op_off + t]) ? 1 : 0;
+        const bool two = R.b >= 0;
+        if (two ? nd < 3 : nd < 1) continue;
+        Op f{};
+        f.coef = (uint32_t)P->coefs.size();
+        if (two) {
+            cd U[16], E[16], T[16];
+            for (int t = 0; t < 16; ++t) U[t] = (t % 5 == 0) ? 1.0 : 0.0;
+            for (int t : R.mem) {
+                op_matrix4(P, P->ops[op_off + t], R.a, R.b, E);
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        cd acc = 0.0;
+                        for (int k = 0; k < 4; ++k) acc += E[i * 4 + k] * U[k * 4 + j];
+                        T[i * 4 + j] = acc;
+                    }
+                std::copy(T, T + 16, U);
+            }
+            f.code = OP_DENSE2;
+            f.b[0] = (uint8_t)R.a;
+            f.b[1] = (uint8_t)R.b;
+            P->coefs.insert(P->coefs.end(), U, U + 16);
+        } else {
+            // one bit: the same product on the 2x2 of bit a (embedded at b = a + 1)
+            cd U[16], E[16], T[16];
+            for (int t = 0; t < 16; ++t) U[t] = (t % 5 == 0) ? 1.0 : 0.0;
+            for (int t : R.mem) {
+                op_matrix4(P, P->ops[op_off + t], R.a, R.a + 1, E);
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        cd acc = 0.0;
+                        for (int k = 0; k < 4; ++k) acc += E[i * 4 + k] * U[k * 4 + j];
+                        T[i * 4 + j] = acc;
+                    }
+                std::copy(T, T + 16, U);
+            }
+            f.code = OP_DENSE1;
+            f.b[0] = (uint8_t)R.a;
+            const cd M[4] = {U[0], U[1], U[4], U[5]};
+            P->coefs.insert(P->coefs.end(), M, M + 4);
+        }
+        fuse[r] = 1;
+        fused_op[r] = f;
+    }
+    std::vector<Op> out;
+    out.reserve(nops);
+    for (int o = 0; o < nops; ++o) {
+        const int r = run_of[o];
+        if (r < 0 || !fuse[r]) { out.push_back(P->ops[op_off + o]); continue; }
+        if (o == runs[r].mem.back()) out.push_back(fused_op[r]);
+    }
+    P->ops.resize(op_off);
+    P->ops.insert(P->ops.end(), out.begin(), out.end());
 }
 
 // Merge runs of consecutive controlled phases that share one block bit (the
@@ -941,6 +1132,7 @@ int emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m_
             P->ops.push_back(op);
         }
     }
+    if (K.type == QK_KERNEL_LDS && P->ko.fuse_gates) fuse_runs(P, K.op_off);
     if (K.type == QK_KERNEL_LDS) group_phase_runs(P, K.op_off);
     K.n_ops = (int)P->ops.size() - K.op_off;
     K.desc.n_ops = K.n_ops;

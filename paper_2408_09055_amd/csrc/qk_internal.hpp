@@ -60,6 +60,10 @@ enum OpCode : uint8_t {
     // the kernel.  Entry e (of k): coef[5 e] = (qubit a, qubit b) as real
     // numbers, coef[5 e + 1 + s] the factor for s = bit(a) + 2 bit(b).
     OP_BPHRUN = 14,
+    // 4x4 matrix on bits b0 < b1 (both active): coef[0..15] row-major, index
+    // bit(b0) + 2 bit(b1); the product of a run of gates fused in the planner.
+    // Register form: both bits in registers.
+    OP_DENSE2 = 15,
 };
 
 struct Op {

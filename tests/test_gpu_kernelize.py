@@ -82,3 +82,38 @@ def test_kernelize_plans_match_oracle(ctx, dtype, kernelizer):
         qk.set_max_groups(0)
         print(f"{name} dtype={dtype} kernelizer={kernelizer}: {len(plan)} kernels (ordered: {n_ordered}) "
               f"1-F={loss:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_fused_gate_runs_match_oracle(ctx, dtype):
+    """Runs of gates on the same one or two qubits inside an LDS kernel are
+    replaced by one 2x2 or 4x4 product (fuse_gates): the state must equal the
+    oracle's with and without that fusion, on register-blocked blocks (n = 16)
+    and on the LDS gate-sequence kernel (n = 9, blocks below 2^12)."""
+    rng = np.random.default_rng(77)
+    for n in (9, 16):
+        g = []
+        for r in range(6):
+            for q in range(n):
+                g.append(W.gate(W.U3, [q], list(rng.uniform(0, 6.3, 3))))
+            for q in range(r % 2, n - 1, 2):
+                kind = [W.CZ, W.CX, W.CP, W.RZZ][int(rng.integers(4))]
+                a, b = (q, q + 1) if rng.random() < 0.5 else (q + 1, q)
+                g.append(W.gate(kind, [a, b], [float(rng.uniform(0, 6.3))] if kind in (W.CP, W.RZZ) else []))
+            g.append(W.gate(W.H, [int(rng.integers(n))]))
+            g.append(W.gate(W.RZ, [int(rng.integers(n))], [float(rng.uniform(0, 6.3))]))
+        circ = W.from_list(n, g, f"brick{n}")
+        psi = W.random_state(n, 8)
+        ref = oracle.run(circ, psi)
+        for fg in (0, 1):
+            for kz in (qk.QK_KERNELIZE_ORDERED, qk.QK_KERNELIZE_FULL):
+                plan = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, kernelizer=kz, fuse_gates=fg))
+                st = qk.sv_alloc(ctx, n, dtype)
+                st.upload(psi.astype(st.np_dtype))
+                qk.execute_plan(ctx, plan, st)
+                out = st.download()
+                st.free()
+                loss = _check(out, ref, dtype, f"brick{n} fuse={fg} kernelizer={kz}")
+                print(f"brick{n} dtype={dtype} fuse={fg} kernelizer={kz}: {len(plan)} kernels, "
+                      f"{sum(k.n_ops for k in plan.kernels())} ops, impl {[k.impl for k in plan.kernels()]}, "
+                      f"1-F={loss:.3e}", flush=True)

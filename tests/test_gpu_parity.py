@@ -460,7 +460,9 @@ def test_lane_exchange_gates(ctx, dtype, m_max, ell):
         circ = W.from_list(n, kernel(pool, 60, controls))
         psi = W.random_state(n, 5 + len(pool))
         ref = oracle.run(circ, psi)
-        plan = qk.kernelize_single(ctx, circ, qk.kopts(dtype=dtype, m_max=m_max, ell=ell, insular=1),
+        # gate-run fusion off: a fused 4x4 needs both of its bits in
+        # registers, which is not the lane-exchange path under test
+        plan = qk.kernelize_single(ctx, circ, qk.kopts(dtype=dtype, m_max=m_max, ell=ell, insular=1, fuse_gates=0),
                                    qk.QK_KERNEL_LDS)
         info = plan.kernel(0)
         print(f"{name}: dtype={dtype} m={m_max} phases={info.n_phases} transposes={info.n_transposes}", flush=True)
