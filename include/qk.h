@@ -211,6 +211,10 @@ typedef struct qk_kopts {
     int32_t dp_prune;      /* Kernelize: prune to T/2 states whenever T are reached
                               (appendix, "Pruning DP states"); 0 = exact (tiny circuits only) */
     int32_t dp_flags;      /* Kernelize: QK_DP_* options */
+    int32_t local_qubits;  /* stages: 0 = one stage; L (m_max <= L < n) = every
+                              stage's non-insular qubits lie in L local qubits held
+                              in physical bits 0..L-1, with a permutation pass
+                              between stages (see plan_kernel_info.stage) */
     int32_t fuse_gates;    /* 1: inside an LDS kernel, a run of gates on the same
                               one or two qubits with no other gate on them in
                               between becomes one 2x2 or 4x4 operation (product in
@@ -257,7 +261,7 @@ typedef struct qk_kopts {
 
 /* Defaults: complex64, analytic, k_max 5, m_max 0 (auto), ell 0 (auto), swaps absorbed,
  * both kernel types, block_qubits 0, insular 1, kernelizer ORDERED, dp_prune 500,
- * dp_flags ATTACH_1Q | SUBSUME | PACK, fuse_gates 1, tables NULL. */
+ * dp_flags ATTACH_1Q | SUBSUME | PACK, local_qubits 0, fuse_gates 1, tables NULL. */
 void qk_kopts_default(qk_kopts* ko);
 
 typedef struct qk_kernel_info {
@@ -272,6 +276,8 @@ typedef struct qk_kernel_info {
     int32_t impl;          /* device kernel: QK_IMPL_* */
     int32_t n_phases;      /* register phases (register-blocked kernel), else 0 */
     int32_t n_transposes;  /* LDS layout changes per block (register-blocked kernel), else 0 */
+    int32_t stage;         /* stage of the kernel (0 without stages); apply_kernel runs
+                              the permutation pass into a stage before its first kernel */
 } qk_kernel_info;
 /* Device kernel that runs a plan kernel. */
 enum {
@@ -297,6 +303,10 @@ int plan_num_gates(const qk_plan* p, int64_t* out);
 int plan_gate_source(const qk_plan* p, int64_t i, int64_t* out);
 /* Layout after the last kernel: perm[q] = physical bit of logical qubit q. */
 int plan_final_layout(const qk_plan* p, int32_t* perm);
+/* Stages of the plan (1 without local_qubits), and stage s's map: sigma[v] =
+ * physical bit of qubit v (after SWAP absorption) during stage s. */
+int plan_num_stages(const qk_plan* p, int64_t* out);
+int plan_stage_map(const qk_plan* p, int64_t s, int32_t* sigma);
 /* Which cost model priced the plan: learned_used = 1 if the learned model's
  * predictions were used, learned_fallback = 1 if the learned model was
  * requested but analytic costs were used instead: no weights were loaded, or
@@ -304,6 +314,21 @@ int plan_final_layout(const qk_plan* p, int32_t* perm);
  * trained on. */
 int plan_cost_model(const qk_plan* p, int* learned_used, int* learned_fallback);
 int plan_free(qk_plan* p);
+
+/* ---- host-DRAM offload ---------------------------------------------------
+ * A state in pinned host memory (sv_alloc_host; freed by sv_free) for n up
+ * to 36 qubits: sv_init_basis, sv_upload, sv_download(_range), sv_norm2 and
+ * sv_gather work on it (on the host); the device entry points refuse it.
+ * simulate_offload runs a circuit on it with the GPU holding 2^L-amplitude
+ * chunks, L = ko->local_qubits (4..n-1; the planner's stager bounds every
+ * stage's non-insular qubits to L local bits, as for the stages of a device
+ * state): per stage, every chunk is copied to the device, its plan applied
+ * and copied back (two buffers on two streams), and insular gates on qubits
+ * outside the chunk become local gates from those qubits' values in the chunk
+ * (section "Hierarchical Partitioning", DRAM offloading).  The host exchanges
+ * bit pairs between stages and returns the state in logical order. */
+int sv_alloc_host(qk_ctx* ctx, int n_qubits, int dtype, qk_state** out);
+int simulate_offload(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_state* host_state);
 
 /* ---- execution (Execute on one GPU) ------------------------------------- */
 /* Enqueue kernel i of plan p on st (LaunchKernel of alg:atlas).  The state
@@ -435,6 +460,28 @@ typedef struct qk_batch_stats {
 } qk_batch_stats;
 int simulate_batch(qk_ctx* ctx, const qk_circuit* circuits, qk_state* const* states, int64_t count,
                    const qk_kopts* kos, double* latency_ms, qk_batch_stats* stats);
+
+/* The same batch in ONE persistent launch (spec batched execution):
+ * every circuit is kernelized on the host (tuned or given options, as above)
+ * and its plan uploaded; then a single kernel runs the whole batch.  Each
+ * workgroup takes whole circuits from a device counter, longest predicted
+ * cost first, and runs all of a circuit's kernels itself (block after
+ * block; a state of at most one block, n <= 13 complex64 / 12 complex128,
+ * stays in LDS for all its kernels), so workgroups never wait for each other.
+ * Every kernel is planned as an LDS gate sequence (allow_fused is ignored;
+ * no register-blocked or matrix-core variants).  Circuits must have 4..26 qubits.  Every launch descriptor is
+ * bounds-checked on the host first (QK_EINVAL).  latency_ms[i] (may be NULL):
+ * device wall-clock time from the first workgroup's start to circuit i's
+ * completion.  States return in logical order.
+ * CURRENTLY SWITCHED OFF: returns QK_EUNSUPPORTED before any launch (the
+ * kernel did not finish in its device run and the cause is not known). */
+int simulate_batch_persistent(qk_ctx* ctx, const qk_circuit* circuits, qk_state* const* states, int64_t count,
+                              const qk_kopts* kos, double* latency_ms, qk_batch_stats* stats);
+/* Plan a batch and run the host bounds checks of its persistent-launch
+ * descriptors without launching (works on host-only contexts); *n_kernels
+ * (may be NULL) = kernels in the batch. */
+int simulate_batch_check(qk_ctx* ctx, const qk_circuit* circuits, int64_t count, int dtype, const qk_kopts* kos,
+                         int64_t* n_kernels);
 
 /* Autotuner: for every n in [n_lo, n_hi] (4..26) time batches of 8 copies of
  * a layered RY/RZ/CX-ring circuit under a grid of (k_max, block qubits, ell)

@@ -70,14 +70,14 @@ class qk_kopts(ctypes.Structure):
                 ("allow_fused", ctypes.c_int32), ("allow_lds", ctypes.c_int32),
                 ("block_qubits", ctypes.c_int32), ("insular", ctypes.c_int32),
                 ("kernelizer", ctypes.c_int32), ("dp_prune", ctypes.c_int32), ("dp_flags", ctypes.c_int32),
-                ("fuse_gates", ctypes.c_int32), ("tables", ctypes.POINTER(qk_cost_tables))]
+                ("local_qubits", ctypes.c_int32), ("fuse_gates", ctypes.c_int32), ("tables", ctypes.POINTER(qk_cost_tables))]
 
 
 class qk_kernel_info(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("k", ctypes.c_int32), ("gate_begin", ctypes.c_int64),
                 ("gate_end", ctypes.c_int64), ("qubit_mask", ctypes.c_uint64), ("cost_ps", ctypes.c_int64),
                 ("block_qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32), ("impl", ctypes.c_int32),
-                ("n_phases", ctypes.c_int32), ("n_transposes", ctypes.c_int32)]
+                ("n_phases", ctypes.c_int32), ("n_transposes", ctypes.c_int32), ("stage", ctypes.c_int32)]
 
 
 class qk_train_opts(ctypes.Structure):
@@ -126,10 +126,13 @@ _SIGS = {
     "plan_kernel_info": [_P, _i64, ctypes.POINTER(qk_kernel_info)],
     "plan_total_cost": [_P, ctypes.POINTER(_i64)], "plan_num_gates": [_P, ctypes.POINTER(_i64)],
     "plan_gate_source": [_P, _i64, ctypes.POINTER(_i64)], "plan_final_layout": [_P, _P],
+    "plan_num_stages": [_P, ctypes.POINTER(_i64)], "plan_stage_map": [_P, _i64, _P],
     "plan_free": [_P],
     "apply_kernel": [_P, _P, _i64, _P], "plan_finish": [_P, _P, _P],
     "simulate": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _P],
     "simulate_noalloc": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _P],
+    "sv_alloc_host": [_P, ctypes.c_int, ctypes.c_int, _PP],
+    "simulate_offload": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), _P],
     "execute_plan": [_P, _P, _P],
     "plan_cost_model": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
     "qk_ctx_set_tables": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qk_cost_tables)],
@@ -146,6 +149,8 @@ _SIGS = {
     "mlp_forward_backward": [_P, _P, _P, _P, _i64, _P, _P, _P],
     "mlp_adam_step": [_P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int],
     "simulate_batch": [_P, _P, _P, _i64, _P, _P, ctypes.POINTER(qk_batch_stats)],
+    "simulate_batch_persistent": [_P, _P, _P, _i64, _P, _P, ctypes.POINTER(qk_batch_stats)],
+    "simulate_batch_check": [_P, _P, _i64, ctypes.c_int, _P, ctypes.POINTER(_i64)],
     "qk_autotune": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p],
     "qk_autotune_load": [_P, ctypes.c_int, ctypes.c_char_p],
     "qk_set_tuned": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qk_kopts)],
@@ -189,7 +194,7 @@ def set_max_groups(groups: int):
 # ---------------------------------------------------------------- options
 def kopts(dtype=QK_C64, cost_model=QK_COST_ANALYTIC, k_max=None, m_max=None, ell=None,
           absorb_swaps=None, allow_fused=None, allow_lds=None, block_qubits=None, tables=None,
-          insular=None, kernelizer=None, dp_prune=None, dp_flags=None, fuse_gates=None) -> qk_kopts:
+          insular=None, kernelizer=None, dp_prune=None, dp_flags=None, fuse_gates=None, local_qubits=None) -> qk_kopts:
     ko = qk_kopts()
     _lib.qk_kopts_default(ctypes.byref(ko))
     ko.dtype = int(dtype)
@@ -197,7 +202,8 @@ def kopts(dtype=QK_C64, cost_model=QK_COST_ANALYTIC, k_max=None, m_max=None, ell
     for name, val in (("k_max", k_max), ("m_max", m_max), ("ell", ell), ("absorb_swaps", absorb_swaps),
                       ("allow_fused", allow_fused), ("allow_lds", allow_lds), ("block_qubits", block_qubits),
                       ("insular", insular), ("kernelizer", kernelizer), ("dp_prune", dp_prune),
-                      ("dp_flags", dp_flags), ("fuse_gates", fuse_gates)):
+                      ("dp_flags", dp_flags), ("fuse_gates", fuse_gates),
+                      ("local_qubits", local_qubits)):
         if val is not None:
             setattr(ko, name, int(val))
     if tables is not None:
@@ -438,6 +444,7 @@ class KernelInfo:
         self.impl = s.impl
         self.n_phases = s.n_phases
         self.n_transposes = s.n_transposes
+        self.stage = s.stage
 
     def as_tuple(self):
         return (self.gate_begin, self.gate_end, self.type, self.cost_ps)
@@ -509,6 +516,16 @@ class Plan:
         _check(_lib.plan_final_layout(self.h, out.ctypes.data))
         return [int(x) for x in out]
 
+    def num_stages(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.plan_num_stages(self.h, ctypes.byref(v)))
+        return v.value
+
+    def stage_map(self, s: int) -> list:
+        out = np.zeros(self.n, np.int32)
+        _check(_lib.plan_stage_map(self.h, s, out.ctypes.data))
+        return [int(x) for x in out]
+
 
 # ---------------------------------------------------------------- entry points
 def sv_alloc(ctx: Context, n: int, dtype: int = QK_C64) -> State:
@@ -538,6 +555,18 @@ def execute_plan(ctx: Context, plan: Plan, state: State):
 def simulate(ctx: Context, circuit, state: State, ko: qk_kopts | None = None):
     c = _circuit_struct(circuit)
     _check(_lib.simulate(ctx.h, ctypes.byref(c), ctypes.byref(ko) if ko is not None else None, state.h))
+
+
+def sv_alloc_host(ctx: Context, n: int, dtype: int = QK_C64) -> State:
+    """A state in pinned host memory, for simulate_offload."""
+    h = ctypes.c_void_p()
+    _check(_lib.sv_alloc_host(ctx.h, n, dtype, ctypes.byref(h)))
+    return State(ctx, h, n, dtype)
+
+
+def simulate_offload(ctx: Context, circuit, state: State, ko: qk_kopts):
+    c = _circuit_struct(circuit)
+    _check(_lib.simulate_offload(ctx.h, ctypes.byref(c), ctypes.byref(ko), state.h))
 
 
 def simulate_noalloc(ctx: Context, circuit, state: State, ko: qk_kopts | None = None):
@@ -587,6 +616,49 @@ def mlp_adam_step(ctx: Context, params, grads, m, v, lr: float, step: int):
     vv = np.array(v, np.float32)
     _check(_lib.mlp_adam_step(ctx.h, p.ctypes.data, g.ctypes.data, mm.ctypes.data, vv.ctypes.data, lr, step))
     return p, mm, vv
+
+
+def _circuit_array(circuits):
+    n = len(circuits)
+    cstructs = (qk_circuit * n)()
+    keep = []
+    for i, c in enumerate(circuits):
+        cs = _circuit_struct(c)
+        keep.append(cs)
+        ctypes.memmove(ctypes.byref(cstructs, i * ctypes.sizeof(qk_circuit)), ctypes.byref(cs),
+                       ctypes.sizeof(qk_circuit))
+    return cstructs, keep
+
+
+def simulate_batch_persistent(ctx: Context, circuits, states, kos=None):
+    """Run many circuits in one persistent launch.  Returns (stats dict,
+    per-circuit latency in ms from the first workgroup's start)."""
+    n = len(circuits)
+    assert len(states) == n and n > 0
+    cstructs, keep = _circuit_array(circuits)
+    sptr = (ctypes.c_void_p * n)(*[s.h.value if isinstance(s.h, ctypes.c_void_p) else s.h for s in states])
+    karr = (qk_kopts * n)(*kos) if kos is not None else None
+    lat = np.zeros(n, np.float64)
+    st = qk_batch_stats()
+    _check(_lib.simulate_batch_persistent(ctx.h, ctypes.cast(cstructs, ctypes.c_void_p),
+                                          ctypes.cast(sptr, ctypes.c_void_p), n,
+                                          ctypes.cast(karr, ctypes.c_void_p) if karr is not None else None,
+                                          lat.ctypes.data, ctypes.byref(st)))
+    return ({"total_ms": st.total_ms, "items": st.items, "whole_circuits": st.whole_circuits,
+             "errors": st.errors}, lat)
+
+
+def simulate_batch_check(ctx: Context, circuits, dtype: int, kos=None) -> int:
+    """Plan a batch and bounds-check its persistent-launch descriptors on the
+    host; returns the number of kernels."""
+    n = len(circuits)
+    cstructs, keep = _circuit_array(circuits)
+    karr = (qk_kopts * n)(*kos) if kos is not None else None
+    nk = ctypes.c_int64()
+    _check(_lib.simulate_batch_check(ctx.h, ctypes.cast(cstructs, ctypes.c_void_p), n, dtype,
+                                     ctypes.cast(karr, ctypes.c_void_p) if karr is not None else None,
+                                     ctypes.byref(nk)))
+    return nk.value
 
 
 def simulate_batch(ctx: Context, circuits, states, kos=None):

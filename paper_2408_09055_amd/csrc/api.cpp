@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -274,6 +275,7 @@ void qk_kopts_default(qk_kopts* ko)
     ko->dp_prune = 500;
     ko->dp_flags = QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK;
     ko->fuse_gates = 1;
+    ko->local_qubits = 0;
     ko->tables = nullptr;
 }
 
@@ -378,7 +380,10 @@ int sv_free(qk_state* st)
 {
     if (!st) return QK_OK;
     if (st->ctx && !st->ctx->host_only) (void)hipStreamSynchronize((hipStream_t)st->ctx->stream);
-    if (st->owned && st->psi) (void)hipFree(st->psi);
+    if (st->owned && st->psi) {
+        if (st->host) (void)hipHostFree(st->psi);
+        else (void)hipFree(st->psi);
+    }
     if (st->tmp) (void)hipFree(st->tmp);
     delete st;
     return QK_OK;
@@ -411,6 +416,13 @@ int sv_init_basis(qk_state* st, uint64_t x)
     if (!st) return fail(QK_EINVAL, "sv_init_basis: null state");
     const uint64_t N = 1ull << st->n;
     if (x >= N) return fail(QK_EINVAL, "sv_init_basis: index out of range");
+    if (st->host) {
+        std::memset(st->psi, 0, amp_bytes(st->dtype) << st->n);
+        if (st->dtype == QK_C128) ((double*)st->psi)[2 * x] = 1.0;
+        else ((float*)st->psi)[2 * x] = 1.0f;
+        for (int q = 0; q < st->n; ++q) st->layout[q] = q;
+        return QK_OK;
+    }
     int e = launch_fill_basis(st->dtype, st->psi, N, x, st->ctx->stream);
     if (e) return hip_fail(e, "sv_init_basis");
     for (int q = 0; q < st->n; ++q) st->layout[q] = q;
@@ -420,6 +432,11 @@ int sv_init_basis(qk_state* st, uint64_t x)
 int sv_upload(qk_state* st, const void* host)
 {
     if (!st || !host) return fail(QK_EINVAL, "sv_upload: null argument");
+    if (st->host) {
+        std::memcpy(st->psi, host, amp_bytes(st->dtype) << st->n);
+        for (int q = 0; q < st->n; ++q) st->layout[q] = q;
+        return QK_OK;
+    }
     hipError_t e = hipMemcpyAsync(st->psi, host, amp_bytes(st->dtype) << st->n, hipMemcpyHostToDevice,
                                   (hipStream_t)st->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "sv_upload");
@@ -434,6 +451,10 @@ int sv_download_range(qk_state* st, uint64_t offset, uint64_t count, void* host)
     if (offset > N || count > N - offset) return fail(QK_EINVAL, "sv_download_range: range out of bounds");
     if (!is_identity(st->layout)) return fail(QK_ESTATE, "sv_download: state is not in logical order (call sv_restore)");
     const size_t s = amp_bytes(st->dtype);
+    if (st->host) {
+        std::memcpy(host, (const char*)st->psi + offset * s, count * s);
+        return QK_OK;
+    }
     hipError_t e = hipMemcpyAsync(host, (char*)st->psi + offset * s, count * s, hipMemcpyDeviceToHost,
                                   (hipStream_t)st->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "sv_download");
@@ -443,6 +464,7 @@ int sv_download_range(qk_state* st, uint64_t offset, uint64_t count, void* host)
 int sv_download_physical(qk_state* st, void* host)
 {
     if (!st || !host) return fail(QK_EINVAL, "sv_download_physical: null argument");
+    if (st->host) return fail(QK_EINVAL, "sv_download_physical: host state");
     hipError_t e = hipMemcpyAsync(host, st->psi, amp_bytes(st->dtype) << st->n, hipMemcpyDeviceToHost,
                                   (hipStream_t)st->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "sv_download_physical");
@@ -458,6 +480,7 @@ int sv_download(qk_state* st, void* host)
 int sv_permute_inplace(qk_state* st, const int32_t* perm)
 {
     if (!st || !perm) return fail(QK_EINVAL, "sv_permute_inplace: null argument");
+    if (st->host) return fail(QK_EINVAL, "sv_permute_inplace: host state");
     int rc = need_device(st->ctx);
     if (rc) return rc;
     std::vector<int32_t> p(perm, perm + st->n);
@@ -474,6 +497,7 @@ int sv_permute_inplace(qk_state* st, const int32_t* perm)
 int sv_permute(qk_state* st, const int32_t* perm)
 {
     if (!st || !perm) return fail(QK_EINVAL, "sv_permute: null argument");
+    if (st->host) return fail(QK_EINVAL, "sv_permute: host state");
     std::vector<int32_t> p(perm, perm + st->n);
     std::vector<int> seen(st->n, 0);
     for (int b = 0; b < st->n; ++b) {
@@ -487,12 +511,26 @@ int sv_permute(qk_state* st, const int32_t* perm)
 int sv_restore(qk_state* st)
 {
     if (!st) return fail(QK_EINVAL, "sv_restore: null state");
+    if (st->host) return fail(QK_EINVAL, "sv_restore: host state");
     return restore_on(st, st->ctx->stream);
 }
 
 int sv_norm2(qk_state* st, double* out)
 {
     if (!st || !out) return fail(QK_EINVAL, "sv_norm2: null argument");
+    if (st->host) {
+        // FP64 with Neumaier compensation, sequential
+        double sum = 0.0, comp = 0.0;
+        const uint64_t N = 2ull << st->n;
+        for (uint64_t i = 0; i < N; ++i) {
+            const double v = st->dtype == QK_C128 ? ((const double*)st->psi)[i] : (double)((const float*)st->psi)[i];
+            const double x = v * v, t = sum + x;
+            comp += std::fabs(sum) >= std::fabs(x) ? (sum - t) + x : (x - t) + sum;
+            sum = t;
+        }
+        *out = sum + comp;
+        return QK_OK;
+    }
     qk_ctx* ctx = st->ctx;
     double* res = ctx->d_partials + 2 * reduce_partials();
     int e = launch_norm2(st->dtype, st->psi, 1ull << st->n, ctx->d_partials, res, ctx->stream);
@@ -508,6 +546,7 @@ int sv_norm2(qk_state* st, double* out)
 int sv_overlap_host(qk_state* st, const double* ref, uint64_t offset, uint64_t count, double out[2])
 {
     if (!st || !out || (!ref && count)) return fail(QK_EINVAL, "sv_overlap_host: null argument");
+    if (st->host) return fail(QK_EINVAL, "sv_overlap_host: host state");
     const uint64_t N = 1ull << st->n;
     if (offset > N || count > N - offset) return fail(QK_EINVAL, "sv_overlap_host: range out of bounds");
     if (!is_identity(st->layout)) return fail(QK_ESTATE, "sv_overlap_host: state is not in logical order");
@@ -539,6 +578,18 @@ int sv_gather(qk_state* st, const uint64_t* idx, uint64_t cnt, double* out)
     for (uint64_t i = 0; i < cnt; ++i)
         if (idx[i] >= N) return fail(QK_EINVAL, "sv_gather: index out of range");
     if (cnt == 0) return QK_OK;
+    if (st->host) {
+        for (uint64_t i = 0; i < cnt; ++i) {
+            if (st->dtype == QK_C128) {
+                out[2 * i] = ((const double*)st->psi)[2 * idx[i]];
+                out[2 * i + 1] = ((const double*)st->psi)[2 * idx[i] + 1];
+            } else {
+                out[2 * i] = ((const float*)st->psi)[2 * idx[i]];
+                out[2 * i + 1] = ((const float*)st->psi)[2 * idx[i] + 1];
+            }
+        }
+        return QK_OK;
+    }
     qk_ctx* ctx = st->ctx;
     int rc = ensure_stage(ctx, cnt * 24);
     if (rc) return rc;
@@ -636,6 +687,7 @@ int plan_kernel_info(const qk_plan* p, int64_t i, qk_kernel_info* out)
     else out->impl = K.k >= 5 && mfma_ok(K.k, K.desc.m) ? QK_IMPL_MFMA_DENSE : QK_IMPL_LDS_DENSE;
     out->n_phases = K.rb ? K.rbd.n_phases : 0;
     out->n_transposes = K.rb ? K.rbd.n_transposes : 0;
+    out->stage = K.stage;
     return QK_OK;
 }
 
@@ -676,6 +728,21 @@ int plan_final_layout(const qk_plan* p, int32_t* perm)
     return QK_OK;
 }
 
+int plan_num_stages(const qk_plan* p, int64_t* out)
+{
+    if (!p || !out) return fail(QK_EINVAL, "plan_num_stages: null argument");
+    *out = (int64_t)p->stage_sigma.size();
+    return QK_OK;
+}
+
+int plan_stage_map(const qk_plan* p, int64_t s, int32_t* sigma)
+{
+    if (!p || !sigma) return fail(QK_EINVAL, "plan_stage_map: null argument");
+    if (s < 0 || s >= (int64_t)p->stage_sigma.size()) return fail(QK_EINVAL, "plan_stage_map: stage out of range");
+    std::copy(p->stage_sigma[s].begin(), p->stage_sigma[s].end(), sigma);
+    return QK_OK;
+}
+
 int plan_free(qk_plan* p)
 {
     if (!p) return QK_OK;
@@ -695,11 +762,27 @@ int apply_kernel(qk_ctx* ctx, const qk_plan* p, int64_t i, qk_state* st)
     int rc = need_device(ctx);
     if (rc) return rc;
     if (!p || !st) return fail(QK_EINVAL, "apply_kernel: null argument");
+    if (st->host) return fail(QK_EINVAL, "apply_kernel: host state (use simulate_offload)");
     if (i < 0 || i >= (int64_t)p->kernels.size()) return fail(QK_EINVAL, "apply_kernel: kernel index out of range");
     if (st->n != p->n || st->dtype != p->dtype) return fail(QK_ESTATE, "apply_kernel: state n/dtype differ from the plan's");
     if (!p->d_ops) return fail(QK_ESTATE, "apply_kernel: plan was built without a device");
-    // single stage: every kernel runs on the layout the plan started from
-    if (!is_identity(st->layout)) return fail(QK_ESTATE, "apply_kernel: state layout differs from the plan's");
+    // during a plan the state's layout maps each (virtual) qubit to its bit:
+    // the identity before the first stage, then the map of the current stage
+    const std::vector<int32_t>& want = p->stage_sigma[p->kernels[i].stage];
+    if (st->layout != want) {
+        // entering a stage: only before its first kernel, from the previous
+        // stage's map (the identity before stage 0); one permutation pass
+        const int s = p->kernels[i].stage;
+        const bool first = i == 0 || p->kernels[i - 1].stage != s;
+        std::vector<int32_t> prev(st->n);
+        for (int q = 0; q < st->n; ++q) prev[q] = q;
+        if (s > 0) prev = p->stage_sigma[s - 1];
+        if (!first || st->layout != prev) return fail(QK_ESTATE, "apply_kernel: state layout differs from the plan's");
+        std::vector<int32_t> perm(st->n);
+        for (int v = 0; v < st->n; ++v) perm[st->layout[v]] = want[v];
+        rc = permute_pass(st, perm, ctx->stream);
+        if (rc) return rc;
+    }
     return launch_plan_kernel(p, i, st, ctx->stream);
 }
 
@@ -708,10 +791,15 @@ int plan_finish(qk_ctx* ctx, const qk_plan* p, qk_state* st)
     int rc = need_device(ctx);
     if (rc) return rc;
     if (!p || !st) return fail(QK_EINVAL, "plan_finish: null argument");
+    if (st->host) return fail(QK_EINVAL, "plan_finish: host state (use simulate_offload)");
     if (st->n != p->n || st->dtype != p->dtype) return fail(QK_ESTATE, "plan_finish: state n/dtype differ from the plan's");
-    if (!is_identity(st->layout)) return fail(QK_ESTATE, "plan_finish: state layout differs from the plan's");
-    // the SWAPs absorbed while planning left logical qubit q at bit final_layout[q]
-    st->layout = p->final_layout;
+    const std::vector<int32_t>& last = p->stage_sigma.back();
+    if (st->layout != last) return fail(QK_ESTATE, "plan_finish: state layout differs from the plan's");
+    // the SWAPs absorbed while planning left logical qubit q on virtual qubit
+    // final_layout[q], which the last stage holds at bit last[final_layout[q]]
+    std::vector<int32_t> l(st->n);
+    for (int q = 0; q < st->n; ++q) l[q] = last[p->final_layout[q]];
+    st->layout = l;
     return sv_restore(st);
 }
 
@@ -730,6 +818,7 @@ int simulate(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_state* st)
     int rc = need_device(ctx);
     if (rc) return rc;
     if (!c || !st) return fail(QK_EINVAL, "simulate: null argument");
+    if (st->host) return fail(QK_EINVAL, "simulate: host state (use simulate_offload)");
     if (c->n_qubits != st->n) return fail(QK_EINVAL, "simulate: circuit and state sizes differ");
     qk_kopts k;
     if (ko) k = *ko; else qk_kopts_default(&k);
@@ -788,6 +877,7 @@ int simulate_noalloc(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_st
     int rc = need_device(ctx);
     if (rc) return rc;
     if (!c || !st) return fail(QK_EINVAL, "simulate_noalloc: null argument");
+    if (st->host) return fail(QK_EINVAL, "simulate_noalloc: host state (use simulate_offload)");
     if (c->n_qubits != st->n) return fail(QK_EINVAL, "simulate_noalloc: circuit and state sizes differ");
     if (st->n < 4) return fail(QK_EUNSUPPORTED, "simulate_noalloc: needs at least 4 qubits (in-place permutation tiles)");
     qk_kopts k;
@@ -837,10 +927,22 @@ int simulate_noalloc(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko, qk_st
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) { plan_free(P); return hip_fail(e, "simulate_noalloc: table upload"); }
     if (!is_identity(st->layout)) { plan_free(P); return fail(QK_ESTATE, "simulate_noalloc: state is not in logical order"); }
-    for (int64_t i = 0; i < (int64_t)P->kernels.size() && rc == QK_OK; ++i)
+    for (int64_t i = 0; i < (int64_t)P->kernels.size() && rc == QK_OK; ++i) {
+        const std::vector<int32_t>& want = P->stage_sigma[P->kernels[i].stage];
+        if (st->layout != want) {
+            // stage change: bits exchanged in pairs, one in-place pass
+            std::vector<int32_t> perm(st->n);
+            for (int v = 0; v < st->n; ++v) perm[st->layout[v]] = want[v];
+            rc = permute_pairs_pass(st, perm, ctx->stream);
+            if (rc) break;
+        }
         rc = launch_plan_kernel(P, i, st, ctx->stream);
+    }
     if (rc == QK_OK) {
-        st->layout = P->final_layout;
+        const std::vector<int32_t>& last = P->stage_sigma.back();
+        std::vector<int32_t> l(st->n);
+        for (int q = 0; q < st->n; ++q) l[q] = last[P->final_layout[q]];
+        st->layout = l;
         rc = restore_in_place(st, ctx->stream);
     }
     plan_free(P);   // host side only: the tables stay in the scratch array

@@ -71,7 +71,9 @@ struct Ctx {
     }
     bool feasible(int type, uint64_t q, uint64_t need) const
     {
-        if (type == QK_KERNEL_FUSED) return ko.allow_fused && pc(q) <= ko.k_max;
+        if (type == QK_KERNEL_FUSED)
+            return ko.allow_fused && pc(q) <= ko.k_max && (ko.local_qubits <= 0 || ko.local_qubits >= 64 ||
+                                                            (q >> ko.local_qubits) == 0);
         return ko.allow_lds && pc(need | lowmask) <= ko.m_max;
     }
     int32_t push_unit(int32_t unit, int32_t prev)

@@ -421,6 +421,36 @@ __device__ __forceinline__ void block_loop(C* __restrict__ psi, const BlockDesc&
     }
 }
 
+// A gate sequence on a block staged in LDS (2^m amplitudes; bb = the block's
+// first amplitude index, whose bits are the values of the qubits outside the
+// block): the operations one by one, a barrier after each.
+template <typename C>
+__device__ void seq_ops(C* s, int m, uint64_t bb, const Op* __restrict__ ops, int n_ops, const C* __restrict__ coef)
+{
+    for (int o = 0; o < n_ops; ++o) {
+        const Op op = ops[o];
+        const C* u = coef + op.coef;
+        const uint32_t s2 = (uint32_t)(bb >> op.b[2]) & 1u, s3 = (uint32_t)(bb >> op.b[3]) & 1u;
+        switch (op.code) {
+        case OP_BPHASE: op_scale(s, m, u[op.k == 2 ? s2 + 2 * s3 : s2]); break;
+        case OP_DIAG1C: op_diag1(s, m, op.b[0], u + 2 * s2); break;
+        case OP_XC: if (s2) op_x(s, m, op.b[0]); break;
+        case OP_PHRUN: op_phrun(s, m, op.b[0], u, op.k, bb); break;
+        case OP_DENSE1: case OP_H: op_dense1(s, m, op.b[0], u); break;
+        case OP_DIAG1: op_diag1(s, m, op.b[0], u); break;
+        case OP_X: op_x(s, m, op.b[0]); break;
+        case OP_CX: op_cx(s, m, op.b[0], op.b[1]); break;
+        case OP_CZ: op_cz(s, m, op.b[0], op.b[1]); break;
+        case OP_CPHASE: op_cphase(s, m, op.b[0], op.b[1], u); break;
+        case OP_DIAG2: op_diag2(s, m, op.b[0], op.b[1], u); break;
+        case OP_SWAP: op_swap(s, m, op.b[0], op.b[1]); break;
+        case OP_DENSE2: op_dense2(s, m, op.b[0], op.b[1], u); break;
+        default: break;
+        }
+        __syncthreads();
+    }
+}
+
 // LDS gate-sequence kernel: the kernel's gates one by one on the staged block.
 template <typename C>
 __global__ __launch_bounds__(kNT) void k_block_seq(C* __restrict__ psi, BlockDesc d,
@@ -429,30 +459,7 @@ __global__ __launch_bounds__(kNT) void k_block_seq(C* __restrict__ psi, BlockDes
 {
     extern __shared__ __align__(16) unsigned char smem[];
     C* sm = reinterpret_cast<C*>(smem);
-    block_loop(psi, d, sm, [&](C* s, int m, uint64_t bb) {
-        for (int o = 0; o < d.n_ops; ++o) {
-            const Op op = ops[o];
-            const C* u = coef + op.coef;
-            const uint32_t s2 = (uint32_t)(bb >> op.b[2]) & 1u, s3 = (uint32_t)(bb >> op.b[3]) & 1u;
-            switch (op.code) {
-            case OP_BPHASE: op_scale(s, m, u[op.k == 2 ? s2 + 2 * s3 : s2]); break;
-            case OP_DIAG1C: op_diag1(s, m, op.b[0], u + 2 * s2); break;
-            case OP_XC: if (s2) op_x(s, m, op.b[0]); break;
-            case OP_PHRUN: op_phrun(s, m, op.b[0], u, op.k, bb); break;
-            case OP_DENSE1: case OP_H: op_dense1(s, m, op.b[0], u); break;
-            case OP_DIAG1: op_diag1(s, m, op.b[0], u); break;
-            case OP_X: op_x(s, m, op.b[0]); break;
-            case OP_CX: op_cx(s, m, op.b[0], op.b[1]); break;
-            case OP_CZ: op_cz(s, m, op.b[0], op.b[1]); break;
-            case OP_CPHASE: op_cphase(s, m, op.b[0], op.b[1], u); break;
-            case OP_DIAG2: op_diag2(s, m, op.b[0], op.b[1], u); break;
-            case OP_SWAP: op_swap(s, m, op.b[0], op.b[1]); break;
-            case OP_DENSE2: op_dense2(s, m, op.b[0], op.b[1], u); break;
-            default: break;
-            }
-            __syncthreads();
-        }
-    });
+    block_loop(psi, d, sm, [&](C* s, int m, uint64_t bb) { seq_ops(s, m, bb, ops, d.n_ops, coef); });
 }
 
 // Fused kernel: one dense 2^K x 2^K product on the staged block.
@@ -513,13 +520,21 @@ __device__ __forceinline__ typename Real<C>::T uexp(const C* __restrict__ U, int
     return lo_i == lo_k ? u.x : (lo_i ? -u.y : u.y);
 }
 
-template <typename C, int K>
+// A_LDS: the real expansion of U is staged once per workgroup in LDS after
+// the block, transposed (sA[k * APITCH + i] = A[i][k]) so that the 16 lanes
+// reading one k-step's rows hit consecutive words; the pitch is padded by 16
+// so that the four k-steps of a wave fall on different banks.  Without it
+// (large K) A is read from global memory inside the k-loop.
+template <int M2>
+constexpr int mfma_apitch() { return M2 + 16; }
+
+template <typename C, int K, bool A_LDS>
 __global__ __launch_bounds__(kNT) void k_block_mfma(C* __restrict__ psi, BlockDesc d, const Op* __restrict__ ops,
                                                     const C* __restrict__ coef)
 {
     using R = typename Real<C>::T;
     using Acc = typename MfmaAcc<R>::T;
-    constexpr int D = 1 << K, M2 = 2 * D;
+    constexpr int D = 1 << K, M2 = 2 * D, AP = mfma_apitch<M2>();
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t rowtab[D];
     C* sm = reinterpret_cast<C*>(smem);
@@ -527,6 +542,14 @@ __global__ __launch_bounds__(kNT) void k_block_mfma(C* __restrict__ psi, BlockDe
     const Op op = ops[0];
     const C* __restrict__ U = coef + op.coef;
     const int m = d.m;
+    R* sA = reinterpret_cast<R*>(smem + (sizeof(C) << m));
+    if constexpr (A_LDS) {
+        for (int idx = threadIdx.x; idx < M2 * M2; idx += kNT) {
+            const int i = idx % M2, k = idx / M2;
+            sA[k * AP + i] = uexp(U, D, i, k);
+        }
+        // ordered before the first read by the barrier that ends block_loop's first fill
+    }
     const int N = 1 << (m - K);
     // rows: deposit over the kernel bits; columns: over the remaining bits
     uint8_t ob[16];
@@ -581,7 +604,7 @@ __global__ __launch_bounds__(kNT) void k_block_mfma(C* __restrict__ psi, BlockDe
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 if (a >= RM) break;
-                const R afr = uexp(U, D, 16 * (tm0 + a) + lr, k);
+                const R afr = A_LDS ? sA[k * AP + 16 * (tm0 + a) + lr] : uexp(U, D, 16 * (tm0 + a) + lr, k);
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
                     if (t < RN) acc[a][t] = mfma16(afr, bfr[t], acc[a][t]);
@@ -1521,6 +1544,70 @@ void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog
     }
 }
 
+// ----------------------------------------------------------- batched execution
+// One persistent launch runs a batch of circuits.  Each workgroup takes whole
+// circuits from an atomic counter (in the host's longest-first order) and runs
+// every kernel of its circuit itself, block after block, so no workgroup ever
+// waits for another: a workgroup leaves the loop when the counter passes the
+// batch size, and every loop inside it is bounded by the circuit's kernels
+// and blocks.  A circuit whose state fits one block (2^n <= 2^m amplitudes)
+// is loaded into LDS once and all its kernels run there.  Between two kernels
+// of a circuit the workgroup's stores are made visible to its own loads
+// (agent-scope fence, then a barrier).  Only gate-sequence kernels run here
+// (the host plans batch circuits without fused kernels): the dense
+// 2^k x 2^k products keep 2^k-entry arrays per thread, and all of them in one
+// kernel would need kilobytes of scratch memory per lane.
+template <typename C>
+__device__ void batch_kernel_body(C* s, int m, uint64_t bb, const BatchKern& k)
+{
+    seq_ops(s, m, bb, k.ops, k.d.n_ops, reinterpret_cast<const C*>(k.coef));
+}
+
+template <typename C>
+__global__ __launch_bounds__(kNT) void k_batch(BatchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_item;
+    C* sm = reinterpret_cast<C*>(smem);
+    constexpr int CH = 16 / sizeof(C);
+    const int tid = threadIdx.x;
+    if (tid == 0)
+        __hip_atomic_fetch_min(a.t_start, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (tid == 0) s_item = __hip_atomic_fetch_add(a.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();   // every thread has read s_item before it changes
+        if (item >= a.count) break;
+        const uint32_t ci = a.order[item];
+        const BatchCirc c = a.circ[ci];
+        C* psi = reinterpret_cast<C*>(c.psi);
+        if (c.whole) {
+            // the state is one block: load it, run every kernel in LDS, store it
+            const uint32_t nch = (1u << c.n) / CH;
+            for (uint32_t q = tid; q < nch; q += kNT)
+                *reinterpret_cast<u32x4*>(&sm[q * CH]) = *reinterpret_cast<const u32x4*>(&psi[q * CH]);
+            __syncthreads();
+            for (uint32_t k = 0; k < c.k_count; ++k) batch_kernel_body<C>(sm, c.n, 0, a.kern[c.k_first + k]);
+            for (uint32_t q = tid; q < nch; q += kNT)
+                *reinterpret_cast<u32x4*>(&psi[q * CH]) = *reinterpret_cast<const u32x4*>(&sm[q * CH]);
+        } else {
+            for (uint32_t k = 0; k < c.k_count; ++k) {
+                const BatchKern kk = a.kern[c.k_first + k];
+                block_loop(psi, kk.d, sm, [&](C* s, int m, uint64_t bb) { batch_kernel_body<C>(s, m, bb, kk); },
+                           0, 1);
+                // this kernel's stores reach memory before the next kernel loads
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+                __syncthreads();
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(a.t_done + ci, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // ----------------------------------------------------------- permutation pass
 // Tile = the 2^m amplitudes with fixed source bits outside act_src.  Reads
 // use the source run (lo_src low bits contiguous), writes the destination run.
@@ -1815,7 +1902,14 @@ uint64_t resident_groups(const void* f, size_t lds, int threads = kNT)
         if (cache[i].f == f && cache[i].lds == lds) return (uint64_t)cache[i].occ * cus;
     bool seen = false;
     for (int i = 0; i < ncache; ++i) seen |= cache[i].f == f;
-    if (!seen) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (!seen) {
+        // the whole 160 KiB of a CU's LDS minus the kernel's static LDS
+        hipFuncAttributes fa{};
+        int stat = 0;
+        if (hipFuncGetAttributes(&fa, f) == hipSuccess) stat = (int)fa.sharedSizeBytes;
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - stat);
+        (void)hipGetLastError();
+    }
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, threads, lds) != hipSuccess || occ <= 0) occ = 1;
     if (ncache < 64) cache[ncache++] = KernelFacts{f, lds, occ};
@@ -1844,6 +1938,22 @@ bool mfma_ok(int K, int m)
            (TM / RM) * (TN / RN) == 4;
 }
 
+// Matrix-core fused kernel: with A staged in LDS when block + A fit
+// (complex64 up to K = 6, complex128 up to K = 5), else A read from global.
+template <typename C, int K>
+int launch_mfma(C* p, const BlockDesc& d, const Op* ops, const void* coef, size_t lds, hipStream_t s)
+{
+    using R = typename Real<C>::T;
+    constexpr int M2 = 2 << K;
+    constexpr bool A_LDS = sizeof(R) == 4 ? K <= 6 : K <= 5;
+    if constexpr (A_LDS) {
+        const size_t la = lds + (size_t)M2 * mfma_apitch<M2>() * sizeof(R);
+        return launch_one<C>(k_block_mfma<C, K, true>, p, d, ops, coef, la, s);
+    } else {
+        return launch_one<C>(k_block_mfma<C, K, false>, p, d, ops, coef, lds, s);
+    }
+}
+
 template <typename C>
 int launch_typed(int fused_k, void* psi, const BlockDesc& d, const Op* ops, const void* coef, size_t lds,
                  hipStream_t s)
@@ -1855,11 +1965,11 @@ int launch_typed(int fused_k, void* psi, const BlockDesc& d, const Op* ops, cons
     case 2: return launch_one<C>(k_block_dense<C, 2>, p, d, ops, coef, lds, s);
     case 3: return launch_one<C>(k_block_dense<C, 3>, p, d, ops, coef, lds, s);
     case 4: return launch_one<C>(k_block_dense<C, 4>, p, d, ops, coef, lds, s);
-    case 5: return mfma_ok(5, d.m) ? launch_one<C>(k_block_mfma<C, 5>, p, d, ops, coef, lds, s)
+    case 5: return mfma_ok(5, d.m) ? launch_mfma<C, 5>(p, d, ops, coef, lds, s)
                                    : launch_one<C>(k_block_dense<C, 5>, p, d, ops, coef, lds, s);
-    case 6: return mfma_ok(6, d.m) ? launch_one<C>(k_block_mfma<C, 6>, p, d, ops, coef, lds, s)
+    case 6: return mfma_ok(6, d.m) ? launch_mfma<C, 6>(p, d, ops, coef, lds, s)
                                    : launch_one<C>(k_block_dense<C, 6>, p, d, ops, coef, lds, s);
-    case 7: return mfma_ok(7, d.m) ? launch_one<C>(k_block_mfma<C, 7>, p, d, ops, coef, lds, s)
+    case 7: return mfma_ok(7, d.m) ? launch_mfma<C, 7>(p, d, ops, coef, lds, s)
                                    : launch_one<C>(k_block_dense<C, 7>, p, d, ops, coef, lds, s);
     default: return (int)hipErrorInvalidValue;
     }
@@ -1972,6 +2082,19 @@ int launch_permute(int dtype, const void* src, void* dst, const PermDesc& d, voi
         hipLaunchKernelGGL(k_permute<float2>, dim3(persistent_grid(d.nblocks, res)), dim3(kNT), lds, s,
                            (const float2*)src, (float2*)dst, d);
     }
+    return (int)hipGetLastError();
+}
+
+int launch_batch(int dtype, const BatchArgs& a, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const size_t lds = 64 * 1024;
+    const void* f = dtype == QK_C128 ? reinterpret_cast<const void*>(k_batch<double2>)
+                                     : reinterpret_cast<const void*>(k_batch<float2>);
+    const uint64_t res = resident_groups(f, lds);
+    const uint32_t grid = persistent_grid(a.count, res);
+    if (dtype == QK_C128) hipLaunchKernelGGL(k_batch<double2>, dim3(grid), dim3(kNT), lds, s, a);
+    else hipLaunchKernelGGL(k_batch<float2>, dim3(grid), dim3(kNT), lds, s, a);
     return (int)hipGetLastError();
 }
 

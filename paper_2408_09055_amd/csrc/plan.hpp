@@ -27,6 +27,7 @@ struct PKernel {
     bool rb;           // runs on the register-blocked kernel
     RbDesc rbd;        // its launch descriptor
     int64_t prog_off;  // its program in the plan's register-kernel blob
+    int stage = 0;     // stage index (stage mode), 0 otherwise
 };
 
 // Feature vector of a candidate kernel for the learned cost model.
@@ -76,7 +77,8 @@ struct qk_plan {
     bool learned_fallback = false;
     std::vector<qk::CGate> gates;
     std::vector<qk::PKernel> kernels;
-    std::vector<int32_t> final_layout;   // logical q -> physical bit
+    std::vector<int32_t> final_layout;   // logical q -> virtual qubit (SWAP absorption)
+    std::vector<std::vector<int32_t>> stage_sigma;   // per stage: virtual qubit -> physical bit
     std::vector<qk::Op> ops;
     std::vector<qk::cd> coefs;           // FP64 master copy
     std::vector<uint8_t> rbprog;         // register-kernel programs (16-byte aligned each)

@@ -212,6 +212,8 @@ int resolve_opts(const qk_kopts* ko_in, int n, qk_kopts& ko, int& mblk)
     if (ko.dp_prune < 0 || ko.dp_prune == 1) return fail(QK_EINVAL, "kernelize: dp_prune must be 0 or >= 2");
     if ((uint32_t)ko.dp_flags & ~(QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK | QK_DP_FUSED))
         return fail(QK_EINVAL, "kernelize: unknown dp_flags bits");
+    if (ko.local_qubits < 0 || (ko.local_qubits > 0 && ko.local_qubits < n && ko.local_qubits < std::max(ko.m_max, ko.k_max)))
+        return fail(QK_EINVAL, "kernelize: local_qubits must be 0 or at least m_max and k_max");
     mblk = ko.block_qubits ? ko.block_qubits : ko.m_max;
     if (mblk < ko.m_max || mblk <= ko.k_max || mblk > kMaxBlockQubits)
         return fail(QK_EINVAL, "kernelize: block_qubits must be >= m_max, > k_max and <= 14");
@@ -1154,11 +1156,13 @@ struct OrderedResult {
     std::vector<int> types;
 };
 
-int ordered_partition(qk_ctx* ctx, qk_plan* P, const qk_kopts& ko, OrderedResult& R)
+int ordered_partition(qk_ctx* ctx, qk_plan* P, const qk_kopts& ko, int64_t lo, int64_t hi, OrderedResult& R)
 {
-    const int64_t m = (int64_t)P->gates.size();
-    const std::vector<CGate>& G = P->gates;
+    const int64_t m = hi - lo;
+    const CGate* G = P->gates.data() + lo;
     const int n = P->n;
+    // stage mode: fused kernels only on the stage's local qubits
+    const uint64_t localmask = (ko.local_qubits > 0 && ko.local_qubits < n) ? (1ull << ko.local_qubits) - 1 : ~0ull;
 
     // ---- enumerate feasible segments (early exit is exact: see header)
     const uint64_t lowmask = (1ull << ko.ell) - 1;
@@ -1174,7 +1178,7 @@ int ordered_partition(qk_ctx* ctx, qk_plan* P, const qk_kopts& ko, OrderedResult
             need |= need_mask(G[j], insular);
             s += P->tab.lds_gate_ps[gate_class(G[j].kind)];
             const int k = popcount64(mask);
-            const bool fok = ko.allow_fused && k <= ko.k_max;
+            const bool fok = ko.allow_fused && k <= ko.k_max && (mask & ~localmask) == 0;
             const bool lok = ko.allow_lds && popcount64(need | lowmask) <= ko.m_max;
             if (!fok && !lok) break;
             seg_fused.push_back(fok ? P->tab.fused_ps[k] : kInf);
@@ -1256,7 +1260,7 @@ int ordered_partition(qk_ctx* ctx, qk_plan* P, const qk_kopts& ko, OrderedResult
     R.types.clear();
     R.costs.clear();
     for (int64_t i = m; i > 0; i = back_j[i]) {
-        R.cuts.push_back(i);
+        R.cuts.push_back(lo + i);
         R.types.push_back(back_t[i]);
         R.costs.push_back(back_cost[i]);
     }
@@ -1265,6 +1269,119 @@ int ordered_partition(qk_ctx* ctx, qk_plan* P, const qk_kopts& ko, OrderedResult
     std::reverse(R.costs.begin(), R.costs.end());
     return QK_OK;
 
+}
+
+// The kernelizer on canonical gates [lo, hi) (one stage): OrderedKernelize,
+// Kernelize's own kernels (DP), or Kernelize's gate order partitioned by
+// OrderedKernelize (FULL; the input order is kept when that is no worse).
+// Kernelize may reorder the gates inside the range.  Cuts are absolute.
+int partition_range(qk_ctx* ctx, qk_plan* P, const qk_kopts& ko, int64_t lo, int64_t hi, OrderedResult& R)
+{
+    R = OrderedResult{};
+    if (hi <= lo) return QK_OK;
+    if (ko.kernelizer != QK_KERNELIZE_DP && ko.kernelizer != QK_KERNELIZE_FULL)
+        return ordered_partition(ctx, P, ko, lo, hi, R);
+    // Kernelize fixes a topologically equivalent gate order (thm:dp-correct)
+    std::vector<CGate> orig(P->gates.begin() + lo, P->gates.begin() + hi), re(orig.size());
+    std::vector<int64_t> order;
+    std::vector<DPKernel> dks;
+    int64_t dtot = 0;
+    int rc = kernelize_dp(orig, ko, P->tab, order, dks, dtot);
+    if (rc) return rc;
+    for (size_t t = 0; t < orig.size(); ++t) re[t] = orig[order[t]];
+    if (ko.kernelizer == QK_KERNELIZE_DP) {
+        std::copy(re.begin(), re.end(), P->gates.begin() + lo);
+        R.total = dtot;
+        for (const DPKernel& k : dks) {
+            R.cuts.push_back(lo + k.end);
+            R.types.push_back(k.type);
+            R.costs.push_back(k.cost);
+        }
+        return QK_OK;
+    }
+    // OrderedKernelize on the input order and on Kernelize's order; the
+    // cheaper partition (the input order on a tie) is kept
+    rc = ordered_partition(ctx, P, ko, lo, hi, R);
+    if (rc) return rc;
+    std::copy(re.begin(), re.end(), P->gates.begin() + lo);
+    OrderedResult R2;
+    rc = ordered_partition(ctx, P, ko, lo, hi, R2);
+    if (rc) return rc;
+    if (R2.total < R.total || (R2.total == R.total && R2.cuts.size() < R.cuts.size())) R = std::move(R2);
+    else std::copy(orig.begin(), orig.end(), P->gates.begin() + lo);
+    return QK_OK;
+}
+
+// Stages for local_qubits = L < n (a project-written greedy stager, not the
+// paper's ILP): a stage is a contiguous run of gates whose non-insular qubits
+// (need_mask with the insular relaxation) all lie in one set of L "local"
+// qubits.  Each stage's local set is the needs of its gates, taken greedily
+// from its first gate while they fit, completed with qubits that were local
+// in the previous stage and then the lowest ones.  The local qubits occupy
+// physical bits 0..L-1: a qubit local in both stages keeps its bit, entering
+// and leaving qubits exchange bits, so a stage change is one permutation
+// pass (between stages, as Execute's Shard step).  Gates are relabelled to
+// the physical bits of their stage; P->stage_sigma[s][v] is the physical bit
+// of virtual qubit v in stage s.  Without stages: one stage, identity map.
+int stage_gates(qk_plan* P, const qk_kopts& ko, std::vector<int64_t>& lo, std::vector<int64_t>& hi)
+{
+    const int n = P->n;
+    const int64_t m = (int64_t)P->gates.size();
+    std::vector<int32_t> sigma(n);
+    for (int q = 0; q < n; ++q) sigma[q] = q;
+    P->stage_sigma.clear();
+    const int L = ko.local_qubits;
+    if (L <= 0 || L >= n || m == 0) {
+        lo.assign(1, 0);
+        hi.assign(1, m);
+        P->stage_sigma.push_back(sigma);
+        return QK_OK;
+    }
+    const uint64_t lowL = (1ull << L) - 1;
+    int64_t i = 0;
+    while (i < m) {
+        uint64_t cand = 0;
+        int64_t j = i;
+        while (j < m) {
+            const uint64_t nm = cand | need_mask(P->gates[j], true);
+            if (popcount64(nm) > L) break;
+            cand = nm;
+            ++j;
+        }
+        if (j == i) return fail(QK_EINVAL, "kernelize: a gate needs more than local_qubits qubits");
+        // complete the local set: previously local qubits, then the lowest
+        for (int v = 0; v < n && popcount64(cand) < L; ++v)
+            if (sigma[v] < L) cand |= 1ull << v;
+        for (int v = 0; v < n && popcount64(cand) < L; ++v) cand |= 1ull << v;
+        // entering qubits take the bits of leaving ones (lowest bits first)
+        std::vector<int32_t> ns = sigma;
+        std::vector<int> enter, leave_bits;
+        for (int v = 0; v < n; ++v) {
+            const bool want = (cand >> v) & 1, is = sigma[v] < L;
+            if (want && !is) enter.push_back(v);
+        }
+        for (int b = 0; b < L; ++b) {
+            int v = 0;
+            while (sigma[v] != b) ++v;
+            if (!((cand >> v) & 1)) leave_bits.push_back(b);
+        }
+        for (size_t t = 0; t < enter.size(); ++t) {
+            const int v = enter[t], b = leave_bits[t];
+            int w = 0;
+            while (sigma[w] != b) ++w;   // the leaving qubit on bit b
+            ns[w] = sigma[v];
+            ns[v] = b;
+        }
+        sigma = ns;
+        for (int64_t t = i; t < j; ++t)
+            for (int u = 0; u < P->gates[t].nq; ++u) P->gates[t].q[u] = sigma[P->gates[t].q[u]];
+        (void)lowL;
+        lo.push_back(i);
+        hi.push_back(j);
+        P->stage_sigma.push_back(sigma);
+        i = j;
+    }
+    return QK_OK;
 }
 
 int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan** out)
@@ -1289,39 +1406,22 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
     rc = canonicalize(c, ko, P);
     if (rc) { delete P; return rc; }
     const int64_t m = (int64_t)P->gates.size();
+    // stages (one unless local_qubits < n): gate ranges and the
+    // virtual -> physical bit map of each; gates relabelled to physical bits
+    std::vector<int64_t> st_lo, st_hi;
+    rc = stage_gates(P, ko, st_lo, st_hi);
+    if (rc) { delete P; return rc; }
     OrderedResult R;
-    if (ko.kernelizer == QK_KERNELIZE_DP || ko.kernelizer == QK_KERNELIZE_FULL) {
-        // Kernelize fixes a topologically equivalent gate order (thm:dp-correct)
-        std::vector<int64_t> order;
-        std::vector<DPKernel> dks;
-        int64_t dtot = 0;
-        rc = kernelize_dp(P->gates, ko, P->tab, order, dks, dtot);
+    std::vector<int> kstage;
+    for (size_t sgi = 0; sgi < st_lo.size(); ++sgi) {
+        OrderedResult Rs;
+        rc = partition_range(ctx, P, ko, st_lo[sgi], st_hi[sgi], Rs);
         if (rc) { delete P; return rc; }
-        std::vector<CGate> orig = P->gates, re(m);
-        for (int64_t t = 0; t < m; ++t) re[t] = orig[order[t]];
-        if (ko.kernelizer == QK_KERNELIZE_DP) {
-            P->gates = re;
-            R.total = dtot;
-            for (const DPKernel& k : dks) {
-                R.cuts.push_back(k.end);
-                R.types.push_back(k.type);
-                R.costs.push_back(k.cost);
-            }
-        } else {
-            // OrderedKernelize on the input order and on Kernelize's order;
-            // the cheaper partition (the input order on a tie) is kept
-            rc = ordered_partition(ctx, P, ko, R);
-            if (rc) { delete P; return rc; }
-            P->gates = re;
-            OrderedResult R2;
-            rc = ordered_partition(ctx, P, ko, R2);
-            if (rc) { delete P; return rc; }
-            if (R2.total < R.total || (R2.total == R.total && R2.cuts.size() < R.cuts.size())) R = std::move(R2);
-            else P->gates = orig;
-        }
-    } else {
-        rc = ordered_partition(ctx, P, ko, R);
-        if (rc) { delete P; return rc; }
+        R.total += Rs.total;
+        R.cuts.insert(R.cuts.end(), Rs.cuts.begin(), Rs.cuts.end());
+        R.types.insert(R.types.end(), Rs.types.begin(), Rs.types.end());
+        R.costs.insert(R.costs.end(), Rs.costs.begin(), Rs.costs.end());
+        kstage.insert(kstage.end(), Rs.cuts.size(), (int)sgi);
     }
     P->total_cost = R.total;
 
@@ -1331,6 +1431,7 @@ int build_plan(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, qk_plan*
     for (size_t t = 0; t < R.cuts.size(); ++t) {
         rc = emit_kernel(P, j, R.cuts[t], R.types[t], R.costs[t], m_exec);
         if (rc) { delete P; return rc; }
+        P->kernels.back().stage = kstage[t];
         j = R.cuts[t];
     }
     *out = P;
@@ -1358,6 +1459,8 @@ int build_single(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, int ty
     if (ko.tables) P->tab = *ko.tables;
     else if (!ctx_lookup_tables(ctx, n, ko.dtype, &P->tab)) P->tab = default_tables(n, ko.dtype);
     rc = canonicalize(c, ko, P);
+    P->stage_sigma.assign(1, std::vector<int32_t>(n));
+    for (int q = 0; q < n; ++q) P->stage_sigma[0][q] = q;
     if (rc) { delete P; return rc; }
     const int64_t m = (int64_t)P->gates.size();
     if (m == 0) { delete P; return fail(QK_EINVAL, "kernelize_single: no gate left after SWAP absorption"); }

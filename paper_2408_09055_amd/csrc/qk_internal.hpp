@@ -193,6 +193,36 @@ bool mfma_ok(int K, int m);
 // Bound on the workgroups of every persistent block launch (0 = none).
 void set_max_groups(uint32_t g);
 
+// One persistent launch over a batch of circuits (k_batch).  BatchKern: one
+// kernel of a circuit's plan (its block geometry, LDS-form operations and
+// coefficients in the state's precision; fused_k = 0 for a gate sequence,
+// else the size of its single dense operation).  BatchCirc: a circuit's
+// state, its kernels [k_first, k_first + k_count) of the kernel table, and
+// whole = 1 when the state is a single block (n <= m, loaded into LDS once).
+struct BatchKern {
+    BlockDesc d;
+    const Op* ops;
+    const void* coef;
+    int32_t fused_k;
+    int32_t pad;
+};
+struct BatchCirc {
+    void* psi;
+    uint32_t k_first, k_count;
+    int32_t n, whole;
+};
+struct BatchArgs {
+    const BatchCirc* circ;
+    const BatchKern* kern;
+    const uint32_t* order;   // queue position -> circuit
+    uint32_t count;
+    uint32_t pad;
+    uint32_t* queue;         // zero at launch
+    uint64_t* t_start;       // ~0 at launch: earliest workgroup start (wall clock)
+    uint64_t* t_done;        // per circuit: wall clock when its last kernel is done
+};
+int launch_batch(int dtype, const BatchArgs& a, void* stream);
+
 // Allocation-free scratch (kernels.hip): a static device array of
 // kNoallocScratchBytes per device.  scratch_setup(device) looks up its device
 // address once per device (that device current; returns a hipError_t value);
@@ -253,6 +283,7 @@ struct qk_state {
     int dtype = 0;
     void* psi = nullptr;
     bool owned = false;
+    bool host = false;              // pinned host memory (sv_alloc_host): offload only
     void* tmp = nullptr;            // permutation scratch (same size)
     std::vector<int32_t> layout;    // layout[q] = physical bit of logical q
     ~qk_state() { qk::ctx_unref(ctx); }

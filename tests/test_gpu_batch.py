@@ -3,11 +3,16 @@ the single-circuit path), latencies are reported, and the autotuner's cache
 round-trips.
 
 The first two tests were written for an earlier single-launch persistent
-batch kernel (workgroups taking circuits from a device queue).  That kernel
-did not finish on the device in two runs, the cause was not found, and it was
-removed; the tests stay, skipped, as the record of that case.  The batch
-executor now deals circuits over HIP streams and runs the same kernels as the
-one-circuit path; the stream_* tests cover it."""
+batch kernel (workgroups taking circuits from a device queue, with waits on
+other workgroups' progress between a circuit's kernels).  That kernel did not
+finish on the device in two runs, the cause was not found, and it was
+removed; the tests stay, skipped, as the record of that case.
+simulate_batch deals circuits over HIP streams (the stream_* tests); the
+persistent_* tests were written for simulate_batch_persistent, a different
+single-launch design in which each workgroup runs whole circuits and never
+waits for another workgroup, with every launch descriptor bounds-checked on
+the host.  It did not return in its device runs either; the entry point is
+switched off and the tests are skipped with that reason."""
 import numpy as np
 import pytest
 
@@ -26,6 +31,11 @@ def ctx():
     yield c
     c.close()
 
+
+PERSISTENT_OFF = ("simulate_batch_persistent (workgroups running whole circuits from a device counter, no "
+                  "waits between workgroups) did not return within the test's time limit in its two device runs "
+                  "(before and after its scratch memory was cut from 8.5 KB to 80 B per lane); its cause is not "
+                  "known and the entry point is switched off (QK_EUNSUPPORTED)")
 
 PERSISTENT_HANG = ("the single-launch persistent batch kernel this test exercised did not finish on the "
                    "device (two runs); it was removed with its cause unfound")
@@ -160,3 +170,78 @@ def test_autotune_and_cache(ctx, tmp_path):
     with pytest.raises(qk.QkError):
         qk.autotune_load(c2, qk.QK_C64, bad)
     c2.close()
+
+
+def _batch_states(ctx, circs, dtype, seed):
+    states, psis = [], []
+    for i, c in enumerate(circs):
+        st = qk.sv_alloc(ctx, c.n_qubits, dtype)
+        psi = W.random_state(c.n_qubits, seed + i)
+        st.upload(psi.astype(st.np_dtype))
+        states.append(st)
+        psis.append(psi)
+    return states, psis
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_persistent_batch_vs_oracle(ctx, dtype):
+    """One persistent launch over uneven circuits: 4..18 qubits (states of
+    one block stay in LDS for all their kernels, larger ones walk their
+    blocks), a QFT-15 with absorbed SWAPs, a SWAP-only-plus-H circuit, an
+    empty circuit, and a random circuit planned without the insular
+    relaxation; every state against the oracle from a random input state."""
+    rng = np.random.default_rng(60 + dtype)
+    circs = W.hea_batch(20, seed=60 + dtype, n_lo=4, n_hi=18, d_lo=2, d_hi=6)
+    circs.append(W.qft(15))
+    circs.append(W.from_list(9, [W.gate(W.SWAP, [0, 8]), W.gate(W.H, [0])]))
+    circs.append(W.from_list(5, []))
+    circs.append(W.random_circuit(14, 80, rng))
+    kos = [qk.kopts(dtype=dtype) for _ in circs]
+    kos[-1] = qk.kopts(dtype=dtype, insular=0)
+    assert qk.simulate_batch_check(ctx, circs, dtype, kos) > 0
+    states, psis = _batch_states(ctx, circs, dtype, 100)
+    print(f"persistent dtype={dtype}: launching {len(circs)} circuits", flush=True)
+    stats, lat = qk.simulate_batch_persistent(ctx, circs, states, kos)
+    print(f"persistent dtype={dtype}: {stats}, latency max {lat.max():.3f} ms", flush=True)
+    assert stats["items"] == len(circs) and stats["whole_circuits"] > 0
+    assert np.all(lat >= 0) and lat.max() <= stats["total_ms"] * 1.5 + 1.0
+    for c, st, psi in zip(circs, states, psis):
+        assert st.layout() == list(range(c.n_qubits))
+        ref = oracle.run(c, psi)
+        got = st.download()
+        assert oracle.fidelity_loss(got, ref) <= _bar(dtype), c.name
+        st.free()
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+def test_persistent_ansatz_sweep(ctx):
+    """The batched-sweep workload in one persistent launch: 256 ansatz
+    circuits (seed 4), n uniform 10..22, depth 4..12, complex64, from
+    |0...0>.  Every circuit against the one-circuit path, the largest ones
+    and a sample against the oracle; circuits/s and p50/p99 latency printed."""
+    circs = W.hea_batch(256, seed=4)
+    states = []
+    for c in circs:
+        st = qk.sv_alloc(ctx, c.n_qubits, qk.QK_C64)
+        st.init_basis(0)
+        states.append(st)
+    print("persistent sweep: launching 256 circuits", flush=True)
+    stats, lat = qk.simulate_batch_persistent(ctx, circs, states)
+    print(f"persistent sweep: {stats['total_ms']:.2f} ms, {256 / stats['total_ms'] * 1e3:.0f} circuits/s, "
+          f"p50={np.percentile(lat, 50):.3f} ms p99={np.percentile(lat, 99):.3f} ms, "
+          f"whole={stats['whole_circuits']}", flush=True)
+    rng = np.random.default_rng(1)
+    sample = set(rng.choice(len(circs), 8, replace=False).tolist())
+    sample.update(int(i) for i in np.argsort([c.n_qubits for c in circs])[-2:])
+    for i, (c, st) in enumerate(zip(circs, states)):
+        got = st.download()
+        if i in sample:
+            ref = oracle.run(c, oracle.basis(c.n_qubits, 0))
+            assert oracle.fidelity_loss(got, ref) <= 1e-6, c.name
+        one = qk.sv_alloc(ctx, c.n_qubits, qk.QK_C64)
+        one.init_basis(0)
+        qk.simulate(ctx, c, one, qk.kopts(dtype=qk.QK_C64))
+        assert oracle.fidelity_loss(got, one.download()) <= 1e-6, c.name
+        one.free()
+        st.free()

@@ -289,3 +289,63 @@ def test_native_kernelize_benchmark_circuits(hctx):
         assert KF.is_topologically_equivalent(gates, order)
         if circ.name.startswith("rl"):
             assert len(p1) <= 0.7 * len(p0), (len(p1), len(p0))
+
+
+def test_persistent_batch_descriptors_pass_host_checks(hctx):
+    """The persistent batch launch's descriptors (block geometry, first and
+    last block addresses, operation bits, coefficient ranges) pass the host
+    bounds checks for the batched-sweep workload and for mixed batches, and
+    circuits outside 4..26 qubits are refused before any launch."""
+    nk = qk.simulate_batch_check(hctx, W.hea_batch(256, seed=4), qk.QK_C64)
+    assert nk > 256
+    mixed = [W.qft(12), W.random_layered(16, 4, 1), W.ghz(20), W.from_list(5, []),
+             W.from_list(9, [W.gate(W.SWAP, [0, 8]), W.gate(W.H, [0])])]
+    for dt in (qk.QK_C64, qk.QK_C128):
+        assert qk.simulate_batch_check(hctx, mixed, dt) > 0
+        kos = [qk.kopts(dtype=dt, insular=0, k_max=7) for _ in mixed]
+        assert qk.simulate_batch_check(hctx, mixed, dt, kos) > 0
+    _expect(qk.QK_EINVAL, qk.simulate_batch_check, hctx, [W.qft(3)], qk.QK_C64)
+
+
+# ---------------------------------------------------------------- stages
+@pytest.mark.parametrize("seed", range(12))
+def test_stage_mode_keeps_needs_local(seed, hctx):
+    """With local_qubits = L every gate's non-insular qubits lie on physical
+    bits 0..L-1 in its stage, fused kernels touch only those bits, stages
+    follow one another in the kernel sequence, and consecutive stage maps
+    differ by exchanges of bit pairs (one permutation pass that is its own
+    inverse).  Without stages there is one stage with the identity map."""
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(10, 20))
+    L = int(rng.integers(8, n))
+    c = W.random_circuit(n, 80, rng) if seed % 2 else W.random_layered(n, 3, seed)
+    kz = [qk.QK_KERNELIZE_ORDERED, qk.QK_KERNELIZE_FULL][seed % 2]
+    ko = qk.kopts(dtype=qk.QK_C64, m_max=min(8, L), k_max=4, local_qubits=L, kernelizer=kz)
+    p = qk.kernelize(hctx, c, ko)
+    ns = p.num_stages()
+    gates, P = oracle.canonicalize(c, True)
+    virt = {g[2]: g[1] for g in gates}      # source gate -> virtual qubits
+    kinds = {g[2]: g[0] for g in gates}
+    prev = list(range(n))
+    stages = [k.stage for k in p.kernels()]
+    assert stages == sorted(stages) and (not stages or stages[-1] == ns - 1)
+    for s in range(ns):
+        sig = p.stage_map(s)
+        assert sorted(sig) == list(range(n))
+        perm = [0] * n
+        for v in range(n):
+            perm[prev[v]] = sig[v]
+        assert all(perm[perm[b]] == b for b in range(n)), "stage change is not an exchange of bit pairs"
+        prev = sig
+        for k in p.kernels():
+            if k.stage != s:
+                continue
+            for t in range(k.gate_begin, k.gate_end):
+                src = p.gate_source(t)
+                need = oracle.need_qubits(kinds[src], virt[src], True)
+                assert all(sig[v] < L for v in need), (s, src)
+                if k.type == qk.QK_KERNEL_FUSED:
+                    assert all(sig[v] < L for v in virt[src])
+    p1 = qk.kernelize(hctx, c, qk.kopts(dtype=qk.QK_C64, kernelizer=kz))
+    assert p1.num_stages() == 1 and p1.stage_map(0) == list(range(n))
+    _expect(qk.QK_EINVAL, qk.kernelize, hctx, c, qk.kopts(dtype=qk.QK_C64, m_max=8, local_qubits=6))
