@@ -12,6 +12,11 @@ analytic-cost plans are timed the same way beside them.  The complex64 state
 (32 GiB, FP32) is timed as extra keys.  State re-initialisation before each
 circuit is outside the timed events.
 
+Plans come from the full kernelizer by default: Kernelize (Algorithm alg:dp)
+fixes a gate order, and OrderedKernelize with the chosen cost model partitions
+both that order and the input order; the cheaper partition is kept
+(--kernelizer ordered restricts it to the input order).
+
 After timing, every timed plan's final state is compared with oracle
 amplitudes at 4,098 seeded indices (values stored by
 tests/golden/make_bench_samples.py); the run fails if any 1 - F exceeds the
@@ -274,6 +279,8 @@ def dominant_kernel(r, pass_bytes):
 
 
 KERNELIZERS = {"ordered": 0, "full": 1}
+KERNELIZER_TEXT = {"ordered": "OrderedKernelize",
+                   "full": "Kernelize-ordered + OrderedKernelize (best of input and Kernelize order)"}
 
 KERNEL_NAMES = {"register": "k_block_rb", "lds_sequence": "k_block_seq", "lds_dense": "k_block_dense",
                 "mfma_dense": "k_block_mfma"}
@@ -350,8 +357,9 @@ def main():
         "dtype": "complex128 (f64)",
         "data": "synthetic",
         "config": {"workload": f"qft{n}(basis seed 30) + rl{n}x20(seed 31) + ghz{n}; complex128 state "
-                               f"({(1 << n) * 16 >> 30} GiB); {model}-cost OrderedKernelize plans",
-                   "qubits": n, "cost_model": model, "state_gib": (1 << n) * 16 / 2 ** 30},
+                               f"({(1 << n) * 16 >> 30} GiB); {model}-cost {KERNELIZER_TEXT[args.kernelizer]} plans",
+                   "qubits": n, "cost_model": model, "kernelizer": args.kernelizer,
+                   "state_gib": (1 << n) * 16 / 2 ** 30},
         "hbm_gbps": round(gbps, 1),
         "per_circuit_ms": {k: round(v, 3) for k, v in per_ms.items()},
         "fidelity_1mF": None,

@@ -355,9 +355,10 @@ int simulate_batch_persistent(qk_ctx* ctx, const qk_circuit* cs, qk_state* const
         if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
             return fail(QK_EINVAL, "simulate_batch_persistent: a state appears twice");
     }
-    // Switched off: in its one device run this launch did not return within
-    // the test's time limit (as two earlier single-launch designs did), and
-    // no cause has been shown.  The host-side planning and descriptor checks
+    // Switched off: in its two device runs (before and after its per-lane
+    // scratch was cut from 8.5 KB to 80 B) this launch did not return within
+    // the test's time limit, as two earlier single-launch designs did not,
+    // and no cause has been shown.  The host-side planning and descriptor checks
     // stay available through simulate_batch_check.
     if (kPersistentBatchOff)
         return fail(QK_EUNSUPPORTED, "simulate_batch_persistent: switched off (the single-launch batch kernel did "
