@@ -94,7 +94,8 @@ def _segment(n, ktype, rng, k_max, m_max, ell, dtype=QK_C64):
         c = _kernelize_order(c, dtype)
     g = c.gates[c.gates["kind"] != W.SWAP]
     start = int(rng.integers(len(g)))
-    limit = int(rng.integers(1, 65))
+    # Kernelize's kernels run to 100+ gates (several layers on one window)
+    limit = int(rng.integers(1, 65)) if rng.random() < 0.5 else int(rng.integers(65, 161))
     low = (1 << ell) - 1
     mask = 0
     end = start

@@ -257,28 +257,6 @@ int qk_debug_set_max_groups(int groups)
     return QK_OK;
 }
 
-void qk_kopts_default(qk_kopts* ko)
-{
-    if (!ko) return;
-    std::memset(ko, 0, sizeof(*ko));
-    ko->dtype = QK_C64;
-    ko->cost_model = QK_COST_ANALYTIC;
-    ko->k_max = 5;
-    ko->m_max = 0;
-    ko->ell = 0;
-    ko->absorb_swaps = 1;
-    ko->allow_fused = 1;
-    ko->allow_lds = 1;
-    ko->block_qubits = 0;
-    ko->insular = 1;
-    ko->kernelizer = QK_KERNELIZE_ORDERED;
-    ko->dp_prune = 500;
-    ko->dp_flags = QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK;
-    ko->fuse_gates = 1;
-    ko->local_qubits = 0;
-    ko->tables = nullptr;
-}
-
 int qk_ctx_create(void* hip_stream, uint32_t flags, qk_ctx** out)
 {
     if (!out) return fail(QK_EINVAL, "qk_ctx_create: null out");

@@ -1802,6 +1802,33 @@ __global__ __launch_bounds__(kNT) void k_norm2(const C* __restrict__ psi, uint64
     block_reduce2(s + c, 0.0, partials + 2 * blockIdx.x);
 }
 
+__device__ __forceinline__ double sq_sum(const float4 v)
+{
+    const double a = v.x, b = v.y, c = v.z, d = v.w;
+    return (a * a + b * b) + (c * c + d * d);
+}
+__device__ __forceinline__ double sq_sum(const double2 v) { return v.x * v.x + v.y * v.y; }
+
+// The same sum with 16-byte loads (two complex64 amplitudes or one
+// complex128 amplitude per load) and U loads in flight per thread, in a
+// fixed order per thread; V holds nv vectors.
+template <typename V, int U>
+__global__ __launch_bounds__(kNT) void k_norm2_vec(const V* __restrict__ p, uint64_t nv, double* partials)
+{
+    double s = 0, c = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * kNT;
+    uint64_t i = (uint64_t)blockIdx.x * kNT + threadIdx.x;
+    for (; i + (U - 1) * stride < nv; i += U * stride) {
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) comp_add(s, c, sq_sum(v[u]));
+    }
+    for (; i < nv; i += stride) comp_add(s, c, sq_sum(p[i]));
+    block_reduce2(s + c, 0.0, partials + 2 * blockIdx.x);
+}
+
 template <typename C>
 __global__ __launch_bounds__(kNT) void k_overlap(const C* __restrict__ psi, uint64_t offset, uint64_t count,
                                                  const double2* __restrict__ ref, double* partials)
@@ -1984,41 +2011,6 @@ int launch_block(int dtype, int fused_k, void* psi, const BlockDesc& d, const Op
     return launch_typed<float2>(fused_k, psi, d, ops, coef, lds, s);
 }
 
-int rb_threads(int dtype, int m)
-{
-    if (dtype == QK_C64) return m == 12 ? 256 : m == 13 ? 512 : 0;
-    return m == 12 ? 256 : 0;
-}
-
-bool rb_io_friendly(int dtype, const uint8_t* reg, const uint8_t* lx)
-{
-    // complex128: block bits 0..2 are lane bits.  complex64: either register
-    // bit 0 is block bit 0 and block bits 1..3 are lane bits (16-byte pairs),
-    // or block bits 0..3 are all lane bits (8-byte amplitudes).  Lane-pinned
-    // bits sit on lane bits 4 and 5, above those groups, and must not take
-    // one of their block bits.
-    const int lo = dtype == QK_C128 ? 3 : 4;
-    for (int j = 0; j < kRbLaneBits; ++j)
-        if (lx[j] != kNoLane && lx[j] < lo) return false;
-    for (int k = 0; k < kRbBits; ++k) {
-        if (reg[k] >= lo) continue;
-        if (dtype == QK_C64 && k == 0 && reg[0] == 0) continue;
-        return false;
-    }
-    return true;
-}
-
-void rb_io_reg(int dtype, int threads, uint8_t* reg)
-{
-    const int lt = threads == 512 ? 9 : 8;
-    if (dtype == QK_C64) {
-        reg[0] = 0;
-        reg[1] = (uint8_t)(lt + 1); reg[2] = (uint8_t)(lt + 2); reg[3] = (uint8_t)(lt + 3);
-    } else {
-        reg[0] = (uint8_t)lt; reg[1] = (uint8_t)(lt + 1); reg[2] = (uint8_t)(lt + 2); reg[3] = (uint8_t)(lt + 3);
-    }
-}
-
 template <typename C, int NT>
 int launch_rb_typed(void* psi, const RbDesc& d, const void* prog, hipStream_t s)
 {
@@ -2113,10 +2105,17 @@ int reduce_partials() { return kRedBlocks; }
 
 int launch_norm2(int dtype, const void* psi, uint64_t N, double* partials, double* result, void* stream)
 {
-    const int nb = (int)std::min<uint64_t>(kRedBlocks, (N + kNT - 1) / kNT);
     hipStream_t s = (hipStream_t)stream;
-    if (dtype == QK_C128)
+    const bool a16 = ((uintptr_t)psi & 15u) == 0;
+    // 16-byte vectors when the state is 16-byte aligned (complex64: an even count)
+    const uint64_t nv = dtype == QK_C128 ? N : (a16 && N % 2 == 0 ? N / 2 : 0);
+    const int nb = (int)std::max<uint64_t>(1, std::min<uint64_t>(kRedBlocks, ((nv ? nv : N) + kNT - 1) / kNT));
+    if (dtype == QK_C128 && a16)
+        hipLaunchKernelGGL((k_norm2_vec<double2, 4>), dim3(nb), dim3(kNT), 0, s, (const double2*)psi, nv, partials);
+    else if (dtype == QK_C128)
         hipLaunchKernelGGL(k_norm2<double2>, dim3(nb), dim3(kNT), 0, s, (const double2*)psi, N, partials);
+    else if (nv)
+        hipLaunchKernelGGL((k_norm2_vec<float4, 4>), dim3(nb), dim3(kNT), 0, s, (const float4*)psi, nv, partials);
     else
         hipLaunchKernelGGL(k_norm2<float2>, dim3(nb), dim3(kNT), 0, s, (const float2*)psi, N, partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kNT), 0, s, (const double*)partials, nb, result);

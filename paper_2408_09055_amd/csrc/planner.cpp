@@ -131,6 +131,45 @@ bool ctx_lookup_tables(const qk_ctx* ctx, int n, int dtype, qk_cost_tables* out)
     return false;
 }
 
+// ------------------------------------------------------- register-kernel layout rules
+// Threads of a register-blocked workgroup for a block of 2^m amplitudes (0 when
+// the register kernel has no variant for it), and the load/store layouts that
+// move whole 128-byte lines; the device code in kernels.hip follows these.
+int rb_threads(int dtype, int m)
+{
+    if (dtype == QK_C64) return m == 12 ? 256 : m == 13 ? 512 : 0;
+    return m == 12 ? 256 : 0;
+}
+
+bool rb_io_friendly(int dtype, const uint8_t* reg, const uint8_t* lx)
+{
+    // complex128: block bits 0..2 are lane bits.  complex64: either register
+    // bit 0 is block bit 0 and block bits 1..3 are lane bits (16-byte pairs),
+    // or block bits 0..3 are all lane bits (8-byte amplitudes).  Lane-pinned
+    // bits sit on lane bits 4 and 5, above those groups, and must not take
+    // one of their block bits.
+    const int lo = dtype == QK_C128 ? 3 : 4;
+    for (int j = 0; j < kRbLaneBits; ++j)
+        if (lx[j] != kNoLane && lx[j] < lo) return false;
+    for (int k = 0; k < kRbBits; ++k) {
+        if (reg[k] >= lo) continue;
+        if (dtype == QK_C64 && k == 0 && reg[0] == 0) continue;
+        return false;
+    }
+    return true;
+}
+
+void rb_io_reg(int dtype, int threads, uint8_t* reg)
+{
+    const int lt = threads == 512 ? 9 : 8;
+    if (dtype == QK_C64) {
+        reg[0] = 0;
+        reg[1] = (uint8_t)(lt + 1); reg[2] = (uint8_t)(lt + 2); reg[3] = (uint8_t)(lt + 3);
+    } else {
+        reg[0] = (uint8_t)lt; reg[1] = (uint8_t)(lt + 1); reg[2] = (uint8_t)(lt + 2); reg[3] = (uint8_t)(lt + 3);
+    }
+}
+
 // ------------------------------------------------------------------ features
 uint64_t need_mask(const CGate& g, bool insular)
 {
@@ -1489,3 +1528,29 @@ int build_single(qk_ctx* ctx, const qk_circuit* c, const qk_kopts* ko_in, int ty
 }
 
 }  // namespace qk
+
+extern "C" {
+
+void qk_kopts_default(qk_kopts* ko)
+{
+    if (!ko) return;
+    std::memset(ko, 0, sizeof(*ko));
+    ko->dtype = QK_C64;
+    ko->cost_model = QK_COST_ANALYTIC;
+    ko->k_max = 5;
+    ko->m_max = 0;
+    ko->ell = 0;
+    ko->absorb_swaps = 1;
+    ko->allow_fused = 1;
+    ko->allow_lds = 1;
+    ko->block_qubits = 0;
+    ko->insular = 1;
+    ko->kernelizer = QK_KERNELIZE_ORDERED;
+    ko->dp_prune = 500;
+    ko->dp_flags = QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK;
+    ko->fuse_gates = 1;
+    ko->local_qubits = 0;
+    ko->tables = nullptr;
+}
+
+}  // extern "C"
