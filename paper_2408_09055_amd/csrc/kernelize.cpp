@@ -265,7 +265,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
                 if (packing) {
                     int64_t openc = 0;
                     for (uint32_t j = 0; j < S.len; ++j) openc += C.cost(arena[S.off + j]);
-                    pv = S.v - openc + C.packed_cost(&arena[S.off], S.len, &npk);
+                    pv = S.v - openc + C.packed_cost(arena.data() + S.off, S.len, &npk);
                 }
                 sc.emplace_back(pv, S.ncl + npk, s);
             }
@@ -300,7 +300,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
             narena.resize(off);
         };
         for (const DState& S : cur) {
-            const DKer* ks = &arena[S.off];
+            const DKer* ks = arena.data() + S.off;   // len may be 0 at the end of the arena
             std::vector<uint32_t> cands;
             for (uint32_t j = 0; j < S.len; ++j) {
                 const DKer& K = ks[j];
@@ -364,7 +364,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
         int64_t closed_cost = 0;
         for (int32_t c = S.closed; c >= 0; c = C.cn[c].prev) closed_cost += C.cn[c].cost;
         int64_t npk = S.len, oc = 0;
-        if (packing) oc = C.packed_cost(&arena[S.off], S.len, &npk);
+        if (packing) oc = C.packed_cost(arena.data() + S.off, S.len, &npk);
         else for (uint32_t j = 0; j < S.len; ++j) oc += C.cost(arena[S.off + j]);
         const int64_t tot = closed_cost + oc, nks = S.ncl + npk;
         if (tot < best_tot || (tot == best_tot && nks < best_n)) {
@@ -380,7 +380,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
     std::vector<std::pair<int, int32_t>> seq;   // (type, units head)
     std::vector<int64_t> costs;
     for (const CNode* c : cl) { seq.push_back({c->type, c->units}); costs.push_back(c->cost); }
-    if (packing) C.pack(&arena[B.off], B.len, pk);
+    if (packing) C.pack(arena.data() + B.off, B.len, pk);
     else pk.assign(arena.begin() + B.off, arena.begin() + B.off + B.len);
     for (const DKer& K : pk) { seq.push_back({K.type, K.units}); costs.push_back(C.cost(K)); }
     for (size_t k = 0; k < seq.size(); ++k) {

@@ -770,8 +770,8 @@ void build_rb(qk_plan* P, PKernel& K)
     K.prog_off = (int64_t)P->rbprog.size();
     P->rbprog.resize(P->rbprog.size() + bytes, 0);
     uint8_t* dst = P->rbprog.data() + K.prog_off;
-    std::memcpy(dst, ph.data(), ph.size() * sizeof(Phase));
-    std::memcpy(dst + d.ops_off, lops.data(), lops.size() * sizeof(Op));
+    if (!ph.empty()) std::memcpy(dst, ph.data(), ph.size() * sizeof(Phase));
+    if (!lops.empty()) std::memcpy(dst + d.ops_off, lops.data(), lops.size() * sizeof(Op));
     for (size_t t = 0; t < kc.size(); ++t) {
         if (P->dtype == QK_C128) {
             double v[2] = {kc[t].real(), kc[t].imag()};
@@ -791,7 +791,7 @@ void build_rb(qk_plan* P, PKernel& K)
     }
     const uint32_t nruns = (uint32_t)runs.size();
     std::memcpy(dst + d.runs_off, &nruns, 4);
-    std::memcpy(dst + d.runs_off + 4, runs.data(), 4 * runs.size());
+    if (!runs.empty()) std::memcpy(dst + d.runs_off + 4, runs.data(), 4 * runs.size());
     K.rb = true;
 }
 

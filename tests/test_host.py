@@ -349,3 +349,118 @@ def test_stage_mode_keeps_needs_local(seed, hctx):
     p1 = qk.kernelize(hctx, c, qk.kopts(dtype=qk.QK_C64, kernelizer=kz))
     assert p1.num_stages() == 1 and p1.stage_map(0) == list(range(n))
     _expect(qk.QK_EINVAL, qk.kernelize, hctx, c, qk.kopts(dtype=qk.QK_C64, m_max=8, local_qubits=6))
+
+
+# --------------------------------------------------------------- sanitizers
+_SAN_SOURCES = ("planner.cpp", "kernelize.cpp", "gates.cpp")
+
+
+@pytest.fixture(scope="module")
+def planner_san(tmp_path_factory):
+    """The planner's sources (no GPU code) built with AddressSanitizer and
+    UndefinedBehaviorSanitizer around tests/native/planner_sanitize.cpp."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ is not available")
+    out = tmp_path_factory.mktemp("san") / "planner_sanitize"
+    csrc = os.path.join(ROOT, "paper_2408_09055_amd", "csrc")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-I" + os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "native", "planner_sanitize.cpp")]
+    cmd += [os.path.join(csrc, s) for s in _SAN_SOURCES] + ["-o", str(out)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return str(out)
+
+
+def _san_circuits():
+    rng = np.random.default_rng(97)
+    circs = [W.qft(14), W.random_layered(16, 6, 3), W.ghz(13), W.random_circuit(15, 140, rng),
+             W.random_circuit(12, 60, rng)]
+    g = []
+    for r in range(4):
+        for q in range(10):
+            g.append(W.gate(W.U3, [q], list(rng.uniform(0, 6.3, 3))))
+        for q in range(r % 2, 9, 2):
+            g.append(W.gate([W.CZ, W.CX, W.CP, W.RZZ][int(rng.integers(4))], [q, q + 1],
+                            [float(rng.uniform(0, 6.3))]))
+        g.append(W.gate(W.SWAP, [int(rng.integers(5)), 5 + int(rng.integers(5))]))
+    circs.append(W.from_list(10, g, "brick10"))
+    circs.append(W.from_list(8, [], "empty8"))
+    return circs
+
+
+def _san_bad_circuits():
+    """Malformed inputs every kernelizer must reject without touching memory
+    it does not own: a qubit out of range, repeated qubits, an unknown kind,
+    a wrong arity, no qubits."""
+    bad = []
+    for field, val in (("q", [9, 0, 0]), ("q", [1, 1, 0]), ("kind", 999), ("nq", 3)):
+        g = W.from_list(4, [W.gate(W.H, [0]), W.gate(W.CX, [0, 1])]).gates.copy()
+        g[1][field] = val
+        bad.append((4, g))
+    bad.append((0, W.from_list(1, [W.gate(W.H, [0])]).gates))
+    return bad
+
+
+_SAN_OPTS = [  # dtype kernelizer insular fuse local k_max prune absorb
+    (0, 0, 1, 1, 0, 5, 500, 1), (1, 0, 0, 0, 0, 4, 500, 1), (0, 1, 1, 1, 0, 5, 500, 1),
+    (1, 1, 1, 1, 0, 6, 500, 0), (0, 2, 1, 0, 0, 5, 64, 1), (1, 2, 0, 1, 0, 3, 500, 1),
+    (0, 0, 1, 1, 13, 5, 500, 1), (1, 1, 1, 1, 12, 5, 500, 1), (0, 1, 0, 0, 13, 7, 200, 0),
+    (0, 0, 1, 1, 12, 5, 500, 1),  # invalid: local_qubits below m_max (13 for complex64)
+]
+
+
+def test_planner_under_sanitizers(planner_san, tmp_path, hctx):
+    """Every kernelizer (ordered, full, Kernelize alone), with and without the
+    insular relaxation, gate-run fusion, stages and SWAP absorption, over
+    random, layered, QFT, GHZ, brickwork and empty circuits plus malformed
+    ones: the sanitizer build exits cleanly (any heap, stack or
+    undefined-behaviour error aborts it) and returns, kernel for kernel, the
+    plans of the shipped library."""
+    import struct
+    import subprocess
+    circs = _san_circuits()
+    recs = [(c.n_qubits, np.ascontiguousarray(c.gates)) for c in circs] + _san_bad_circuits()
+    cfile, ofile = tmp_path / "circuits.bin", tmp_path / "opts.txt"
+    with open(cfile, "wb") as f:
+        for n, g in recs:
+            f.write(struct.pack("<iiq", n, 0, len(g)))
+            f.write(np.ascontiguousarray(g).tobytes())
+    ofile.write_text("\n".join(" ".join(str(x) for x in o) for o in _SAN_OPTS) + "\n")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([planner_san, str(cfile), str(ofile)], capture_output=True, text=True, timeout=900, env=env)
+    assert r.returncode == 0, r.stderr[-6000:]
+    assert "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, r.stderr[-6000:]
+    got = {}
+    cur = None
+    for line in r.stdout.splitlines():
+        t = line.split()
+        if t[0] == "plan":
+            cur = (int(t[1]), int(t[2]))
+            got[cur] = {"rc": int(t[3]), "kernels": int(t[4]), "cost": int(t[5]), "stages": int(t[6]), "ks": []}
+        else:
+            got[cur]["ks"].append(tuple(int(x) for x in t[1:]))
+    assert len(got) == len(recs) * len(_SAN_OPTS)
+    for ci, (n, g) in enumerate(recs):
+        for oi, o in enumerate(_SAN_OPTS):
+            want = got[(ci, oi)]
+            ko = qk.kopts(dtype=o[0], kernelizer=o[1], insular=o[2], fuse_gates=o[3], local_qubits=o[4],
+                          k_max=o[5], dp_prune=o[6], absorb_swaps=o[7])
+            if ci >= len(circs):
+                assert want["rc"] != 0, (ci, oi)
+                continue
+            try:
+                plan = qk.kernelize(hctx, circs[ci], ko)
+            except qk.QkError as e:
+                assert want["rc"] == e.code != 0, (circs[ci].name, o, str(e))
+                continue
+            ks = [(k.type, k.gate_begin, k.gate_end, k.qubit_mask, k.n_ops, k.stage,
+                   1 if k.impl == qk.QK_IMPL_REGISTER else 0) for k in plan.kernels()]
+            assert want["rc"] == 0, (circs[ci].name, o)
+            assert (want["kernels"], want["cost"], want["stages"]) == (len(ks), plan.total_cost(),
+                                                                        plan.num_stages()), (circs[ci].name, o)
+            assert want["ks"] == ks, (circs[ci].name, o)
