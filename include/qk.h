@@ -199,7 +199,12 @@ typedef struct qk_kopts {
     int32_t allow_fused;
     int32_t allow_lds;
     int32_t block_qubits;  /* amplitudes per staged block = 2^block_qubits
-                              (>= m_max and >= k_max; 0 = m_max) */
+                              (>= m_max and >= k_max; 0 = m_max).  Nonzero
+                              also keeps fused kernels of 5..7 qubits on the
+                              staged-block kernels; 0 lets them run on the
+                              direct matrix-core kernel, which needs no
+                              staging (at least 2^(k+4) amplitudes; complex128
+                              up to 6 qubits) */
     int32_t insular;       /* 1: LDS kernels need only the non-insular qubits of
                               their gates in the active set (appendix, "Insular
                               qubits" optimisation; Definition def:insular_qubit):

@@ -203,6 +203,8 @@ int launch_plan_kernel(const qk_plan* p, int64_t i, qk_state* st, void* stream)
     int e;
     if (K.rb) {
         e = launch_block_rb(p->dtype, st->psi, K.rbd, (const uint8_t*)p->d_rbprog + K.prog_off, stream);
+    } else if (K.direct) {
+        e = launch_fused_direct(p->dtype, st->psi, K.fd, p->d_coef, stream);
     } else {
         const int fused_k = K.type == QK_KERNEL_FUSED ? K.k : 0;
         e = launch_block(p->dtype, fused_k, st->psi, K.desc, (const Op*)p->d_ops + K.op_off, p->d_coef, stream);
@@ -661,6 +663,7 @@ int plan_kernel_info(const qk_plan* p, int64_t i, qk_kernel_info* out)
     out->block_qubits = K.desc.m;
     out->n_ops = K.n_ops;
     if (K.rb) out->impl = QK_IMPL_REGISTER;
+    else if (K.direct) out->impl = QK_IMPL_MFMA_DENSE;
     else if (K.type == QK_KERNEL_LDS) out->impl = QK_IMPL_LDS_SEQUENCE;
     else out->impl = K.k >= 5 && mfma_ok(K.k, K.desc.m) ? QK_IMPL_MFMA_DENSE : QK_IMPL_LDS_DENSE;
     out->n_phases = K.rb ? K.rbd.n_phases : 0;

@@ -106,8 +106,10 @@ int time_launch(qk_ctx* ctx, const qk_plan* P, int64_t i, qk_state* st, int reps
     int rc = QK_OK;
     for (int r = 0; r <= reps; ++r) {
         (void)hipEventRecord(e0, s);
-        int e = K.rb ? launch_block_rb(P->dtype, st->psi, rd, (const uint8_t*)P->d_rbprog + K.prog_off, s)
-                     : launch_block(P->dtype, fused_k, st->psi, d, (const Op*)P->d_ops + K.op_off, P->d_coef, s);
+        int e = K.rb       ? launch_block_rb(P->dtype, st->psi, rd, (const uint8_t*)P->d_rbprog + K.prog_off, s)
+                : K.direct && n_ops_override < 0 ? launch_fused_direct(P->dtype, st->psi, K.fd, P->d_coef, s)
+                                                 : launch_block(P->dtype, fused_k, st->psi, d, (const Op*)P->d_ops + K.op_off,
+                                                                P->d_coef, s);
         (void)hipEventRecord(e1, s);
         if (e) { rc = hip_fail(e, "time_kernel launch"); break; }
         hipError_t he = hipEventSynchronize(e1);

@@ -1354,6 +1354,155 @@ __device__ __forceinline__ uint64_t chunk_offset(int I, const uint64_t* rb)
 // Occupancy target: two workgroups of 512 (complex64) or 256 (complex128)
 // threads per compute unit, i.e. 4 or 2 waves per SIMD.
 
+// ----------------------------------------------------------- direct matrix-core fused kernel
+// Y = U X on the state viewed as X[r][c] (rows: the K kernel qubits; columns:
+// the other qubits), computed as the real product of the expansion
+// A = [[Ur, -Ui], [Ui, Ur]] with [Xr; Xi] on 16x16x4 matrix-core tiles, with
+// no staging of the state in LDS.  A wave takes a group of 16 columns: lane l
+// holds column l % 16 and the complex rows 4 j + l / 16 (j < D / 4), i.e.
+// exactly the B operand of k-step j (real parts) and of k-step D / 4 + j
+// (imaginary parts).  It accumulates all 2D / 16 output tiles, and the
+// accumulators are stored straight back: with the row order of the fragment
+// table, register v of lane l in output tile a (and its imaginary partner
+// tile a + D / 8) is complex row 16 a + 4 v + l / 16 of column l % 16.  Loads
+// and stores of one instruction thus cover the four lowest other qubits and
+// the two lowest kernel qubits.  Waves walk the groups with a stride of the
+// grid's wave count; with PF the next group is loaded while the current one
+// is multiplied.  The fragments of A come from registers (loaded once), LDS
+// (copied once per workgroup) or the global table (read at each step), by
+// size.
+constexpr int kFragReg = 0, kFragLds = 1, kFragGlobal = 2;
+
+template <typename C, int K, int ASRC, bool PF>
+__global__ __launch_bounds__(kNT) void k_fused_direct(C* __restrict__ psi, FusedDesc f, const C* __restrict__ coef)
+{
+    using R = typename Real<C>::T;
+    using V = CxOf<C>;
+    using Acc = typename MfmaAcc<R>::T;
+    using Raw = typename std::conditional<sizeof(C) == 8, u32x2, u32x4>::type;
+    constexpr int D = 1 << K, TM = D / 8, S = D / 2, J = D / 4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const R* __restrict__ fr = reinterpret_cast<const R*>(coef + f.frag);
+    R* sA = reinterpret_cast<R*>(smem);
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    if constexpr (ASRC == kFragLds) {
+        for (int e = threadIdx.x; e < TM * S * 64; e += kNT) sA[e] = fr[e];
+        __syncthreads();
+    }
+    R areg[ASRC == kFragReg ? TM * S : 1];
+    if constexpr (ASRC == kFragReg)
+        static_for<0, TM * S>([&](auto E) QK_AI { areg[E.value] = fr[E.value * 64 + lane]; });
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint64_t g = (uint64_t)blockIdx.x * (kNT / 64) + wave;
+    const uint64_t gstride = (uint64_t)gridDim.x * (kNT / 64);
+    if (g >= f.ngroups) return;   // no barrier follows
+    // this lane's offset: its column (four lowest other qubits) and its row
+    // within a quad of rows (the two lowest kernel qubits)
+    uint64_t loff = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if ((lr >> t) & 1) loff |= 1ull << f.lo[t];
+    if (lk & 1) loff |= 1ull << f.q[0];
+    if (lk & 2) loff |= 1ull << f.q[1];
+    // offset of row quad j: bits of j on kernel qubits q[2..]
+    auto rowhi = [&](int j) QK_AI {
+        uint64_t o = 0;
+#pragma unroll
+        for (int t = 0; t + 2 < K; ++t)
+            if ((j >> t) & 1) o |= 1ull << f.q[t + 2];
+        return o;
+    };
+    auto gbase = [&](uint64_t gi) {
+        uint64_t o = 0;
+        for (int r = 0; r < f.nruns; ++r)
+            o |= ((gi >> f.run_src[r]) & ((1ull << f.run_len[r]) - 1)) << f.run_dst[r];
+        return o;
+    };
+    auto load = [&](V (&x)[J], uint64_t gb) QK_AI {
+        const uint64_t b = gb + loff;
+        static_for<0, J>([&](auto Jc) QK_AI {
+            const Raw w = __builtin_nontemporal_load(reinterpret_cast<const Raw*>(&psi[b + rowhi(Jc.value)]));
+            if constexpr (sizeof(C) == 8) x[Jc.value] = V{__uint_as_float(w.x), __uint_as_float(w.y)};
+            else
+                x[Jc.value] = V{__builtin_bit_cast(R, (uint64_t)w.x | ((uint64_t)w.y << 32)),
+                                __builtin_bit_cast(R, (uint64_t)w.z | ((uint64_t)w.w << 32))};
+        });
+    };
+    // the table pointer is re-materialised for every group (the empty asm),
+    // so that the loop-invariant fragment loads are not hoisted out of the
+    // group loop, where they would need a register each
+    const R* frg = fr;
+    auto afr = [&](int e) QK_AI -> R {
+        if constexpr (ASRC == kFragLds) return sA[e * 64 + lane];
+        else return frg[e * 64 + lane];
+    };
+    V x[J];
+    uint64_t gb = gbase(g);
+    load(x, gb);
+    for (;;) {
+        const uint64_t gn = g + gstride;
+        const bool more = gn < f.ngroups;
+        const uint64_t gbn = more ? gbase(gn) : 0;
+        V xn[PF ? J : 1];
+        if constexpr (PF)
+            if (more) load(xn, gbn);
+        Acc acc[TM];
+        static_for<0, TM>([&](auto A) QK_AI { acc[A.value] = Acc{0, 0, 0, 0}; });
+        if constexpr (ASRC == kFragGlobal) {
+            frg = fr;
+            asm volatile("" : "+s"(frg));
+        }
+        if constexpr (ASRC == kFragReg) {
+            static_for<0, J>([&](auto Jc) QK_AI {
+                static_for<0, TM>([&](auto A) QK_AI {
+                    acc[A.value] = mfma16(areg[A.value * S + Jc.value], x[Jc.value].x, acc[A.value]);
+                    acc[A.value] = mfma16(areg[A.value * S + J + Jc.value], x[Jc.value].y, acc[A.value]);
+                });
+            });
+        } else {
+            // the fragments of step j + 1 are read while step j multiplies; a
+            // scheduling fence per step keeps the reads from all being
+            // hoisted (which would take a register per fragment)
+            R fa[2][2 * TM];
+            auto fetch = [&](R (&dst)[2 * TM], int j) QK_AI {
+                static_for<0, TM>([&](auto A) QK_AI {
+                    dst[2 * A.value] = afr(A.value * S + j);
+                    dst[2 * A.value + 1] = afr(A.value * S + J + j);
+                });
+            };
+            fetch(fa[0], 0);
+            static_for<0, J>([&](auto Jc) QK_AI {
+                constexpr int cur = Jc.value & 1;
+                if constexpr (Jc.value + 1 < J) fetch(fa[cur ^ 1], Jc.value + 1);
+                static_for<0, TM>([&](auto A) QK_AI {
+                    acc[A.value] = mfma16(fa[cur][2 * A.value], x[Jc.value].x, acc[A.value]);
+                    acc[A.value] = mfma16(fa[cur][2 * A.value + 1], x[Jc.value].y, acc[A.value]);
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        }
+        const uint64_t b = gb + loff;
+        static_for<0, TM / 2>([&](auto A) QK_AI {
+            static_for<0, 4>([&](auto Vv) QK_AI {
+                const R re = acc[A.value][Vv.value], im = acc[A.value + TM / 2][Vv.value];
+                Raw w;
+                if constexpr (sizeof(C) == 8) {
+                    w = Raw{__float_as_uint(re), __float_as_uint(im)};
+                } else {
+                    const uint64_t a = __builtin_bit_cast(uint64_t, re), c = __builtin_bit_cast(uint64_t, im);
+                    w = Raw{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)c, (uint32_t)(c >> 32)};
+                }
+                __builtin_nontemporal_store(w, reinterpret_cast<Raw*>(&psi[b + rowhi(4 * A.value + Vv.value)]));
+            });
+        });
+        if (!more) break;
+        if constexpr (PF) static_for<0, J>([&](auto Jc) QK_AI { x[Jc.value] = xn[Jc.value]; });
+        else load(x, gbn);
+        g = gn;
+        gb = gbn;
+    }
+}
+
 template <typename C, int NT, bool FUSED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(C) == 8 ? 4 : 2)))
 void k_block_rb(C* __restrict__ psi, RbDesc d, const uint8_t* __restrict__ gprog)
@@ -1979,6 +2128,47 @@ int launch_mfma(C* p, const BlockDesc& d, const Op* ops, const void* coef, size_
     } else {
         return launch_one<C>(k_block_mfma<C, K, false>, p, d, ops, coef, lds, s);
     }
+}
+
+template <typename C, int K, int ASRC, bool PF>
+int launch_fd(C* p, const FusedDesc& f, const C* coef, hipStream_t s)
+{
+    using R = typename Real<C>::T;
+    constexpr int D = 1 << K;
+    const size_t lds = ASRC == kFragLds ? (size_t)(D / 8) * (D / 2) * 64 * sizeof(R) : 0;
+    auto kern = k_fused_direct<C, K, ASRC, PF>;
+    const uint64_t res = resident_groups(reinterpret_cast<const void*>(kern), lds, kNT);
+    const uint64_t need = (f.ngroups + kNT / 64 - 1) / (kNT / 64);
+    hipLaunchKernelGGL(kern, dim3(persistent_grid(need, res)), dim3(kNT), lds, s, p, f, coef);
+    return (int)hipGetLastError();
+}
+
+// Where the fragments of A live: registers while they fit (complex64 at 5
+// qubits: 64 words per lane), LDS up to 64 KiB per workgroup, else the global
+// table (L2-resident, read at every step).
+int launch_fused_direct(int dtype, void* psi, const FusedDesc& f, const void* coef, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (f.n < f.k + 4 || f.ngroups != (1ull << (f.n - f.k - 4))) return (int)hipErrorInvalidValue;
+    if (dtype == QK_C64) {
+        float2* p = (float2*)psi;
+        const float2* c = (const float2*)coef;
+        switch (f.k) {
+        case 5: return launch_fd<float2, 5, kFragReg, true>(p, f, c, s);
+        case 6: return launch_fd<float2, 6, kFragLds, true>(p, f, c, s);
+        case 7: return launch_fd<float2, 7, kFragGlobal, false>(p, f, c, s);
+        default: break;
+        }
+    } else {
+        double2* p = (double2*)psi;
+        const double2* c = (const double2*)coef;
+        switch (f.k) {
+        case 5: return launch_fd<double2, 5, kFragLds, true>(p, f, c, s);
+        case 6: return launch_fd<double2, 6, kFragGlobal, false>(p, f, c, s);
+        default: break;
+        }
+    }
+    return (int)hipErrorInvalidValue;
 }
 
 template <typename C>

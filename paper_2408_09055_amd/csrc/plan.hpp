@@ -28,6 +28,8 @@ struct PKernel {
     RbDesc rbd;        // its launch descriptor
     int64_t prog_off;  // its program in the plan's register-kernel blob
     int stage = 0;     // stage index (stage mode), 0 otherwise
+    bool direct = false;   // fused kernel on the direct matrix-core path
+    FusedDesc fd{};        // its launch descriptor
 };
 
 // Feature vector of a candidate kernel for the learned cost model.
@@ -64,6 +66,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
 
 // Analytic tables used when a context has none for (n, dtype).
 qk_cost_tables default_tables(int n, int dtype);
+bool fused_direct_ok(int dtype, int k, int n);
 bool ctx_lookup_tables(const qk_ctx* ctx, int n, int dtype, qk_cost_tables* out);
 
 }  // namespace qk

@@ -170,6 +170,70 @@ void rb_io_reg(int dtype, int threads, uint8_t* reg)
     }
 }
 
+// Fused kernels of 5..7 qubits run on the direct matrix-core path (one
+// matrix-core tile column per group of 16 state columns) when the state has
+// at least 16 columns; complex128 at 7 qubits stays on the staged-block
+// kernel (its accumulators and operands exceed the register file).
+bool fused_direct_ok(int dtype, int k, int n)
+{
+    if (k < 5 || k > 7 || n - k < 4) return false;
+    return !(dtype == QK_C128 && k == 7);
+}
+
+namespace {
+
+// The real expansion A = [[Ur, -Ui], [Ui, Ur]] of the D x D matrix U in the
+// order the matrix-core kernel reads it: fragment (a, s) of lane l is
+// A[16 a + rho(l % 16)][4 s + l / 16], stored at ((a * S + s) * 64 + l), for
+// the 2D / 16 row tiles a and the 2D / 4 k-steps s.  rho reorders the rows of
+// each 16-row tile so that the accumulator register v of lane l holds the
+// complex row 4 v + l / 16 (FP32 accumulators hold tile row 4 (l / 16) + v,
+// FP64 ones row l / 16 + 4 v, which needs no reordering).  Two reals per
+// complex entry, appended to the coefficient table (FP64, rounded once with
+// the rest of the table).
+void append_fragments(int dtype, int k, const std::vector<cd>& U, std::vector<cd>& coefs)
+{
+    const int D = 1 << k, TM = D / 8, S = D / 2;
+    std::vector<double> fr((size_t)TM * S * 64);
+    for (int a = 0; a < TM; ++a)
+        for (int s = 0; s < S; ++s)
+            for (int l = 0; l < 64; ++l) {
+                const int lr = l & 15, lk = l >> 4;
+                const int rho = dtype == QK_C64 ? 4 * (lr & 3) + (lr >> 2) : lr;
+                const int r = 16 * a + rho, c = 4 * s + lk;
+                const cd u = U[(size_t)(r & (D - 1)) * D + (c & (D - 1))];
+                const bool rre = r < D, cre = c < D;
+                fr[((size_t)a * S + s) * 64 + l] = rre == cre ? u.real() : (rre ? -u.imag() : u.imag());
+            }
+    for (size_t e = 0; e < fr.size(); e += 2) coefs.push_back(cd(fr[e], fr[e + 1]));
+}
+
+// Columns of a direct fused launch: the other qubits ascending, the lowest
+// four on lanes, the rest filled from the group index in runs.
+void fill_fused_desc(FusedDesc& f, int n, uint64_t mask, const int* kq, int nk)
+{
+    f = FusedDesc{};
+    f.n = n;
+    f.k = nk;
+    for (int u = 0; u < nk; ++u) f.q[u] = (uint8_t)kq[u];
+    int other[64], no = 0;
+    for (int q = 0; q < n; ++q)
+        if (!((mask >> q) & 1)) other[no++] = q;
+    for (int t = 0; t < 4; ++t) f.lo[t] = (uint8_t)other[t];
+    for (int t = 4; t < no;) {
+        int e = t + 1;
+        while (e < no && other[e] == other[e - 1] + 1) ++e;
+        f.run_src[f.nruns] = (uint8_t)(t - 4);
+        f.run_len[f.nruns] = (uint8_t)(e - t);
+        f.run_dst[f.nruns] = (uint8_t)other[t];
+        ++f.nruns;
+        t = e;
+    }
+    f.ngroups = 1ull << (n - nk - 4);
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ features
 uint64_t need_mask(const CGate& g, bool insular)
 {
@@ -1088,6 +1152,13 @@ int emit_kernel(qk_plan* P, int64_t j, int64_t i, int type, int64_t cost, int m_
         op.coef = (uint32_t)P->coefs.size();
         P->coefs.insert(P->coefs.end(), U.begin(), U.end());
         P->ops.push_back(op);
+        // an explicit block size keeps the kernel on the staged-block path
+        if (P->ko.block_qubits == 0 && fused_direct_ok(P->dtype, nk, n)) {
+            K.direct = true;
+            fill_fused_desc(K.fd, n, mask, kq, nk);
+            K.fd.frag = (uint32_t)P->coefs.size();
+            append_fragments(P->dtype, nk, U, P->coefs);
+        }
     } else {
         for (int64_t t = j; t < i; ++t) {
             const CGate& g = G[t];

@@ -84,6 +84,26 @@ struct BlockDesc {
     uint8_t act[16];    // block bit j -> physical qubit, ascending
 };
 
+// Descriptor of a direct matrix-core fused launch: the state is viewed as
+// the complex matrix X[r][c] with rows over the kernel qubits q[0..k-1]
+// (ascending, row bit u <-> q[u]) and columns over the other qubits
+// (ascending).  A wave takes groups of 16 columns, the four lowest other
+// qubits lo[] on its lanes; the group index fills the remaining other qubits
+// through `nruns` runs (group bits run_src.. -> qubits run_dst.., run_len
+// long).  frag is the offset, in complex entries of the plan's coefficient
+// table, of the real expansion of U in matrix-core fragment order (two reals
+// per complex entry).
+struct FusedDesc {
+    uint64_t ngroups;   // 2^(n - k - 4)
+    int32_t n, k;
+    uint32_t frag;
+    int32_t nruns;
+    uint8_t q[8];
+    uint8_t lo[4];
+    uint8_t run_src[8], run_len[8], run_dst[8];
+};
+int launch_fused_direct(int dtype, void* psi, const FusedDesc& f, const void* coef, void* stream);
+
 // Descriptor of one out-of-place permutation launch.
 struct PermDesc {
     uint64_t nblocks;   // 2^(n - m)

@@ -92,6 +92,9 @@ def _cases(dtype, n):
         for m in sorted({12, m_hi}):
             cases.append((f"mfma k={K} m={m}", dict(allow_lds=0, k_max=K, m_max=m, block_qubits=m, tables=FLAT),
                           [MFMA], K))
+        # no block size: the direct matrix-core kernel (complex128 at 7
+        # qubits stays on the staged one)
+        cases.append((f"direct mfma k={K}", dict(allow_lds=0, k_max=K, tables=FLAT), [MFMA], K))
         # a block too small for the matrix-core tiling: the VALU dense product
         cases.append((f"staged dense k={K} (m={K + 3})", dict(allow_lds=0, k_max=K, m_max=K + 3,
                                                               block_qubits=K + 3, tables=FLAT), [DENSE], K))
