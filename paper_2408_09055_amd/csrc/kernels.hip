@@ -1373,13 +1373,85 @@ __device__ __forceinline__ uint64_t chunk_offset(int I, const uint64_t* rb)
 // size.
 constexpr int kFragReg = 0, kFragLds = 1, kFragGlobal = 2;
 
+// Addressing of a direct fused launch.  Lane offset: its column (the four
+// lowest other qubits) and its row within a quad of rows (the two lowest
+// kernel qubits).  Row quad j: the bits of j on kernel qubits q[2..].  Group
+// base: the group index deposited on the remaining other qubits.
+__device__ __forceinline__ uint64_t fd_lane_off(const FusedDesc& f, int lr, int lk)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if ((lr >> t) & 1) o |= 1ull << f.lo[t];
+    if (lk & 1) o |= 1ull << f.q[0];
+    if (lk & 2) o |= 1ull << f.q[1];
+    return o;
+}
+
+template <int K>
+__device__ __forceinline__ uint64_t fd_rowhi(const FusedDesc& f, int j)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int t = 0; t + 2 < K; ++t)
+        if ((j >> t) & 1) o |= 1ull << f.q[t + 2];
+    return o;
+}
+
+__device__ __forceinline__ uint64_t fd_gbase(const FusedDesc& f, uint64_t g)
+{
+    uint64_t o = 0;
+    for (int r = 0; r < f.nruns; ++r) o |= ((g >> f.run_src[r]) & ((1ull << f.run_len[r]) - 1)) << f.run_dst[r];
+    return o;
+}
+
+// The lane's 2^K / 4 amplitudes of a group (b: group base + lane offset).
+template <typename C, int K>
+__device__ __forceinline__ void fd_load(const C* __restrict__ psi, const FusedDesc& f, uint64_t b,
+                                        CxOf<C> (&x)[(1 << K) / 4])
+{
+    using R = typename Real<C>::T;
+    using V = CxOf<C>;
+    using Raw = typename std::conditional<sizeof(C) == 8, u32x2, u32x4>::type;
+    static_for<0, (1 << K) / 4>([&](auto Jc) QK_AI {
+        const Raw w = __builtin_nontemporal_load(reinterpret_cast<const Raw*>(&psi[b + fd_rowhi<K>(f, Jc.value)]));
+        if constexpr (sizeof(C) == 8) x[Jc.value] = V{__uint_as_float(w.x), __uint_as_float(w.y)};
+        else
+            x[Jc.value] = V{__builtin_bit_cast(R, (uint64_t)w.x | ((uint64_t)w.y << 32)),
+                            __builtin_bit_cast(R, (uint64_t)w.z | ((uint64_t)w.w << 32))};
+    });
+}
+
+// Accumulator register v of output tile a (real part) and tile a + D / 8
+// (imaginary part) -> complex row 16 a + 4 v + l / 16 of the lane's column.
+template <typename C, int K, typename Acc>
+__device__ __forceinline__ void fd_store(C* __restrict__ psi, const FusedDesc& f, uint64_t b,
+                                         const Acc (&acc)[(1 << K) / 8])
+{
+    using R = typename Real<C>::T;
+    using Raw = typename std::conditional<sizeof(C) == 8, u32x2, u32x4>::type;
+    constexpr int TM = (1 << K) / 8;
+    static_for<0, TM / 2>([&](auto A) QK_AI {
+        static_for<0, 4>([&](auto Vv) QK_AI {
+            const R re = acc[A.value][Vv.value], im = acc[A.value + TM / 2][Vv.value];
+            Raw w;
+            if constexpr (sizeof(C) == 8) {
+                w = Raw{__float_as_uint(re), __float_as_uint(im)};
+            } else {
+                const uint64_t a = __builtin_bit_cast(uint64_t, re), c = __builtin_bit_cast(uint64_t, im);
+                w = Raw{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)c, (uint32_t)(c >> 32)};
+            }
+            __builtin_nontemporal_store(w, reinterpret_cast<Raw*>(&psi[b + fd_rowhi<K>(f, 4 * A.value + Vv.value)]));
+        });
+    });
+}
+
 template <typename C, int K, int ASRC, bool PF>
 __global__ __launch_bounds__(kNT) void k_fused_direct(C* __restrict__ psi, FusedDesc f, const C* __restrict__ coef)
 {
     using R = typename Real<C>::T;
     using V = CxOf<C>;
     using Acc = typename MfmaAcc<R>::T;
-    using Raw = typename std::conditional<sizeof(C) == 8, u32x2, u32x4>::type;
     constexpr int D = 1 << K, TM = D / 8, S = D / 2, J = D / 4;
     extern __shared__ __align__(16) unsigned char smem[];
     const R* __restrict__ fr = reinterpret_cast<const R*>(coef + f.frag);
@@ -1396,38 +1468,7 @@ __global__ __launch_bounds__(kNT) void k_fused_direct(C* __restrict__ psi, Fused
     uint64_t g = (uint64_t)blockIdx.x * (kNT / 64) + wave;
     const uint64_t gstride = (uint64_t)gridDim.x * (kNT / 64);
     if (g >= f.ngroups) return;   // no barrier follows
-    // this lane's offset: its column (four lowest other qubits) and its row
-    // within a quad of rows (the two lowest kernel qubits)
-    uint64_t loff = 0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-        if ((lr >> t) & 1) loff |= 1ull << f.lo[t];
-    if (lk & 1) loff |= 1ull << f.q[0];
-    if (lk & 2) loff |= 1ull << f.q[1];
-    // offset of row quad j: bits of j on kernel qubits q[2..]
-    auto rowhi = [&](int j) QK_AI {
-        uint64_t o = 0;
-#pragma unroll
-        for (int t = 0; t + 2 < K; ++t)
-            if ((j >> t) & 1) o |= 1ull << f.q[t + 2];
-        return o;
-    };
-    auto gbase = [&](uint64_t gi) {
-        uint64_t o = 0;
-        for (int r = 0; r < f.nruns; ++r)
-            o |= ((gi >> f.run_src[r]) & ((1ull << f.run_len[r]) - 1)) << f.run_dst[r];
-        return o;
-    };
-    auto load = [&](V (&x)[J], uint64_t gb) QK_AI {
-        const uint64_t b = gb + loff;
-        static_for<0, J>([&](auto Jc) QK_AI {
-            const Raw w = __builtin_nontemporal_load(reinterpret_cast<const Raw*>(&psi[b + rowhi(Jc.value)]));
-            if constexpr (sizeof(C) == 8) x[Jc.value] = V{__uint_as_float(w.x), __uint_as_float(w.y)};
-            else
-                x[Jc.value] = V{__builtin_bit_cast(R, (uint64_t)w.x | ((uint64_t)w.y << 32)),
-                                __builtin_bit_cast(R, (uint64_t)w.z | ((uint64_t)w.w << 32))};
-        });
-    };
+    const uint64_t loff = fd_lane_off(f, lr, lk);
     // the table pointer is re-materialised for every group (the empty asm),
     // so that the loop-invariant fragment loads are not hoisted out of the
     // group loop, where they would need a register each
@@ -1437,15 +1478,15 @@ __global__ __launch_bounds__(kNT) void k_fused_direct(C* __restrict__ psi, Fused
         else return frg[e * 64 + lane];
     };
     V x[J];
-    uint64_t gb = gbase(g);
-    load(x, gb);
+    uint64_t gb = fd_gbase(f, g);
+    fd_load<C, K>(psi, f, gb + loff, x);
     for (;;) {
         const uint64_t gn = g + gstride;
         const bool more = gn < f.ngroups;
-        const uint64_t gbn = more ? gbase(gn) : 0;
+        const uint64_t gbn = more ? fd_gbase(f, gn) : 0;
         V xn[PF ? J : 1];
         if constexpr (PF)
-            if (more) load(xn, gbn);
+            if (more) fd_load<C, K>(psi, f, gbn + loff, xn);
         Acc acc[TM];
         static_for<0, TM>([&](auto A) QK_AI { acc[A.value] = Acc{0, 0, 0, 0}; });
         if constexpr (ASRC == kFragGlobal) {
@@ -1481,25 +1522,93 @@ __global__ __launch_bounds__(kNT) void k_fused_direct(C* __restrict__ psi, Fused
                 __builtin_amdgcn_sched_barrier(0);
             });
         }
-        const uint64_t b = gb + loff;
-        static_for<0, TM / 2>([&](auto A) QK_AI {
-            static_for<0, 4>([&](auto Vv) QK_AI {
-                const R re = acc[A.value][Vv.value], im = acc[A.value + TM / 2][Vv.value];
-                Raw w;
-                if constexpr (sizeof(C) == 8) {
-                    w = Raw{__float_as_uint(re), __float_as_uint(im)};
-                } else {
-                    const uint64_t a = __builtin_bit_cast(uint64_t, re), c = __builtin_bit_cast(uint64_t, im);
-                    w = Raw{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)c, (uint32_t)(c >> 32)};
-                }
-                __builtin_nontemporal_store(w, reinterpret_cast<Raw*>(&psi[b + rowhi(4 * A.value + Vv.value)]));
-            });
-        });
+        fd_store<C, K>(psi, f, gb + loff, acc);
         if (!more) break;
         if constexpr (PF) static_for<0, J>([&](auto Jc) QK_AI { x[Jc.value] = xn[Jc.value]; });
-        else load(x, gbn);
+        else fd_load<C, K>(psi, f, gbn + loff, x);
         g = gn;
         gb = gbn;
+    }
+}
+
+// The same product for tables too large for LDS: the four waves of a
+// workgroup each take a group of 16 columns, and the workgroup copies the
+// fragment table chunk by chunk (SC k-steps of every output tile, 32 KiB)
+// into two alternating LDS buffers, the next chunk's loads in flight while
+// the current one multiplies.  Each chunk read from L2 thus serves four
+// groups.  The group loop is uniform over the workgroup (every wave reaches
+// every barrier); a wave without a group skips only its loads, products and
+// stores.
+template <typename C, int K, int SC>
+__global__ __launch_bounds__(kNT) void k_fused_chunked(C* __restrict__ psi, FusedDesc f, const C* __restrict__ coef)
+{
+    using R = typename Real<C>::T;
+    using V = CxOf<C>;
+    using Acc = typename MfmaAcc<R>::T;
+    constexpr int D = 1 << K, TM = D / 8, S = D / 2, J = D / 4, NCH = S / SC;
+    constexpr int CHR = TM * SC * 64;                       // reals per chunk
+    constexpr int PER = (int)(CHR * sizeof(R) / 16) / kNT;  // 16-byte pieces per thread and chunk
+    static_assert(S % SC == 0 && (CHR * sizeof(R) / 16) % kNT == 0, "chunking");
+    extern __shared__ __align__(16) unsigned char smem[];
+    R* sbuf = reinterpret_cast<R*>(smem);                   // two chunks
+    const R* __restrict__ fr = reinterpret_cast<const R*>(coef + f.frag);
+    const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint64_t loff = fd_lane_off(f, lr, lk);
+    // piece i of chunk c: reals e0 .. e0 + 16 / sizeof(R) of the chunk, which
+    // come from row tile a = e0 / (SC * 64) of the table
+    constexpr int RPP = 16 / (int)sizeof(R);
+    // re-materialised per group (empty asm): the table loads must not be
+    // hoisted out of the group loop
+    const R* frg = fr;
+    auto piece_src = [&](int c, int i) QK_AI {
+        const int e0 = (tid + i * kNT) * RPP;
+        const int a = e0 / (SC * 64), w = e0 % (SC * 64);
+        return reinterpret_cast<const u32x4*>(frg + ((size_t)a * S + (size_t)c * SC) * 64 + w);
+    };
+    for (uint64_t q = blockIdx.x; q * (kNT / 64) < f.ngroups; q += gridDim.x) {
+        frg = fr;
+        asm volatile("" : "+s"(frg));
+        const uint64_t g = q * (kNT / 64) + wave;
+        const bool active = g < f.ngroups;
+        const uint64_t b = active ? fd_gbase(f, g) + loff : 0;
+        V x[J];
+        if (active) fd_load<C, K>(psi, f, b, x);
+        Acc acc[TM];
+        static_for<0, TM>([&](auto A) QK_AI { acc[A.value] = Acc{0, 0, 0, 0}; });
+        u32x4 stg[PER];
+        static_for<0, PER>([&](auto I) QK_AI { stg[I.value] = *piece_src(0, I.value); });
+        __syncthreads();   // the previous group's readers of buffer 0 are done
+        static_for<0, PER>([&](auto I) QK_AI {
+            reinterpret_cast<u32x4*>(sbuf)[tid + I.value * kNT] = stg[I.value];
+        });
+        __syncthreads();
+        static_for<0, NCH>([&](auto Cc) QK_AI {
+            constexpr int c = Cc.value;
+            if constexpr (c + 1 < NCH)
+                static_for<0, PER>([&](auto I) QK_AI { stg[I.value] = *piece_src(c + 1, I.value); });
+            const R* buf = sbuf + (c & 1) * CHR;
+            if (active) {
+                static_for<0, SC>([&](auto T) QK_AI {
+                    constexpr int st = c * SC + T.value;
+                    static_for<0, TM>([&](auto A) QK_AI {
+                        const R a = buf[(A.value * SC + T.value) * 64 + lane];
+                        if constexpr (st < J) acc[A.value] = mfma16(a, x[st].x, acc[A.value]);
+                        else acc[A.value] = mfma16(a, x[st - J].y, acc[A.value]);
+                    });
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            }
+            if constexpr (c + 1 < NCH) {
+                // the other buffer's last readers (chunk c - 1) passed the
+                // barrier that ended chunk c - 1
+                static_for<0, PER>([&](auto I) QK_AI {
+                    reinterpret_cast<u32x4*>(sbuf + ((c + 1) & 1) * CHR)[tid + I.value * kNT] = stg[I.value];
+                });
+                __syncthreads();
+            }
+        });
+        if (active) fd_store<C, K>(psi, f, b, acc);
     }
 }
 
@@ -2143,9 +2252,22 @@ int launch_fd(C* p, const FusedDesc& f, const C* coef, hipStream_t s)
     return (int)hipGetLastError();
 }
 
+template <typename C, int K, int SC>
+int launch_fc(C* p, const FusedDesc& f, const C* coef, hipStream_t s)
+{
+    using R = typename Real<C>::T;
+    constexpr int D = 1 << K;
+    const size_t lds = 2 * (size_t)(D / 8) * SC * 64 * sizeof(R);
+    auto kern = k_fused_chunked<C, K, SC>;
+    const uint64_t res = resident_groups(reinterpret_cast<const void*>(kern), lds, kNT);
+    const uint64_t need = (f.ngroups + kNT / 64 - 1) / (kNT / 64);
+    hipLaunchKernelGGL(kern, dim3(persistent_grid(need, res)), dim3(kNT), lds, s, p, f, coef);
+    return (int)hipGetLastError();
+}
+
 // Where the fragments of A live: registers while they fit (complex64 at 5
-// qubits: 64 words per lane), LDS up to 64 KiB per workgroup, else the global
-// table (L2-resident, read at every step).
+// qubits: 64 words per lane), LDS up to 64 KiB per workgroup, else chunks of
+// the global table staged through LDS per workgroup.
 int launch_fused_direct(int dtype, void* psi, const FusedDesc& f, const void* coef, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
@@ -2156,7 +2278,7 @@ int launch_fused_direct(int dtype, void* psi, const FusedDesc& f, const void* co
         switch (f.k) {
         case 5: return launch_fd<float2, 5, kFragReg, true>(p, f, c, s);
         case 6: return launch_fd<float2, 6, kFragLds, true>(p, f, c, s);
-        case 7: return launch_fd<float2, 7, kFragGlobal, false>(p, f, c, s);
+        case 7: return launch_fc<float2, 7, 8>(p, f, c, s);
         default: break;
         }
     } else {
@@ -2164,7 +2286,7 @@ int launch_fused_direct(int dtype, void* psi, const FusedDesc& f, const void* co
         const double2* c = (const double2*)coef;
         switch (f.k) {
         case 5: return launch_fd<double2, 5, kFragLds, true>(p, f, c, s);
-        case 6: return launch_fd<double2, 6, kFragGlobal, false>(p, f, c, s);
+        case 6: return launch_fc<double2, 6, 8>(p, f, c, s);
         default: break;
         }
     }
