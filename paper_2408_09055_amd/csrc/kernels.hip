@@ -1869,7 +1869,13 @@ __global__ __launch_bounds__(kNT) void k_batch(BatchArgs a)
 // ----------------------------------------------------------- permutation pass
 // Tile = the 2^m amplitudes with fixed source bits outside act_src.  Reads
 // use the source run (lo_src low bits contiguous), writes the destination run.
-// Same persistent, register-prefetched structure as block_loop.
+// Same persistent, register-prefetched structure as block_loop.  The tile's
+// 16-byte chunks sit in LDS at perm_swz(chunk): the bits above 6 are XORed into
+// the six lowest, so the gather of a bit reversal (consecutive lanes reading
+// chunks 64 apart) spreads over the banks, while consecutive chunks (the
+// fill) stay a permutation of consecutive slots.
+__device__ __forceinline__ uint32_t perm_swz(uint32_t q) { return q ^ ((q >> 6) & 63u); }
+
 template <typename C>
 __global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* __restrict__ dst, PermDesc d)
 {
@@ -1912,14 +1918,15 @@ __global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* _
     auto load_all = [&](uint64_t b0) {
         static_for<0, kMaxChunks>([&](auto I) {
             const uint32_t c = tid + (uint32_t)I.value * kNT;
-            if (c < nch) buf[I.value] = *reinterpret_cast<const u32x4*>(&src[b0 + soff_t + soff_i[I.value]]);
+            if (c < nch)
+                buf[I.value] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(&src[b0 + soff_t + soff_i[I.value]]));
         });
     };
     load_all(sb);
     for (;;) {
         static_for<0, kMaxChunks>([&](auto I) {
             const uint32_t c = tid + (uint32_t)I.value * kNT;
-            if (c < nch) *reinterpret_cast<u32x4*>(&sm[c * CH]) = buf[I.value];
+            if (c < nch) *reinterpret_cast<u32x4*>(&sm[perm_swz(c) * CH]) = buf[I.value];
         });
         __syncthreads();
         const uint64_t db = dest_base(sb);
@@ -1933,9 +1940,10 @@ __global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* _
 #pragma unroll
                 for (int e = 0; e < CH; ++e) {
                     const uint32_t se = c * CH + e;
-                    u.v[e] = sm[rlo[se & ((1u << nlo) - 1u)] | rhi[se >> nlo]];
+                    const uint32_t si = rlo[se & ((1u << nlo) - 1u)] | rhi[se >> nlo];
+                    u.v[e] = sm[perm_swz(si / CH) * CH + si % CH];
                 }
-                *reinterpret_cast<u32x4*>(&dst[db + doff_t + doff_i[I.value]]) = u.w;
+                __builtin_nontemporal_store(u.w, reinterpret_cast<u32x4*>(&dst[db + doff_t + doff_i[I.value]]));
             }
         });
         if (next >= d.nblocks) break;
