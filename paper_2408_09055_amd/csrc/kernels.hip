@@ -1185,6 +1185,13 @@ __device__ __forceinline__ void rb_apply(V (&v)[kRbAmps], const Op& op, const C*
         const int nout = b1;
         // four entries per step: their scalar loads are issued together
         int e = 0;
+        if (op.b[2] & 1u) {
+            // linear outside phase: theta0 * (block base & mask)
+            const C c0 = u[0], c1 = u[1];
+            const uint64_t mask = (uint64_t)raw_code(c0.y) | ((uint64_t)raw_code(c1.y) << 32);
+            ang = (RR)((double)c0.x * (double)(bb & mask));
+            e = 2;
+        }
         for (; e + 4 <= nout; e += 4) {
             const C c0 = u[e], c1 = u[e + 1], c2 = u[e + 2], c3 = u[e + 3];
             if ((bb >> raw_code(c0.y)) & 1u) ang += c0.x;

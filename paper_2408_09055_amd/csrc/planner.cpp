@@ -732,8 +732,39 @@ void build_rb(qk_plan* P, PKernel& K)
         Op& o = lops[oi];
         if (o.code == OP_PHRUN) {
             const uint32_t first = (uint32_t)kc.size();
+            // Outside partners whose angles are theta0 * 2^q (the QFT's
+            // controlled phases; any single partner): their sum over the set
+            // partner bits is theta0 * (block base & mask), one product per
+            // block instead of a conditional sum per partner (b[2] = 1; the
+            // two entries hold theta0 with the low mask word and the high one).
+            double theta0 = 0.0;
+            uint64_t omask = 0;
+            int nouts = 0;
+            bool linear = true;
+            for (int e = 0; e < o.k; ++e) {
+                const int code = (int)P->coefs[o.coef + 2 * e + 1].real();
+                if (code < 64) continue;
+                const double th = std::arg(P->coefs[o.coef + 2 * e]);
+                const int q = code - 64;
+                if (nouts == 0) theta0 = std::ldexp(th, -q);
+                linear = linear && !((omask >> q) & 1ull) && std::fabs(std::ldexp(theta0, q) - th) <= 0x1p-50 * std::fabs(th);
+                omask |= 1ull << q;
+                ++nouts;
+            }
             int nout = 0;
-            for (int pass = 0; pass < 2; ++pass)
+            if (nouts > 0 && linear) {
+                kc.push_back(cd(theta0, 0.0));
+                raw.resize(kc.size(), -1);
+                raw.back() = (int64_t)(omask & 0xffffffffull);
+                kc.push_back(cd(0.0, 0.0));
+                raw.resize(kc.size(), -1);
+                raw.back() = (int64_t)(omask >> 32);
+                nout = 2;
+                o.b[2] = 1;
+            } else {
+                o.b[2] = 0;
+            }
+            for (int pass = nout ? 1 : 0; pass < 2; ++pass)
                 for (int e = 0; e < o.k; ++e) {
                     const int code = (int)P->coefs[o.coef + 2 * e + 1].real();
                     const bool outside = code >= 64;
@@ -743,6 +774,7 @@ void build_rb(qk_plan* P, PKernel& K)
                     raw.back() = outside ? code - 64 : code;
                     nout += outside;
                 }
+            o.k = (uint8_t)(kc.size() - first);
             o.b[1] = (uint8_t)nout;
             o.coef = first;
             continue;
