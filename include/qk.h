@@ -195,7 +195,12 @@ typedef struct qk_kopts {
                               0 = 13 for complex64, 12 for complex128 (64 KiB blocks) */
     int32_t ell;           /* lowest qubits forced into every LDS kernel, 1..m_max;
                               0 = 4 (128-byte runs for complex64, 256-byte for complex128) */
-    int32_t absorb_swaps;  /* relabel SWAP gates into the layout instead of running them */
+    int32_t absorb_swaps;  /* bit 0: relabel SWAP gates into the layout instead of
+                              running them; bit 1 (QK_ABSORB_ANTIDIAG): carry X and Y
+                              gates forward, flipping the controls and diagonals they
+                              pass (appendix, insular qubits: an anti-diagonal gate
+                              swapped past a controlled gate flips its control state),
+                              and apply what remains at the end */
     int32_t allow_fused;
     int32_t allow_lds;
     int32_t block_qubits;  /* amplitudes per staged block = 2^block_qubits
@@ -259,6 +264,7 @@ typedef struct qk_kopts {
  *               with pruning, small fusion kernels look cheap early and crowd
  *               out states whose shared-memory kernels later grow; the
  *               OrderedKernelize pass of FULL still prices both types. */
+#define QK_ABSORB_ANTIDIAG 2
 #define QK_DP_ATTACH_1Q 1u
 #define QK_DP_SUBSUME 2u
 #define QK_DP_PACK 4u
@@ -303,7 +309,9 @@ int plan_num_kernels(const qk_plan* p, int64_t* out);
 int plan_kernel_info(const qk_plan* p, int64_t i, qk_kernel_info* out);
 int plan_total_cost(const qk_plan* p, int64_t* out);
 /* Canonical gates (after SWAP absorption): count, then source index of gate
- * i in the input circuit. */
+ * i in the input circuit (-1 for gates the anti-diagonal carry of
+ * QK_ABSORB_ANTIDIAG creates: flipped-control partners, the X gates it
+ * applies where the carry stops or ends, and the global phase). */
 int plan_num_gates(const qk_plan* p, int64_t* out);
 int plan_gate_source(const qk_plan* p, int64_t i, int64_t* out);
 /* Layout after the last kernel: perm[q] = physical bit of logical qubit q. */

@@ -370,6 +370,120 @@ def canonicalize(circuit, absorb_swaps: bool = True):
     return out, P
 
 
+def push_anti_diagonal(circuit, absorb_swaps: bool = True):
+    """Move X and Y gates forward (appendix "Optimizations to the Kernelize
+    Algorithm", insular qubits: an anti-diagonal gate swapped past a
+    controlled gate flips the control state; Definition def:insular_qubit).
+
+    The pending X gates on each qubit are carried forward and every gate they
+    pass is replaced by its conjugate X_F G X_F, written out in the gate
+    set: a flipped control of CX becomes CX followed by X on the target; a
+    flipped qubit of CZ or CP(l) adds Z or P(l) on the other qubit (CP's
+    angle negated); RZ(t), RY(t) and RZZ(t) negate t; RX and a CX target
+    commute; a diagonal Z, S, T or P(l) becomes P(-l) times the global phase
+    e^{il}; Y is i X Z.  H and U3 stop the carry (the X is written before
+    them).  Remaining X gates end the circuit, and a global phase phi
+    becomes P(phi) X P(phi) X on qubit 0.  SWAPs are first absorbed into the
+    qubit map as in ``canonicalize`` (with absorb_swaps), else they move the
+    pending X.
+
+    Returns (list of (kind, qubit tuple, params tuple), final P)."""
+    from workloads import CP, CX, CZ, H, P as PG, RX, RY, RZ, RZZ, S, SWAP, T, U3, X, Y, Z
+    n = circuit.n_qubits
+    perm = list(range(n))
+    flip = [False] * n
+    phase = 0.0
+    out = []
+    diag_angle = {Z: math.pi, S: math.pi / 2, T: math.pi / 4}
+    for g in circuit.gates:
+        k = int(g["kind"]); nq = int(g["nq"])
+        qs = [int(x) for x in g["q"][:nq]]
+        p = tuple(float(x) for x in g["p"])
+        if k == SWAP and absorb_swaps:
+            a, b = qs
+            perm[a], perm[b] = perm[b], perm[a]
+            continue
+        v = [perm[q] for q in qs]
+        if k == X:
+            flip[v[0]] = not flip[v[0]]
+        elif k == Y:
+            # Y = i X Z: Z under the current flips, then X, then the phase i
+            if flip[v[0]]:
+                out.append((PG, (v[0],), (-math.pi, 0.0, 0.0)))
+                phase += math.pi
+            else:
+                out.append((Z, (v[0],), p))
+            flip[v[0]] = not flip[v[0]]
+            phase += math.pi / 2
+        elif k in (Z, S, T, PG):
+            lam = diag_angle.get(k, p[0])
+            if flip[v[0]]:
+                out.append((PG, (v[0],), (-lam, 0.0, 0.0)))
+                phase += lam
+            else:
+                out.append((k, (v[0],), p))
+        elif k in (RZ, RY):
+            out.append((k, (v[0],), (-p[0], 0.0, 0.0) if flip[v[0]] else p))
+        elif k == RX:
+            out.append((k, (v[0],), p))
+        elif k in (H, U3):
+            if flip[v[0]]:
+                out.append((X, (v[0],), (0.0, 0.0, 0.0)))
+                flip[v[0]] = False
+            out.append((k, (v[0],), p))
+        elif k == CX:
+            c, t = v
+            out.append((k, (c, t), p))
+            if flip[c]:
+                flip[t] = not flip[t]
+        elif k == CZ:
+            a, b = v
+            out.append((k, (a, b), p))
+            if flip[a]:
+                out.append((Z, (b,), (0.0, 0.0, 0.0)))
+            if flip[b]:
+                out.append((Z, (a,), (0.0, 0.0, 0.0)))
+            if flip[a] and flip[b]:
+                phase += math.pi
+        elif k == CP:
+            a, b = v
+            lam = p[0]
+            fa, fb = flip[a], flip[b]
+            if fa and fb:
+                out.append((k, (a, b), p))
+                out.append((PG, (a,), (-lam, 0.0, 0.0)))
+                out.append((PG, (b,), (-lam, 0.0, 0.0)))
+                phase += lam
+            elif fa or fb:
+                out.append((k, (a, b), (-lam, 0.0, 0.0)))
+                out.append((PG, (b if fa else a,), (lam, 0.0, 0.0)))
+            else:
+                out.append((k, (a, b), p))
+        elif k == RZZ:
+            a, b = v
+            out.append((k, (a, b), (-p[0], 0.0, 0.0) if flip[a] != flip[b] else p))
+        elif k == SWAP:
+            a, b = v
+            out.append((k, (a, b), p))
+            flip[a], flip[b] = flip[b], flip[a]
+        else:
+            raise ValueError(f"unknown gate kind {k}")
+    for q in range(n):
+        if flip[q]:
+            out.append((X, (q,), (0.0, 0.0, 0.0)))
+    phase = math.remainder(phase, 2 * math.pi)
+    if phase != 0.0:
+        for kk, pp in ((PG, (phase, 0.0, 0.0)), (X, (0.0, 0.0, 0.0)), (PG, (phase, 0.0, 0.0)), (X, (0.0, 0.0, 0.0))):
+            out.append((kk, (0,), pp))
+    return out, perm
+
+
+def circuit_of(n: int, gates, name: str = ""):
+    """A workloads circuit from (kind, qubits, params) triples."""
+    from workloads import from_list, gate
+    return from_list(n, [gate(k, list(qs), list(p)) for k, qs, p in gates], name)
+
+
 def segment_cost(seg, opts: KOpts, tab: CostTables):
     """Cost of one contiguous segment as a single kernel: the minimum over
     the two kernel types (fusion: constant per qubit count; shared memory:

@@ -310,6 +310,8 @@ int resolve_opts(const qk_kopts* ko_in, int n, qk_kopts& ko, int& mblk)
     if (ko.m_max < 2 || ko.m_max > kMaxBlockQubits) return fail(QK_EINVAL, "kernelize: m_max must be 2..14");
     if (ko.ell < 1 || ko.ell > ko.m_max) return fail(QK_EINVAL, "kernelize: ell must be 1..m_max");
     if (!ko.allow_fused && !ko.allow_lds) return fail(QK_EINVAL, "kernelize: no kernel type allowed");
+    if (ko.absorb_swaps < 0 || ko.absorb_swaps > (1 | QK_ABSORB_ANTIDIAG))
+        return fail(QK_EINVAL, "kernelize: absorb_swaps must be a combination of 1 and QK_ABSORB_ANTIDIAG");
     if (ko.kernelizer < QK_KERNELIZE_ORDERED || ko.kernelizer > QK_KERNELIZE_DP)
         return fail(QK_EINVAL, "kernelize: kernelizer must be ORDERED, FULL or DP");
     if (ko.dp_prune < 0 || ko.dp_prune == 1) return fail(QK_EINVAL, "kernelize: dp_prune must be 0 or >= 2");
@@ -327,11 +329,116 @@ int resolve_opts(const qk_kopts* ko_in, int n, qk_kopts& ko, int& mblk)
 }
 
 // Canonicalise c into P->gates / P->final_layout (SWAP absorption).
+// With absorb_swaps & QK_ABSORB_ANTIDIAG: X and Y gates are carried
+// forward instead of applied (appendix, insular qubits: an anti-diagonal gate
+// swapped past a controlled gate flips its control state).  flip[v] marks a
+// pending X on virtual qubit v; each gate G it passes is replaced by
+// X_F G X_F in the gate set, the pending X's continue, and the global phase
+// this produces is accumulated.  H and U3 take the pending X first; the
+// remaining ones and the global phase (P(phi) X P(phi) X on qubit 0) end the
+// circuit.  Returns QK_OK; the gates appended have src = -1 when synthetic.
+struct AntiDiag {
+    std::vector<char> flip;
+    double phase = 0.0;
+    std::vector<CGate>* out;
+    void put(uint32_t kind, int q0, int q1, double p0, int64_t src)
+    {
+        CGate g{};
+        g.kind = kind;
+        g.nq = q1 >= 0 ? 2 : 1;
+        g.q[0] = q0;
+        g.q[1] = q1 >= 0 ? q1 : 0;
+        g.p[0] = p0;
+        g.src = src;
+        out->push_back(g);
+    }
+    void apply(CGate g)
+    {
+        const int a = g.q[0], b = g.nq == 2 ? g.q[1] : -1;
+        const double pi = 3.14159265358979323846;
+        switch (g.kind) {
+        case QK_X: flip[a] ^= 1; return;
+        case QK_Y:
+            // Y = i X Z
+            if (flip[a]) { put(QK_P, a, -1, -pi, g.src); phase += pi; }
+            else put(QK_Z, a, -1, 0.0, g.src);
+            flip[a] ^= 1;
+            phase += pi / 2;
+            return;
+        case QK_Z: case QK_S: case QK_T: case QK_P: {
+            const double lam = g.kind == QK_Z ? pi : g.kind == QK_S ? pi / 2 : g.kind == QK_T ? pi / 4 : g.p[0];
+            if (flip[a]) { put(QK_P, a, -1, -lam, g.src); phase += lam; }
+            else out->push_back(g);
+            return;
+        }
+        case QK_RZ: case QK_RY:
+            if (flip[a]) g.p[0] = -g.p[0];
+            out->push_back(g);
+            return;
+        case QK_RX: out->push_back(g); return;
+        case QK_CX:
+            out->push_back(g);
+            if (flip[a]) flip[b] ^= 1;
+            return;
+        case QK_CZ:
+            out->push_back(g);
+            if (flip[a]) put(QK_Z, b, -1, 0.0, -1);
+            if (flip[b]) put(QK_Z, a, -1, 0.0, -1);
+            if (flip[a] && flip[b]) phase += pi;
+            return;
+        case QK_CP: {
+            const double lam = g.p[0];
+            if (flip[a] && flip[b]) {
+                out->push_back(g);
+                put(QK_P, a, -1, -lam, -1);
+                put(QK_P, b, -1, -lam, -1);
+                phase += lam;
+            } else if (flip[a] || flip[b]) {
+                g.p[0] = -lam;
+                out->push_back(g);
+                put(QK_P, flip[a] ? b : a, -1, lam, -1);
+            } else {
+                out->push_back(g);
+            }
+            return;
+        }
+        case QK_RZZ:
+            if (flip[a] != flip[b]) g.p[0] = -g.p[0];
+            out->push_back(g);
+            return;
+        case QK_SWAP:
+            out->push_back(g);
+            std::swap(flip[a], flip[b]);
+            return;
+        default:   // H, U3: the pending X is applied first
+            if (flip[a]) { put(QK_X, a, -1, 0.0, -1); flip[a] = 0; }
+            out->push_back(g);
+            return;
+        }
+    }
+    void finish(int n)
+    {
+        const double pi = 3.14159265358979323846;
+        for (int q = 0; q < n; ++q)
+            if (flip[q]) put(QK_X, q, -1, 0.0, -1);
+        const double ph = std::remainder(phase, 2 * pi);
+        if (ph != 0.0)
+            for (int t = 0; t < 2; ++t) {
+                put(QK_P, 0, -1, ph, -1);
+                put(QK_X, 0, -1, 0.0, -1);
+            }
+    }
+};
+
 int canonicalize(const qk_circuit* c, const qk_kopts& ko, qk_plan* P)
 {
     const int n = c->n_qubits;
     std::vector<int32_t> layout(n);
     for (int q = 0; q < n; ++q) layout[q] = q;
+    const bool antidiag = (ko.absorb_swaps & QK_ABSORB_ANTIDIAG) != 0;
+    AntiDiag ad;
+    ad.flip.assign(n, 0);
+    ad.out = &P->gates;
     for (int64_t i = 0; i < c->n_gates; ++i) {
         const qk_gate& g = c->gates[i];
         const int ar = kind_arity(g.kind);
@@ -342,7 +449,7 @@ int canonicalize(const qk_circuit* c, const qk_kopts& ko, qk_plan* P)
                 if (g.q[l] == g.q[j]) return fail(QK_EINVAL, "kernelize: gate " + std::to_string(i) + " repeats a qubit");
         }
         if (g.flags != 0) return fail(QK_EINVAL, "kernelize: gate flags must be 0");
-        if (ko.absorb_swaps && g.kind == QK_SWAP) {
+        if ((ko.absorb_swaps & 1) && g.kind == QK_SWAP) {
             std::swap(layout[g.q[0]], layout[g.q[1]]);
             continue;
         }
@@ -352,8 +459,10 @@ int canonicalize(const qk_circuit* c, const qk_kopts& ko, qk_plan* P)
         for (int j = 0; j < ar; ++j) cg.q[j] = layout[g.q[j]];
         cg.p[0] = g.p[0]; cg.p[1] = g.p[1]; cg.p[2] = g.p[2];
         cg.src = i;
-        P->gates.push_back(cg);
+        if (antidiag) ad.apply(cg);
+        else P->gates.push_back(cg);
     }
+    if (antidiag) ad.finish(n);
     P->final_layout = layout;
     return QK_OK;
 }

@@ -475,3 +475,32 @@ def test_lane_exchange_gates(ctx, dtype, m_max, ell):
         st.free()
         plan.free()
         _check(got, ref, dtype, f"lanes {name} m={m_max}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_antidiag_carry_matches_oracle(ctx, dtype):
+    """X and Y carried forward with flipped controls and diagonals
+    (absorb_swaps = 1 | QK_ABSORB_ANTIDIAG): the state equals the oracle's
+    gate-by-gate result of the original circuit, global phase included, with
+    the ordered and the full kernelizer; the carried plan holds no more gates
+    than the input."""
+    rng = np.random.default_rng(90 + dtype)
+    mix = [W.X, W.X, W.X, W.Y, W.Z, W.S, W.T, W.RX, W.RY, W.RZ, W.P, W.H, W.U3, W.CX, W.CX, W.CZ, W.CP, W.RZZ,
+           W.SWAP]
+    for n, count in ((14, 160), (17, 240)):
+        circ = W.random_circuit(n, count, rng, kinds=mix)
+        psi = W.random_state(n, n)
+        ref = oracle.run(circ, psi)
+        for kz in (qk.QK_KERNELIZE_ORDERED, qk.QK_KERNELIZE_FULL):
+            ko = qk.kopts(dtype=dtype, kernelizer=kz, absorb_swaps=1 | qk.QK_ABSORB_ANTIDIAG)
+            plan = qk.kernelize(ctx, circ, ko)
+            st = qk.sv_alloc(ctx, n, dtype)
+            st.upload(psi.astype(st.np_dtype))
+            qk.execute_plan(ctx, plan, st)
+            gpu = st.download()
+            st.free()
+            _check(gpu, ref, dtype, f"carry n={n} kernelizer={kz}")
+            plain = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, kernelizer=kz))
+            assert plan.num_gates() <= plain.num_gates() + n + 4
+            print(f"carry n={n} dtype={dtype} kernelizer={kz}: {len(plan)} kernels "
+                  f"(without the carry {len(plain)}), {plan.num_gates()} gates", flush=True)

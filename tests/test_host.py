@@ -410,6 +410,7 @@ _SAN_OPTS = [  # dtype kernelizer insular fuse local k_max prune absorb
     (1, 1, 1, 1, 0, 6, 500, 0), (0, 2, 1, 0, 0, 5, 64, 1), (1, 2, 0, 1, 0, 3, 500, 1),
     (0, 0, 1, 1, 13, 5, 500, 1), (1, 1, 1, 1, 12, 5, 500, 1), (0, 1, 0, 0, 13, 7, 200, 0),
     (0, 0, 1, 1, 12, 5, 500, 1),  # invalid: local_qubits below m_max (13 for complex64)
+    (0, 1, 1, 1, 0, 5, 500, 3), (1, 0, 0, 0, 13, 4, 500, 2),   # anti-diagonal carry
 ]
 
 
@@ -464,3 +465,46 @@ def test_planner_under_sanitizers(planner_san, tmp_path, hctx):
             assert (want["kernels"], want["cost"], want["stages"]) == (len(ks), plan.total_cost(),
                                                                         plan.num_stages()), (circs[ci].name, o)
             assert want["ks"] == ks, (circs[ci].name, o)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_antidiag_carry_native_equals_oracle(seed, hctx):
+    """absorb_swaps = 1 | QK_ABSORB_ANTIDIAG: the native canonical gate list
+    (X and Y carried forward, controls and diagonals flipped) partitions
+    exactly like the oracle's transform of the same circuit, gate count,
+    qubit map and kernel qubit sets included; gates the carry creates have
+    no source (-1)."""
+    rng = np.random.default_rng(3000 + seed)
+    n = int(rng.integers(2, 12))
+    mix = [W.X, W.X, W.Y, W.Z, W.S, W.T, W.RX, W.RY, W.RZ, W.P, W.H, W.U3, W.CX, W.CX, W.CZ, W.CP, W.RZZ, W.SWAP]
+    circ = W.random_circuit(n, int(rng.integers(1, 90)), rng, kinds=mix)
+    absorb = bool(rng.integers(0, 2))
+    out, perm = oracle.push_anti_diagonal(circ, absorb)
+    gates = [(k, qs, i) for i, (k, qs, _) in enumerate(out)]
+    k_max = int(rng.integers(2, 8))
+    m_max = int(rng.integers(max(3, k_max), 15))
+    opts = oracle.KOpts(k_max=k_max, m_max=m_max, ell=int(rng.integers(1, m_max + 1)), insular=bool(rng.integers(0, 2)))
+    tab = _rand_tables(rng, 1000)
+    ko = qk.kopts(k_max=opts.k_max, m_max=opts.m_max, ell=opts.ell,
+                  absorb_swaps=(1 if absorb else 0) | qk.QK_ABSORB_ANTIDIAG,
+                  block_qubits=max(opts.m_max, opts.k_max + 1), tables=(tab.fused, tab.alpha, tab.gate),
+                  insular=int(opts.insular))
+    plan = qk.kernelize(hctx, circ, ko)
+    assert plan.num_gates() == len(out)
+    assert plan.final_layout() == perm
+    if gates:
+        cost, ks = oracle.ordered_kernelize(gates, opts, tab)
+        assert plan.total_cost() == cost
+        assert [k.as_tuple() for k in plan.kernels()] == ks
+        for k in plan.kernels():
+            mask = 0
+            for (_, qs, _) in gates[k.gate_begin:k.gate_end]:
+                for q in qs:
+                    mask |= 1 << q
+            assert k.qubit_mask == mask
+    srcs = [plan.gate_source(i) for i in range(plan.num_gates())]
+    assert all(-1 <= s < len(circ.gates) for s in srcs)
+    # an X never stays where it was (a carried Y leaves its Z part behind,
+    # which keeps the Y's source)
+    kinds = [int(circ.gates[s]["kind"]) for s in srcs if s >= 0]
+    assert W.X not in kinds
