@@ -251,6 +251,20 @@ def cpu_baseline(n_full: int, gates_per_circuit: int) -> dict:
     one_core_gate = time.perf_counter() - t0
     oracle.set_threads(threads)
     del psi
+    # cross-check without scaling: the whole step (every gate of the three
+    # circuits) at n = 22 on all cores
+    n_w = min(n, 22)
+    psi_w = np.empty(1 << n_w, np.complex128)
+    whole_s = 0.0
+    whole_gates = 0
+    for name, circ, x in build_circuits(n_w):
+        psi_w[:] = 0
+        psi_w[0] = 1.0
+        t0 = time.perf_counter()
+        oracle.run_inplace(circ, psi_w, 0, len(circ))
+        whole_s += time.perf_counter() - t0
+        whole_gates += len(circ)
+    del psi_w
     step_s = sum(per_gate[name] * full[name] for name in full)
     return {
         "value": round(step_s * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
@@ -264,6 +278,8 @@ def cpu_baseline(n_full: int, gates_per_circuit: int) -> dict:
                      "step_ms": round(one_core_gate * sum(full.values()) * 1e3, 1),
                      "gbps": round(2 * (16 << n) / one_core_gate / 1e9, 2),
                      "sample": "first RL gate (U3 on qubit 0) on 1 thread"},
+        "whole_step": {"n": n_w, "gates": whole_gates, "ms": round(whole_s * 1e3, 1), "cores": threads,
+                       "sample": f"QFT-{n_w} + RL-{n_w} (20 layers) + GHZ-{n_w}, every gate, complex128, measured"},
         "first_touch_s": round(touch_s, 2), "host": facts, "build": " ".join(oracle.BUILD_FLAGS),
     }
 
