@@ -504,3 +504,33 @@ def test_antidiag_carry_matches_oracle(ctx, dtype):
             assert plan.num_gates() <= plain.num_gates() + n + 4
             print(f"carry n={n} dtype={dtype} kernelizer={kz}: {len(plan)} kernels "
                   f"(without the carry {len(plain)}), {plan.num_gates()} gates", flush=True)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_fused_direct_smallest_states(ctx, dtype):
+    """The direct matrix-core fused kernels at their smallest states:
+    n = k + 4 (one group of 16 columns: three of the four waves of the only
+    workgroup have no group) and n = k + 5, k = 5..7 (complex128 k = 7 stays
+    on the staged kernel), at low and top qubit positions, against the
+    oracle.  Fused costs equal for every k make the DP take one kernel over
+    all k qubits, which must run on the matrix cores."""
+    flat = ([0] + [1] * 7, 10 ** 9, [10 ** 6] * 7)
+    rng = np.random.default_rng(21 + dtype)
+    for k in (5, 6, 7):
+        for n in (k + 4, k + 5):
+            for qs in (list(range(k)), list(range(n - k, n))):
+                circ = W.random_circuit(n, 4 * k, rng, kinds=[W.U3, W.CX, W.CP, W.H], qubit_pool=qs)
+                used = {int(g['q'][j]) for g in circ.gates for j in range(int(g['nq']))}
+                psi = W.random_state(n, 100 + k + n)
+                ref = oracle.run(circ, psi)
+                plan = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, allow_lds=0, k_max=7, tables=flat))
+                ks = plan.kernels()
+                assert len(ks) == 1 and ks[0].impl == qk.QK_IMPL_MFMA_DENSE and ks[0].k == len(used), ks
+                st = qk.sv_alloc(ctx, n, dtype)
+                st.upload(psi.astype(st.np_dtype))
+                qk.execute_plan(ctx, plan, st)
+                gpu = st.download()
+                st.free()
+                plan.free()
+                print(f"direct k={k} n={n} qubits {qs[0]}..{qs[-1]} dtype={dtype}", flush=True)
+                _check(gpu, ref, dtype, f"k={k} n={n} qs={qs}")
