@@ -263,12 +263,25 @@ typedef struct qk_kopts {
  *               copy (section "Cost Function in Kernelize").  Off by default:
  *               with pruning, small fusion kernels look cheap early and crowd
  *               out states whose shared-memory kernels later grow; the
- *               OrderedKernelize pass of FULL still prices both types. */
+ *               OrderedKernelize pass of FULL still prices both types.
+ *  COMMUTE   -- the appendix's lift of the kernel constraint for insular
+ *               qubits: a qubit shared with an open kernel is ignored in the
+ *               intersect test of Algorithm alg:extensible when it is insular
+ *               (Definition def:insular_qubit: the gate is block-diagonal in
+ *               it) to the new gate and to every gate of that kernel, since
+ *               such gates commute.  Each kernel records the qubits ignored
+ *               against it and then takes a gate in place only if the gate is
+ *               insular on them.  The plan's gate order may then swap
+ *               commuting gates that share insular qubits, so it is
+ *               equivalent to the input up to such swaps rather than
+ *               topologically.  Needs insular = 1 (otherwise no qubit is
+ *               insular and the flag changes nothing).  Off by default. */
 #define QK_ABSORB_ANTIDIAG 2
 #define QK_DP_ATTACH_1Q 1u
 #define QK_DP_SUBSUME 2u
 #define QK_DP_PACK 4u
 #define QK_DP_FUSED 8u
+#define QK_DP_COMMUTE 16u
 
 /* Defaults: complex64, analytic, k_max 5, m_max 0 (auto), ell 0 (auto), swaps absorbed,
  * both kernel types, block_qubits 0, insular 1, kernelizer ORDERED, dp_prune 500,

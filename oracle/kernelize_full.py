@@ -29,6 +29,22 @@ Transitions for gate i (lines dp:add-directly and dp:singleton-kernel):
 Then every other open kernel's E is updated as in alg:extensible.  At the end
 every open kernel is closed in KS order.
 
+Option ``commute`` (the appendix's first lift of the kernel constraint for
+insular qubits): in the intersect test of alg:extensible, a shared qubit is
+ignored when it is insular to the new gate and to every gate of the open
+kernel K' (two gates whose shared qubits are all insular to both commute).
+Reading (listed in the design notes): taken literally this is not enough.
+K' can keep E = ALL past such a gate C (placed in a later kernel), later
+lose ALL to another gate, and then take in place a gate that is
+non-insular on the ignored qubit, which would then run before C without
+commuting with it.  Symmetrically, K' may later move to the end of KS past
+C's kernel, and a gate joining C's kernel in place would then run before
+K''s gates.  Each open kernel therefore also keeps the set I of qubits
+ignored between it and another open kernel (recorded on both, kept for the
+kernel's lifetime: kernels may pass each other again later): a gate joins
+a kernel in place only if it is insular on every qubit of its I.  The key
+of a state includes I.
+
 Reading (listed in the design notes): the appendix also lifts the kernel
 constraint for insular qubits through an "extensible insular qubit set"
 initialised to AllQubits minus Qubits(C[i]).  Read literally, that set can
@@ -55,6 +71,7 @@ class DPOpts:
     prune_T: int = 0            # 0 = no pruning; else keep T/2 states once T are reached
     pack: bool = False          # greedy packing of adjacent open kernels before pricing (end and pruning)
     fork_fused: bool = True     # a new kernel forks a fusion copy as well as a shared-memory copy
+    commute: bool = False       # ignore mutually insular shared qubits in alg:extensible's intersect test
 
 
 def _popcount(x: int) -> int:
@@ -128,10 +145,11 @@ def make_units(gates, opts: KOpts, attach_1q: bool):
 
 
 # ---------------------------------------------------------------------------
-# Kernel records: (type, Q, need, E, lds_sum, units tuple)
+# Kernel records: (type, Q, need, E, lds_sum, units tuple, I)
+# I: qubits the commuting lift ignored between K and another open kernel
 # ---------------------------------------------------------------------------
 def _cost(K, opts: KOpts, tab: CostTables):
-    t, q, nd, e, s, _ = K
+    t, q, nd, e, s, _, _ = K
     return tab.fused[_popcount(q)] if t == TYPE_FUSED else tab.alpha + s
 
 
@@ -141,21 +159,33 @@ def _feasible(t, q, nd, opts: KOpts):
     return opts.allow_lds and _popcount(nd | ((1 << opts.ell) - 1)) <= opts.m_max
 
 
-def _update_others(open_, skip, uq):
+def _update_others(open_, skip, uq, und=None):
     """alg:extensible for every kernel but index ``skip``, after a gate with
-    qubit mask ``uq``."""
+    qubit mask ``uq``.  With ``und`` (the gate's non-insular qubits; the
+    commuting lift) a shared qubit that is insular to the gate and to every
+    gate of the kernel is left out of the intersect test and recorded in the
+    I of both kernels, that one and ``skip`` (the gate's own)."""
     out = []
+    mine = 0
     for j, K in enumerate(open_):
         if j == skip:
             out.append(K)
             continue
-        t, q, nd, e, s, us = K
+        t, q, nd, e, s, us, ins = K
         if e == ALL:
-            if uq & q:
+            shared = uq & q
+            ign = shared & ~und & ~nd if und is not None else 0
+            if shared & ~ign:
                 e = q & ~uq
+            else:
+                ins |= ign
+                mine |= ign
         else:
             e = e & ~uq
-        out.append((t, q, nd, e, s, us))
+        out.append((t, q, nd, e, s, us, ins))
+    if mine:
+        t, q, nd, e, s, us, ins = out[skip]
+        out[skip] = (t, q, nd, e, s, us, ins | mine)
     return out
 
 
@@ -167,7 +197,7 @@ def _pack(open_, opts: KOpts, tab: CostTables):
     for K in open_:
         if out and out[-1][0] == K[0]:
             P = out[-1]
-            M = (K[0], P[1] | K[1], P[2] | K[2], ALL, P[4] + K[4], P[5] + K[5])
+            M = (K[0], P[1] | K[1], P[2] | K[2], ALL, P[4] + K[4], P[5] + K[5], 0)
             if _feasible(M[0], M[1], M[2], opts) and _cost(M, opts, tab) <= _cost(P, opts, tab) + _cost(K, opts, tab):
                 out[-1] = M
                 continue
@@ -199,7 +229,7 @@ def kernelize(gates, opts: KOpts, tab: CostTables, dp: DPOpts | None = None):
         nxt = {}
 
         def offer(v, nk, closed, open_):
-            key = tuple((K[0], K[1], K[2], K[3]) for K in open_)
+            key = tuple((K[0], K[1], K[2], K[3], K[6]) for K in open_)
             cur = nxt.get(key)
             if cur is None or (v, nk) < (cur[0], cur[1]):
                 nxt[key] = (v, nk, closed, tuple(open_))
@@ -207,8 +237,8 @@ def kernelize(gates, opts: KOpts, tab: CostTables, dp: DPOpts | None = None):
         for v, nk, closed, open_ in states:
             cands = []
             for j, K in enumerate(open_):
-                t, q, nd, e, s, us = K
-                if e != ALL and (uq & ~e):
+                t, q, nd, e, s, us, ins = K
+                if e != ALL and ((uq & ~e) or (und & ins)):
                     continue
                 nq_, nnd = q | uq, nd | und
                 if not _feasible(t, nq_, nnd, opts):
@@ -222,29 +252,30 @@ def kernelize(gates, opts: KOpts, tab: CostTables, dp: DPOpts | None = None):
                         sub = j
                         break
             add_to = [sub] if sub is not None else cands
+            cu = und if dp.commute else None
             for j in add_to:
-                t, q, nd, e, s, us = open_[j]
-                K2 = (t, q | uq, nd | und, e, s + ucost[ui], us + (ui,))
+                t, q, nd, e, s, us, ins = open_[j]
+                K2 = (t, q | uq, nd | und, e, s + ucost[ui], us + (ui,), ins)
                 dv = _cost(K2, opts, tab) - _cost(open_[j], opts, tab)
                 lst = list(open_)
                 if e == ALL:          # monotonicity does not apply: K moves to the end
                     del lst[j]
                     lst.append(K2)
-                    lst = _update_others(lst, len(lst) - 1, uq)
+                    lst = _update_others(lst, len(lst) - 1, uq, cu)
                 else:                 # in place
                     lst[j] = K2
-                    lst = _update_others(lst, j, uq)
+                    lst = _update_others(lst, j, uq, cu)
                 offer(v + dv, nk, closed, lst)
             if sub is not None:
                 continue
             for t in (TYPE_FUSED, TYPE_LDS):
                 if (t == TYPE_FUSED and not dp.fork_fused) or not _feasible(t, uq, und, opts):
                     continue
-                Knew = (t, uq, und, ALL, ucost[ui], (ui,))
+                Knew = (t, uq, und, ALL, ucost[ui], (ui,), 0)
                 cnew = _cost(Knew, opts, tab)
                 for p in range(len(open_) + 1):
                     cl = closed + tuple((K[0], K[5], _cost(K, opts, tab)) for K in open_[:p])
-                    lst = _update_others(list(open_[p:]) + [Knew], len(open_) - p, uq)
+                    lst = _update_others(list(open_[p:]) + [Knew], len(open_) - p, uq, cu)
                     offer(v + cnew, nk + 1, cl, lst)
         if not nxt:
             raise ValueError(f"gate unit {ui} fits no kernel type")
@@ -329,6 +360,31 @@ def is_topologically_equivalent(gates, order) -> bool:
     for a in range(m):
         for b in range(a + 1, m):
             if qm[a] & qm[b] and pos[a] > pos[b]:
+                return False
+    return True
+
+
+def is_commuting_equivalent(gates, order) -> bool:
+    """``order`` keeps in their original relative order every pair of gates
+    that share a qubit which is not insular to both (with the commuting
+    lift, gates whose shared qubits are all insular to both may swap: each
+    is block-diagonal in those qubits and acts on disjoint other qubits)."""
+    m = len(gates)
+    if sorted(order) != list(range(m)):
+        return False
+    pos = [0] * m
+    for p, g in enumerate(order):
+        pos[g] = p
+    qm = [gate_qubits(gates, i) for i in range(m)]
+    nm = []
+    for kind, qs, _ in gates:
+        x = 0
+        for q in need_qubits(kind, qs, True):
+            x |= 1 << q
+        nm.append(x)
+    for a in range(m):
+        for b in range(a + 1, m):
+            if qm[a] & qm[b] & (nm[a] | nm[b]) and pos[a] > pos[b]:
                 return False
     return True
 

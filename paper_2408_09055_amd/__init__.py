@@ -40,7 +40,7 @@ QK_NOALLOC_SCRATCH_BYTES = 4 << 20
 QK_IMPL_LDS_SEQUENCE, QK_IMPL_REGISTER, QK_IMPL_LDS_DENSE, QK_IMPL_MFMA_DENSE = 0, 1, 2, 3
 QK_KERNELIZE_ORDERED, QK_KERNELIZE_FULL, QK_KERNELIZE_DP = 0, 1, 2
 QK_ABSORB_ANTIDIAG = 2
-QK_DP_ATTACH_1Q, QK_DP_SUBSUME, QK_DP_PACK, QK_DP_FUSED = 1, 2, 4, 8
+QK_DP_ATTACH_1Q, QK_DP_SUBSUME, QK_DP_PACK, QK_DP_FUSED, QK_DP_COMMUTE = 1, 2, 4, 8, 16
 IMPL_NAMES = ["lds_sequence", "register", "lds_dense", "mfma_dense"]
 NUM_CLASSES = 7
 

@@ -8,16 +8,26 @@
 //
 // DP state before unit u: the closed kernels (final order) and the ordered
 // set KS of open kernels, each with its type, qubit set Q, LDS need set, the
-// extensible set E (kAll = every qubit) and its LDS gate-cost sum.  Two
-// states whose open kernels agree in (type, Q, need, E) have the same
-// futures, so only the cheaper one stays (cost, kernel count, first made).
+// extensible set E (kAll = every qubit), its LDS gate-cost sum and the set I
+// of the commuting lift below.  Two states whose open kernels agree in
+// (type, Q, need, E, I) have the same futures, so only the cheaper one stays
+// (cost, kernel count, first made).
 // Transitions for unit u:
 //   * join an open kernel K whose E holds u's qubits and whose type stays
 //     feasible; K stays in place when E != kAll (monotonicity applies) and
 //     moves to the end of KS otherwise;
 //   * open a new kernel {u} after closing any prefix of KS; it goes last.
 // Then every other open kernel's E follows alg:extensible.  At the end the
-// open kernels are closed in KS order.  Kernel membership and closed kernels
+// open kernels are closed in KS order.
+//
+// Commuting lift (QK_DP_COMMUTE, the appendix's insular qubits): in the
+// intersect test of alg:extensible a shared qubit that is insular to the new
+// unit and to every gate of the other kernel is ignored (such gates commute).
+// Kernels can then pass each other with gates out of input order, so the
+// ignored qubits are recorded in I on both kernels for their lifetime, and a
+// unit joins a kernel in place only if it is insular on all of that kernel's
+// I; without this record a later in-place join could overtake a gate it does
+// not commute with.  Kernel membership and closed kernels
 // are persistent linked lists, so a state copies only its open-kernel
 // records.
 #include <algorithm>
@@ -37,6 +47,7 @@ struct DKer {
     uint64_t q, need, ext;
     int64_t lsum;
     int32_t units;   // head of this kernel's unit list (most recent first)
+    uint64_t ins;    // qubits the commuting lift ignored against other kernels
 };
 
 struct DState {
@@ -99,7 +110,7 @@ struct Ctx {
             const DKer& K = open[i];
             if (!out.empty() && out.back().type == K.type) {
                 const DKer& P = out.back();
-                DKer M{K.type, P.q | K.q, P.need | K.need, kAll, P.lsum + K.lsum, -1};
+                DKer M{K.type, P.q | K.q, P.need | K.need, kAll, P.lsum + K.lsum, -1, 0};
                 if (feasible(M.type, M.q, M.need) && cost(M) <= cost(P) + cost(K)) {
                     M.units = concat_units(P.units, K.units);
                     out.back() = M;
@@ -118,7 +129,7 @@ struct Ctx {
         for (uint32_t i = 0; i < len; ++i) {
             const DKer& K = open[i];
             if (have && P.type == K.type) {
-                DKer M{K.type, P.q | K.q, P.need | K.need, kAll, P.lsum + K.lsum, -1};
+                DKer M{K.type, P.q | K.q, P.need | K.need, kAll, P.lsum + K.lsum, -1, 0};
                 if (feasible(M.type, M.q, M.need) && cost(M) <= cost(P) + cost(K)) {
                     P = M;
                     continue;
@@ -134,18 +145,29 @@ struct Ctx {
     }
 };
 
-// alg:extensible for every open kernel but index `skip`, after unit qubits uq
-void update_others(DKer* ks, uint32_t len, uint32_t skip, uint64_t uq)
+// alg:extensible for every open kernel but index `skip`, after a unit with
+// qubits uq; with `commute`, shared qubits insular to the unit (outside its
+// need set und) and to the kernel are ignored and recorded on both kernels
+void update_others(DKer* ks, uint32_t len, uint32_t skip, uint64_t uq, uint64_t und, bool commute)
 {
+    uint64_t mine = 0;
     for (uint32_t j = 0; j < len; ++j) {
         if (j == skip) continue;
         DKer& K = ks[j];
         if (K.ext == kAll) {
-            if (uq & K.q) K.ext = K.q & ~uq;
+            const uint64_t shared = uq & K.q;
+            const uint64_t ign = commute ? shared & ~und & ~K.need : 0;
+            if (shared & ~ign) {
+                K.ext = K.q & ~uq;
+            } else {
+                K.ins |= ign;
+                mine |= ign;
+            }
         } else {
             K.ext &= ~uq;
         }
     }
+    ks[skip].ins |= mine;
 }
 
 struct KeyHash {
@@ -155,7 +177,7 @@ struct KeyHash {
         uint64_t h = 1469598103934665603ull ^ k.second;
         for (uint32_t i = 0; i < k.second; ++i) {
             const DKer& K = (*arena)[k.first + i];
-            for (uint64_t w : {(uint64_t)K.type, K.q, K.need, K.ext}) {
+            for (uint64_t w : {(uint64_t)K.type, K.q, K.need, K.ext, K.ins}) {
                 h ^= w + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
             }
         }
@@ -170,7 +192,8 @@ struct KeyEq {
         for (uint32_t i = 0; i < a.second; ++i) {
             const DKer& x = (*arena)[a.first + i];
             const DKer& y = (*arena)[b.first + i];
-            if (x.type != y.type || x.q != y.q || x.need != y.need || x.ext != y.ext) return false;
+            if (x.type != y.type || x.q != y.q || x.need != y.need || x.ext != y.ext || x.ins != y.ins)
+                return false;
         }
         return true;
     }
@@ -237,7 +260,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
     if (G.empty()) return QK_OK;
     const uint32_t flags = (uint32_t)ko.dp_flags;
     const bool attach = flags & QK_DP_ATTACH_1Q, subsume = flags & QK_DP_SUBSUME, packing = flags & QK_DP_PACK,
-               fork_fused = flags & QK_DP_FUSED;
+               fork_fused = flags & QK_DP_FUSED, commute = flags & QK_DP_COMMUTE;
     const int64_t T = ko.dp_prune;
     std::vector<Unit> units;
     make_units(G, ko, attach, units);
@@ -304,7 +327,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
             std::vector<uint32_t> cands;
             for (uint32_t j = 0; j < S.len; ++j) {
                 const DKer& K = ks[j];
-                if (K.ext != kAll && (U.q & ~K.ext)) continue;
+                if (K.ext != kAll && ((U.q & ~K.ext) || (U.need & K.ins))) continue;
                 if (!C.feasible(K.type, K.q | U.q, K.need | U.need)) continue;
                 cands.push_back(j);
             }
@@ -314,16 +337,17 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
                     if ((U.q & ~ks[j].q) == 0 || (ks[j].q & ~U.q) == 0) { sub = j; break; }
             auto add_to = [&](uint32_t j) {
                 const DKer& K = ks[j];
-                DKer K2{K.type, K.q | U.q, K.need | U.need, K.ext, K.lsum + U.lcost, C.push_unit((int32_t)ui, K.units)};
+                DKer K2{K.type, K.q | U.q, K.need | U.need, K.ext, K.lsum + U.lcost,
+                        C.push_unit((int32_t)ui, K.units), K.ins};
                 const int64_t dv = C.cost(K2) - C.cost(K);
                 tmp.assign(ks, ks + S.len);
                 if (K.ext == kAll) {
                     tmp.erase(tmp.begin() + j);
                     tmp.push_back(K2);
-                    update_others(tmp.data(), (uint32_t)tmp.size(), (uint32_t)tmp.size() - 1, U.q);
+                    update_others(tmp.data(), (uint32_t)tmp.size(), (uint32_t)tmp.size() - 1, U.q, U.need, commute);
                 } else {
                     tmp[j] = K2;
-                    update_others(tmp.data(), (uint32_t)tmp.size(), j, U.q);
+                    update_others(tmp.data(), (uint32_t)tmp.size(), j, U.q, U.need, commute);
                 }
                 offer(S.v + dv, S.nk, S.ncl, S.closed, tmp);
             };
@@ -334,7 +358,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
             for (uint32_t j : cands) add_to(j);
             for (int t : {QK_KERNEL_FUSED, QK_KERNEL_LDS}) {
                 if ((t == QK_KERNEL_FUSED && !fork_fused) || !C.feasible(t, U.q, U.need)) continue;
-                DKer Kn{t, U.q, U.need, kAll, U.lcost, C.push_unit((int32_t)ui, -1)};
+                DKer Kn{t, U.q, U.need, kAll, U.lcost, C.push_unit((int32_t)ui, -1), 0};
                 const int64_t cnew = C.cost(Kn);
                 int32_t closed = S.closed;
                 for (uint32_t p = 0; p <= S.len; ++p) {
@@ -345,7 +369,7 @@ int kernelize_dp(const std::vector<CGate>& G, const qk_kopts& ko, const qk_cost_
                     }
                     tmp.assign(ks + p, ks + S.len);
                     tmp.push_back(Kn);
-                    update_others(tmp.data(), (uint32_t)tmp.size(), (uint32_t)tmp.size() - 1, U.q);
+                    update_others(tmp.data(), (uint32_t)tmp.size(), (uint32_t)tmp.size() - 1, U.q, U.need, commute);
                     offer(S.v + cnew, S.nk + 1, S.ncl + p, closed, tmp);
                 }
             }

@@ -315,7 +315,7 @@ int resolve_opts(const qk_kopts* ko_in, int n, qk_kopts& ko, int& mblk)
     if (ko.kernelizer < QK_KERNELIZE_ORDERED || ko.kernelizer > QK_KERNELIZE_DP)
         return fail(QK_EINVAL, "kernelize: kernelizer must be ORDERED, FULL or DP");
     if (ko.dp_prune < 0 || ko.dp_prune == 1) return fail(QK_EINVAL, "kernelize: dp_prune must be 0 or >= 2");
-    if ((uint32_t)ko.dp_flags & ~(QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK | QK_DP_FUSED))
+    if ((uint32_t)ko.dp_flags & ~(QK_DP_ATTACH_1Q | QK_DP_SUBSUME | QK_DP_PACK | QK_DP_FUSED | QK_DP_COMMUTE))
         return fail(QK_EINVAL, "kernelize: unknown dp_flags bits");
     if (ko.local_qubits < 0 || (ko.local_qubits > 0 && ko.local_qubits < n && ko.local_qubits < std::max(ko.m_max, ko.k_max)))
         return fail(QK_EINVAL, "kernelize: local_qubits must be 0 or at least m_max and k_max");

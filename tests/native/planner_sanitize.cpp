@@ -12,6 +12,7 @@
 //                 48-byte qk_gate}
 //   options.txt:  one option set per line:
 //                 dtype kernelizer insular fuse_gates local_qubits k_max dp_prune absorb_swaps
+//                 dp_flags
 // Prints, per (circuit, option set): "plan c o rc kernels total_cost stages",
 // then one line per kernel: "k type g0 g1 mask n_ops stage rb".
 #include <cinttypes>
@@ -48,9 +49,10 @@ int main(int argc, char** argv)
     FILE* fo = std::fopen(argv[2], "r");
     if (!fo) return 2;
     for (;;) {
-        std::vector<int32_t> o(8);
-        int got = std::fscanf(fo, "%d %d %d %d %d %d %d %d", &o[0], &o[1], &o[2], &o[3], &o[4], &o[5], &o[6], &o[7]);
-        if (got != 8) break;
+        std::vector<int32_t> o(9);
+        int got = std::fscanf(fo, "%d %d %d %d %d %d %d %d %d", &o[0], &o[1], &o[2], &o[3], &o[4], &o[5], &o[6], &o[7],
+                              &o[8]);
+        if (got != 9) break;
         opts.push_back(o);
     }
     std::fclose(fo);
@@ -79,6 +81,7 @@ int main(int argc, char** argv)
             ko.k_max = o[5];
             ko.dp_prune = o[6];
             ko.absorb_swaps = o[7];
+            ko.dp_flags = o[8];
             qk_plan* P = nullptr;
             const int rc = qk::build_plan(nullptr, &circ, &ko, &P);
             if (rc) {

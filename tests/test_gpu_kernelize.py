@@ -117,3 +117,51 @@ def test_fused_gate_runs_match_oracle(ctx, dtype):
                 print(f"brick{n} dtype={dtype} fuse={fg} kernelizer={kz}: {len(plan)} kernels, "
                       f"{sum(k.n_ops for k in plan.kernels())} ops, impl {[k.impl for k in plan.kernels()]}, "
                       f"1-F={loss:.3e}", flush=True)
+
+
+# Fixed analytic tables (ps) so the plans do not depend on calibration.
+_TABLES = ([0] + [26_000_000_000] * 4 + [95_000_000_000, 175_000_000_000, 176_000_000_000], 26_300_000_000,
+           [75_000_000, 99_000_000, 220_000_000, 774_000_000, 47_000_000, 49_000_000, 1_343_000_000])
+
+
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_commute_lift_plans_match_oracle(ctx, dtype):
+    """Kernelize with the commuting lift (QK_DP_COMMUTE, the appendix's
+    insular-qubit lift of the kernel constraint): plans whose order swaps
+    gates that share only insular qubits.  Random 18-qubit circuits of
+    diagonal gates, CX, H and U3, with fused kernels of at most 3 or 4
+    qubits (where the lift saves kernels) and with staged blocks of 2^9
+    amplitudes.  Every order must be equivalent to the input up to such
+    swaps, the lift must have reordered gates in some case, and every state
+    matches the oracle."""
+    base = qk.QK_DP_ATTACH_1Q | qk.QK_DP_SUBSUME | qk.QK_DP_PACK | qk.QK_DP_COMMUTE
+    kinds = [W.H, W.CX, W.CZ, W.CP, W.RZZ, W.RZ, W.U3]
+    cases = [(0, dict(allow_lds=0, k_max=3), base | qk.QK_DP_FUSED),
+             (4, dict(allow_lds=0, k_max=4), base | qk.QK_DP_FUSED),
+             (3, dict(m_max=9, ell=2, block_qubits=9), base)]
+    reordered = 0
+    for seed, kw, flags in cases:
+        circ = W.random_circuit(18, 120, np.random.default_rng(100 + seed), kinds=kinds)
+        psi = W.random_state(18, seed)
+        ref = oracle.run(circ, psi)
+        gates, _ = oracle.canonicalize(circ, True)
+        by_src = {g[2]: t for t, g in enumerate(gates)}
+        for kz in (qk.QK_KERNELIZE_DP, qk.QK_KERNELIZE_FULL):
+            ko = qk.kopts(dtype=dtype, kernelizer=kz, dp_flags=flags, tables=_TABLES, **kw)
+            plan = qk.kernelize(ctx, circ, ko)
+            order = [by_src[plan.gate_source(t)] for t in range(len(gates))]
+            assert KF.is_commuting_equivalent(gates, order), (seed, kz)
+            reordered += not KF.is_topologically_equivalent(gates, order)
+            plain = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, kernelizer=kz, tables=_TABLES,
+                                                     dp_flags=flags & ~qk.QK_DP_COMMUTE, **kw))
+            st = qk.sv_alloc(ctx, 18, dtype)
+            st.upload(psi.astype(st.np_dtype))
+            qk.execute_plan(ctx, plan, st)
+            out = st.download()
+            st.free()
+            loss = _check(out, ref, dtype, f"commute seed={seed} {kw} kernelizer={kz}")
+            print(f"commute seed={seed} {kw} dtype={dtype} kernelizer={kz}: {len(plan)} kernels "
+                  f"(without the lift {len(plain)}), 1-F={loss:.3e}", flush=True)
+            plan.free()
+            plain.free()
+    assert reordered >= 4

@@ -231,7 +231,8 @@ def _kz_native(hctx, circ, opts, tab, kernelizer, T, flags):
 
 def _dp_opts(flags, T):
     return KF.DPOpts(attach_1q=bool(flags & qk.QK_DP_ATTACH_1Q), subsume=bool(flags & qk.QK_DP_SUBSUME),
-                     pack=bool(flags & qk.QK_DP_PACK), fork_fused=bool(flags & qk.QK_DP_FUSED), prune_T=T)
+                     pack=bool(flags & qk.QK_DP_PACK), fork_fused=bool(flags & qk.QK_DP_FUSED), prune_T=T,
+                     commute=bool(flags & qk.QK_DP_COMMUTE))
 
 
 @pytest.mark.parametrize("seed", range(40))
@@ -264,6 +265,45 @@ def test_native_kernelize_equals_oracle(seed, hctx):
            for k in plan.kernels()]
     assert got == [(t, tuple(gates[g][2] for g in gl), c) for t, gl, c in oks]
     assert plan.total_cost() == oc
+    c2, order, k2 = KF.kernelize_then_order(gates, opts, tab, dp)
+    plan = _kz_native(hctx, circ, opts, tab, qk.QK_KERNELIZE_FULL, T, flags)
+    assert plan.total_cost() == c2
+    assert [plan.gate_source(t) for t in range(plan.num_gates())] == [gates[g][2] for g in order]
+    assert [k.as_tuple() for k in plan.kernels()] == k2
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_native_kernelize_commute_equals_oracle(seed, hctx):
+    """With the commuting lift (QK_DP_COMMUTE) on circuits rich in diagonal
+    gates and CX controls, native Kernelize (DP and FULL modes) returns
+    exactly the oracle's kernels, order and costs, and the order is
+    equivalent to the input up to swaps of gates whose shared qubits are
+    insular to both."""
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(3, 12))
+    kinds = [W.H, W.X, W.U3, W.CX, W.CZ, W.CP, W.RZZ, W.RZ, W.P]
+    circ = W.random_circuit(n, int(rng.integers(1, 9 if seed % 4 == 0 else 60)), rng, kinds=kinds)
+    flags = qk.QK_DP_COMMUTE | int(rng.integers(16))
+    T = 0 if (seed % 4 == 0 and len(circ) <= 8) else int(rng.choice([2, 6, 20, 100]))
+    m_max = int(rng.integers(2, 9))
+    opts = oracle.KOpts(k_max=int(rng.integers(1, 6)), m_max=m_max, ell=int(rng.integers(1, min(3, m_max) + 1)),
+                        insular=seed % 5 != 0)
+    tab = _rand_tables(rng, int(rng.choice([10, 1000, 10 ** 9])))
+    gates, _ = oracle.canonicalize(circ, True)
+    if not gates:
+        return
+    dp = _dp_opts(flags, T)
+    try:
+        oc, oks = KF.kernelize(gates, opts, tab, dp)
+    except ValueError:
+        _expect(qk.QK_EINVAL, _kz_native, hctx, circ, opts, tab, qk.QK_KERNELIZE_DP, T, flags)
+        return
+    plan = _kz_native(hctx, circ, opts, tab, qk.QK_KERNELIZE_DP, T, flags)
+    got = [(k.type, tuple(plan.gate_source(t) for t in range(k.gate_begin, k.gate_end)), k.cost_ps)
+           for k in plan.kernels()]
+    assert got == [(t, tuple(gates[g][2] for g in gl), c) for t, gl, c in oks]
+    assert plan.total_cost() == oc
+    assert KF.is_commuting_equivalent(gates, [g for _, gl, _ in oks for g in gl])
     c2, order, k2 = KF.kernelize_then_order(gates, opts, tab, dp)
     plan = _kz_native(hctx, circ, opts, tab, qk.QK_KERNELIZE_FULL, T, flags)
     assert plan.total_cost() == c2
@@ -389,6 +429,7 @@ def _san_circuits():
         g.append(W.gate(W.SWAP, [int(rng.integers(5)), 5 + int(rng.integers(5))]))
     circs.append(W.from_list(10, g, "brick10"))
     circs.append(W.from_list(8, [], "empty8"))
+    circs.append(W.random_circuit(14, 120, rng, kinds=[W.H, W.X, W.CX, W.CZ, W.CP, W.RZZ, W.RZ]))
     return circs
 
 
@@ -405,12 +446,13 @@ def _san_bad_circuits():
     return bad
 
 
-_SAN_OPTS = [  # dtype kernelizer insular fuse local k_max prune absorb
-    (0, 0, 1, 1, 0, 5, 500, 1), (1, 0, 0, 0, 0, 4, 500, 1), (0, 1, 1, 1, 0, 5, 500, 1),
-    (1, 1, 1, 1, 0, 6, 500, 0), (0, 2, 1, 0, 0, 5, 64, 1), (1, 2, 0, 1, 0, 3, 500, 1),
-    (0, 0, 1, 1, 13, 5, 500, 1), (1, 1, 1, 1, 12, 5, 500, 1), (0, 1, 0, 0, 13, 7, 200, 0),
-    (0, 0, 1, 1, 12, 5, 500, 1),  # invalid: local_qubits below m_max (13 for complex64)
-    (0, 1, 1, 1, 0, 5, 500, 3), (1, 0, 0, 0, 13, 4, 500, 2),   # anti-diagonal carry
+_SAN_OPTS = [  # dtype kernelizer insular fuse local k_max prune absorb dp_flags
+    (0, 0, 1, 1, 0, 5, 500, 1, 7), (1, 0, 0, 0, 0, 4, 500, 1, 7), (0, 1, 1, 1, 0, 5, 500, 1, 7),
+    (1, 1, 1, 1, 0, 6, 500, 0, 7), (0, 2, 1, 0, 0, 5, 64, 1, 7), (1, 2, 0, 1, 0, 3, 500, 1, 7),
+    (0, 0, 1, 1, 13, 5, 500, 1, 7), (1, 1, 1, 1, 12, 5, 500, 1, 7), (0, 1, 0, 0, 13, 7, 200, 0, 7),
+    (0, 0, 1, 1, 12, 5, 500, 1, 7),  # invalid: local_qubits below m_max (13 for complex64)
+    (0, 1, 1, 1, 0, 5, 500, 3, 7), (1, 0, 0, 0, 13, 4, 500, 2, 7),   # anti-diagonal carry
+    (0, 1, 1, 1, 0, 5, 500, 1, 23), (1, 2, 1, 0, 0, 4, 64, 1, 16),   # commuting lift
 ]
 
 
@@ -450,7 +492,7 @@ def test_planner_under_sanitizers(planner_san, tmp_path, hctx):
         for oi, o in enumerate(_SAN_OPTS):
             want = got[(ci, oi)]
             ko = qk.kopts(dtype=o[0], kernelizer=o[1], insular=o[2], fuse_gates=o[3], local_qubits=o[4],
-                          k_max=o[5], dp_prune=o[6], absorb_swaps=o[7])
+                          k_max=o[5], dp_prune=o[6], absorb_swaps=o[7], dp_flags=o[8])
             if ci >= len(circs):
                 assert want["rc"] != 0, (ci, oi)
                 continue

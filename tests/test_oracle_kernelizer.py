@@ -372,3 +372,148 @@ def test_attached_units_stand_at_their_anchor():
     assert [u[0] for u in units] == [(0, 1, 2), (4, 5), (3, 6, 7)]
     order = [g for u in units for g in u[0]]
     assert KF.is_topologically_equivalent(gates, order)
+
+
+# ---------------------------------------------------------------------------
+# The commuting lift of the kernel constraint (appendix, insular qubits)
+# ---------------------------------------------------------------------------
+COMMUTE_KINDS = [W.H, W.X, W.U3, W.CX, W.CZ, W.CP, W.RZZ, W.RZ, W.P]
+
+
+def _reordered_state(c, gates, order, psi):
+    """The state after the canonical gates of ``c`` (no SWAPs, so qubits are
+    logical) run in ``order``."""
+    seq = []
+    for g in order:
+        kind, qs, src = gates[g]
+        seq.append((kind, qs, list(c.gates[src]["p"][:W.KIND_NPARAMS[kind]])))
+    return oracle.run(oracle.circuit_of(c.n_qubits, seq), psi)
+
+
+def test_commuting_checker_against_unitaries():
+    """Every order the checker accepts gives the same state as the input
+    order (all 120 orders of five-gate circuits, two random states), and on
+    each circuit some rejected order gives another state when the circuit
+    has a non-commuting pair."""
+    import itertools
+    for seed in range(12):
+        rng = np.random.default_rng(3000 + seed)
+        c = W.random_circuit(3, 5, rng, kinds=COMMUTE_KINDS)
+        gates, _ = oracle.canonicalize(c)
+        psis = [W.random_state(3, 7), W.random_state(3, 8)]
+        refs = [oracle.run(c, p) for p in psis]
+        differs = False
+        for perm in itertools.permutations(range(len(gates))):
+            outs = [_reordered_state(c, gates, perm, p) for p in psis]
+            same = all(np.allclose(o, r, atol=1e-12) for o, r in zip(outs, refs))
+            if KF.is_commuting_equivalent(gates, list(perm)):
+                assert same, (seed, perm)
+            elif not same:
+                differs = True
+        if not KF.is_commuting_equivalent(gates, list(range(len(gates)))[::-1]):
+            assert differs, seed
+
+
+def test_commuting_checker_on_small_cases():
+    """Shared qubits insular to both gates (diagonal gates, CX controls) let
+    the pair swap; a CX target or an H on the shared qubit does not."""
+    g = lambda k, qs, i: (k, tuple(qs), i)   # noqa: E731
+    assert KF.is_commuting_equivalent([g(W.CZ, [0, 1], 0), g(W.CP, [1, 2], 1)], [1, 0])
+    assert KF.is_commuting_equivalent([g(W.CX, [1, 2], 0), g(W.CZ, [1, 0], 1)], [1, 0])
+    assert KF.is_commuting_equivalent([g(W.CX, [1, 2], 0), g(W.CX, [1, 0], 1)], [1, 0])
+    assert not KF.is_commuting_equivalent([g(W.CX, [0, 1], 0), g(W.CZ, [1, 2], 1)], [1, 0])
+    assert not KF.is_commuting_equivalent([g(W.CZ, [0, 1], 0), g(W.H, [1], 1)], [1, 0])
+    assert not KF.is_commuting_equivalent([g(W.CZ, [0, 1], 0), g(W.X, [0], 1)], [1, 0])
+
+
+def test_commute_lift_merges_across_a_commuting_gate():
+    """CZ(0,1), CZ(1,2), CZ(0,1) with two-qubit fused kernels only: the plain
+    constraint cuts three kernels (the middle gate shares qubit 1); with the
+    lift the two outer gates form one kernel after the middle one.  A CX
+    whose target is qubit 1 keeps three kernels."""
+    opts = KOpts(k_max=2, allow_lds=False, insular=True)
+    tab = CostTables(fused=[0] + [10] * 7, alpha=0, gate=[0] * 7)
+    gates = [(W.CZ, (0, 1), 0), (W.CZ, (1, 2), 1), (W.CZ, (0, 1), 2)]
+    c0, k0 = KF.kernelize(gates, opts, tab)
+    c1, k1 = KF.kernelize(gates, opts, tab, KF.DPOpts(commute=True))
+    assert (c0, len(k0)) == (30, 3) and (c1, len(k1)) == (20, 2)
+    order = [g for _, gl, _ in k1 for g in gl]
+    assert order == [1, 0, 2] and KF.is_commuting_equivalent(gates, order)
+    assert not KF.is_topologically_equivalent(gates, order)
+    gates = [(W.CZ, (0, 1), 0), (W.CX, (2, 1), 1), (W.CZ, (0, 1), 2)]
+    c2, k2 = KF.kernelize(gates, opts, tab, KF.DPOpts(commute=True))
+    assert (c2, len(k2)) == (30, 3)
+
+
+def test_commute_lift_blocks_an_in_place_join_on_an_ignored_qubit():
+    """CZ(1,2), CZ(1,3), H(2), H(1) (qubits 1..3, k_max 2, kernels of one
+    or two qubits at one price): the literal lift would let H(1) join
+    {CZ(1,2)} in place after H(2) restricted it, ahead of CZ(1,3), with which
+    H(1) does not commute.  The recorded ignored set forbids that join, so
+    two-gate kernels can only pair H(1) with CZ(1,3)."""
+    opts = KOpts(k_max=2, allow_lds=False, insular=True)
+    tab = CostTables(fused=[0] + [10] * 7, alpha=0, gate=[0] * 7)
+    gates = [(W.CZ, (1, 2), 0), (W.CZ, (1, 3), 1), (W.H, (2,), 2), (W.H, (1,), 3)]
+    for dp in (KF.DPOpts(commute=True), KF.DPOpts(commute=True, subsume=True, fork_fused=True)):
+        c, ks = KF.kernelize(gates, opts, tab, dp)
+        order = [g for _, gl, _ in ks for g in gl]
+        assert KF.is_commuting_equivalent(gates, order), ks
+        for _, gl, _ in ks:
+            assert set(gl) != {0, 3}, ks
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_commute_lift_keeps_the_state(seed):
+    """Random circuits rich in diagonal gates and CX: with the lift (and the
+    appendix's other options on or off), every Kernelize order is commuting
+    equivalent, runs to the input's state, and (no pruning) never costs more
+    than without the lift on these cases."""
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(3, 6))
+    c = W.random_circuit(n, int(rng.integers(4, 9)), rng, kinds=COMMUTE_KINDS)
+    gates, _ = oracle.canonicalize(c)
+    opts = KOpts(k_max=int(rng.integers(1, 4)), m_max=int(rng.integers(2, 5)), ell=int(rng.integers(0, 2)),
+                 insular=True)
+    tab = _rand_tables(rng)
+    psi = W.random_state(n, seed)
+    ref = oracle.run(c, psi)
+    for extra in (dict(), dict(attach_1q=True, subsume=True, pack=True)):
+        c0, _ = KF.kernelize(gates, opts, tab, KF.DPOpts(**extra))
+        c1, ks = KF.kernelize(gates, opts, tab, KF.DPOpts(commute=True, **extra))
+        order = [g for _, gl, _ in ks for g in gl]
+        assert KF.is_commuting_equivalent(gates, order)
+        assert c1 == sum(cost for _, _, cost in ks) and c1 <= c0
+        for _, gl, cost in ks:
+            assert KF.kernel_cost(gates, gl, opts, tab)[0] <= cost
+        out = _reordered_state(c, gates, order, psi)
+        assert oracle.fidelity_loss(out, ref) < 1e-13 and np.max(np.abs(out - ref)) < 1e-12
+
+
+def _lift_case(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(3, 5))
+    m = int(rng.integers(3, 7))
+    c = W.random_circuit(n, m, rng, kinds=[W.H, W.X, W.U3, W.CX, W.CZ, W.CP, W.RZZ, W.RZ])
+    gates, _ = oracle.canonicalize(c)
+    opts = KOpts(k_max=int(rng.integers(1, 4)), m_max=int(rng.integers(2, 4)), ell=0, insular=True,
+                 allow_lds=bool(rng.integers(2)))
+    tab = CostTables(fused=[0] + sorted(int(x) for x in rng.integers(1, 100, 7)), alpha=int(rng.integers(0, 100)),
+                     gate=[int(x) for x in rng.integers(0, 26, oracle.NUM_CLASSES)])
+    return c, gates, opts, tab
+
+
+# Cases where a join in place that ignores the recorded set I produces an
+# order that is not commuting equivalent (found by searching this recipe with
+# that check removed from the oracle), then a plain range.
+@pytest.mark.parametrize("seed", [491, 1423, 2432, 2695, 5267] + list(range(200)))
+def test_commute_lift_ignored_set_cases(seed):
+    c, gates, opts, tab = _lift_case(seed)
+    try:
+        cost, ks = KF.kernelize(gates, opts, tab, KF.DPOpts(commute=True))
+    except ValueError:
+        return
+    order = [g for _, gl, _ in ks for g in gl]
+    assert KF.is_commuting_equivalent(gates, order), ks
+    psi = W.random_state(c.n_qubits, 1)
+    out = _reordered_state(c, gates, order, psi)
+    assert np.max(np.abs(out - oracle.run(c, psi))) < 1e-12
