@@ -64,6 +64,28 @@ def test_stage_plans_match_oracle(ctx, dtype):
         st.free()
 
 
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_stage_plans_with_the_commuting_lift(ctx, dtype):
+    """Stages over Kernelize plans whose order swaps gates sharing only
+    insular qubits (QK_DP_COMMUTE), on a circuit of diagonal gates, CX, H and
+    U3; L = 14 and 15."""
+    circ = W.random_circuit(18, 160, np.random.default_rng(57), kinds=[W.H, W.CX, W.CZ, W.CP, W.RZZ, W.RZ, W.U3])
+    psi = W.random_state(18, 13)
+    ref = oracle.run(circ, psi)
+    flags = qk.QK_DP_ATTACH_1Q | qk.QK_DP_SUBSUME | qk.QK_DP_PACK | qk.QK_DP_COMMUTE
+    for L in (14, 15):
+        for kz in (qk.QK_KERNELIZE_FULL, qk.QK_KERNELIZE_DP):
+            plan = qk.kernelize(ctx, circ, qk.kopts(dtype=dtype, local_qubits=L, kernelizer=kz, dp_flags=flags))
+            st = qk.sv_alloc(ctx, 18, dtype)
+            st.upload(psi.astype(st.np_dtype))
+            qk.execute_plan(ctx, plan, st)
+            out = st.download()
+            st.free()
+            loss = _check(out, ref, dtype, f"commute L={L} kernelizer={kz}")
+            print(f"commute dtype={dtype} L={L} kernelizer={kz}: {len(plan)} kernels in {plan.num_stages()} "
+                  f"stages, 1-F={loss:.3e}", flush=True)
+
+
 def test_stage_order_enforced(ctx):
     circ = W.random_layered(18, 4, 7)
     plan = qk.kernelize(ctx, circ, qk.kopts(dtype=qk.QK_C64, local_qubits=14))

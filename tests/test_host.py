@@ -391,6 +391,32 @@ def test_stage_mode_keeps_needs_local(seed, hctx):
     _expect(qk.QK_EINVAL, qk.kernelize, hctx, c, qk.kopts(dtype=qk.QK_C64, m_max=8, local_qubits=6))
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_stage_mode_with_the_commuting_lift(seed, hctx):
+    """Stages over Kernelize plans with the commuting lift: every gate's
+    non-insular qubits are local in its stage, and the plan's order is
+    equivalent to the input up to swaps of gates sharing only insular
+    qubits."""
+    rng = np.random.default_rng(4500 + seed)
+    n = int(rng.integers(12, 20))
+    L = int(rng.integers(9, n))
+    c = W.random_circuit(n, 90, rng, kinds=[W.H, W.X, W.U3, W.CX, W.CZ, W.CP, W.RZZ, W.RZ])
+    flags = qk.QK_DP_ATTACH_1Q | qk.QK_DP_SUBSUME | qk.QK_DP_PACK | qk.QK_DP_COMMUTE
+    for kz in (qk.QK_KERNELIZE_FULL, qk.QK_KERNELIZE_DP):
+        p = qk.kernelize(hctx, c, qk.kopts(dtype=qk.QK_C64, m_max=min(8, L), k_max=4, local_qubits=L,
+                                           kernelizer=kz, dp_flags=flags))
+        gates, _ = oracle.canonicalize(c, True)
+        by_src = {g[2]: t for t, g in enumerate(gates)}
+        assert KF.is_commuting_equivalent(gates, [by_src[p.gate_source(t)] for t in range(p.num_gates())])
+        virt = {g[2]: g[1] for g in gates}
+        kinds = {g[2]: g[0] for g in gates}
+        for k in p.kernels():
+            sig = p.stage_map(k.stage)
+            for t in range(k.gate_begin, k.gate_end):
+                src = p.gate_source(t)
+                assert all(sig[v] < L for v in oracle.need_qubits(kinds[src], virt[src], True)), (k.stage, src)
+
+
 # --------------------------------------------------------------- sanitizers
 _SAN_SOURCES = ("planner.cpp", "kernelize.cpp", "gates.cpp")
 
@@ -453,6 +479,7 @@ _SAN_OPTS = [  # dtype kernelizer insular fuse local k_max prune absorb dp_flags
     (0, 0, 1, 1, 12, 5, 500, 1, 7),  # invalid: local_qubits below m_max (13 for complex64)
     (0, 1, 1, 1, 0, 5, 500, 3, 7), (1, 0, 0, 0, 13, 4, 500, 2, 7),   # anti-diagonal carry
     (0, 1, 1, 1, 0, 5, 500, 1, 23), (1, 2, 1, 0, 0, 4, 64, 1, 16),   # commuting lift
+    (0, 1, 1, 1, 13, 5, 500, 1, 23),                                  # commuting lift with stages
 ]
 
 
