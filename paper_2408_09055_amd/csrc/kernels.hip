@@ -1960,11 +1960,19 @@ __global__ __launch_bounds__(kNT) void k_permute(const C* __restrict__ src, C* _
     }
 }
 
+// chunks of 16 bytes per thread in the in-place pass: tiles of at most
+// 2^11 complex128 or 2^12 complex64 amplitudes (checked at launch)
+constexpr int kPairChunks = 8;
+
 // In-place permutation pass for a bit permutation that is its own inverse
 // (the QFT's bit reversal): amplitude (T, i) -- tile T of the bits outside A,
 // local index i over A -- moves to (rho T, sigma i).  A workgroup takes the
 // tile pair {T, rho T} with base(T) <= base(rho T), stages both tiles in LDS
 // and writes each from the other: new_T[j] = old_{rho T}[sigma j].
+// 16-byte chunk q of a tile sits in LDS at q ^ ((q >> s) & (2^s - 1)), s the
+// chunk bits of the tile's low half: sigma sends the low half of the local
+// bits to the high half (bit reversal), so the reads of consecutive lanes,
+// a stride of 2^s chunks apart, land on distinct banks.
 template <typename C>
 __global__ __launch_bounds__(kNT) void k_permute_pairs(C* __restrict__ psi, PermPairDesc d)
 {
@@ -1986,9 +1994,12 @@ __global__ __launch_bounds__(kNT) void k_permute_pairs(C* __restrict__ psi, Perm
     }
     constexpr int CH = 16 / sizeof(C);
     const uint32_t nch = (1u << m) / CH;
+    const int sw = nlo - (CH == 2 ? 1 : 0);
+    const uint32_t swm = (1u << sw) - 1u;
+    auto swz = [&](uint32_t q) { return q ^ ((q >> sw) & swm); };
     const uint64_t off_t = deposit((uint32_t)tid * CH, d.act, m);
-    uint64_t off_i[kMaxChunks];
-    static_for<0, kMaxChunks>([&](auto I) { off_i[I.value] = deposit((uint32_t)I.value * kNT * CH, d.act, m); });
+    uint64_t off_i[kPairChunks];
+    static_for<0, kPairChunks>([&](auto I) { off_i[I.value] = deposit((uint32_t)I.value * kNT * CH, d.act, m); });
     auto image = [&](uint64_t b) {
         uint64_t r = 0;
         static_for<0, 40>([&](auto B) {
@@ -1996,23 +2007,11 @@ __global__ __launch_bounds__(kNT) void k_permute_pairs(C* __restrict__ psi, Perm
         });
         return r;
     };
-    __syncthreads();
-    for (uint64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x) {
-        const uint64_t bt = block_base(t, d.act, m);
-        const uint64_t bp = image(bt);
-        if (bp < bt) continue;   // the partner tile's workgroup moves this pair
+    // new tile T takes the partner's amplitudes: LDS (swizzled) -> HBM
+    auto write_pair = [&](uint64_t bt, uint64_t bp) {
         const bool same = bp == bt;
-        static_for<0, kMaxChunks>([&](auto I) {
-            const uint32_t c = tid + (uint32_t)I.value * kNT;
-            if (c < nch) {
-                *reinterpret_cast<u32x4*>(&sa[c * CH]) = *reinterpret_cast<const u32x4*>(&psi[bt + off_t + off_i[I.value]]);
-                if (!same)
-                    *reinterpret_cast<u32x4*>(&sb[c * CH]) = *reinterpret_cast<const u32x4*>(&psi[bp + off_t + off_i[I.value]]);
-            }
-        });
-        __syncthreads();
-        const C* from_t = same ? sa : sb;   // new tile T takes the partner's amplitudes
-        static_for<0, kMaxChunks>([&](auto I) {
+        const C* from_t = same ? sa : sb;
+        static_for<0, kPairChunks>([&](auto I) {
             const uint32_t c = tid + (uint32_t)I.value * kNT;
             if (c < nch) {
                 union { C v[CH]; u32x4 w; } ut, up;
@@ -2020,14 +2019,86 @@ __global__ __launch_bounds__(kNT) void k_permute_pairs(C* __restrict__ psi, Perm
                 for (int e = 0; e < CH; ++e) {
                     const uint32_t j = c * CH + e;
                     const uint32_t sj = rlo[j & ((1u << nlo) - 1u)] | rhi[j >> nlo];
-                    ut.v[e] = from_t[sj];
-                    up.v[e] = sa[sj];
+                    const uint32_t at = swz(sj / CH) * CH + sj % CH;
+                    ut.v[e] = from_t[at];
+                    up.v[e] = sa[at];
                 }
-                *reinterpret_cast<u32x4*>(&psi[bt + off_t + off_i[I.value]]) = ut.w;
-                if (!same) *reinterpret_cast<u32x4*>(&psi[bp + off_t + off_i[I.value]]) = up.w;
+                __builtin_nontemporal_store(ut.w, reinterpret_cast<u32x4*>(&psi[bt + off_t + off_i[I.value]]));
+                if (!same) __builtin_nontemporal_store(up.w, reinterpret_cast<u32x4*>(&psi[bp + off_t + off_i[I.value]]));
             }
         });
-        __syncthreads();
+    };
+    __syncthreads();
+    if constexpr (sizeof(C) == 16) {
+        // complex128: a pair takes 32 KiB of LDS, so several workgroups per
+        // CU overlap one another's loads and stores; loads go straight to LDS
+        for (uint64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x) {
+            const uint64_t bt = block_base(t, d.act, m);
+            const uint64_t bp = image(bt);
+            if (bp < bt) continue;   // the partner tile's workgroup moves this pair
+            static_for<0, kPairChunks>([&](auto I) {
+                const uint32_t c = tid + (uint32_t)I.value * kNT;
+                if (c < nch) {
+                    const uint32_t q = swz(c) * CH;
+                    *reinterpret_cast<u32x4*>(&sa[q]) =
+                        __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(&psi[bt + off_t + off_i[I.value]]));
+                    if (bp != bt)
+                        *reinterpret_cast<u32x4*>(&sb[q]) =
+                            __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(&psi[bp + off_t + off_i[I.value]]));
+                }
+            });
+            __syncthreads();
+            write_pair(bt, bp);
+            __syncthreads();
+        }
+    } else {
+        // complex64: a pair takes 64 KiB of LDS (two workgroups per CU), so
+        // each workgroup loads the next pair into registers while it writes
+        // the current one; pairs partition the tiles, so the next pair never
+        // overlaps the one in flight
+        auto lead = [&](uint64_t t) {   // first tile at or after t that leads its pair
+            for (; t < d.ntiles; t += gridDim.x) {
+                const uint64_t b = block_base(t, d.act, m);
+                if (image(b) >= b) break;
+            }
+            return t;
+        };
+        uint64_t t = lead(blockIdx.x);
+        if (t >= d.ntiles) return;
+        u32x4 bufa[kPairChunks], bufb[kPairChunks];
+        auto load_pair = [&](uint64_t bt, uint64_t bp) {
+            static_for<0, kPairChunks>([&](auto I) {
+                const uint32_t c = tid + (uint32_t)I.value * kNT;
+                if (c < nch) {
+                    bufa[I.value] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(&psi[bt + off_t + off_i[I.value]]));
+                    if (bp != bt)
+                        bufb[I.value] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(&psi[bp + off_t + off_i[I.value]]));
+                }
+            });
+        };
+        uint64_t bt = block_base(t, d.act, m), bp = image(bt);
+        load_pair(bt, bp);
+        for (;;) {
+            static_for<0, kPairChunks>([&](auto I) {
+                const uint32_t c = tid + (uint32_t)I.value * kNT;
+                if (c < nch) {
+                    const uint32_t q = swz(c) * CH;
+                    *reinterpret_cast<u32x4*>(&sa[q]) = bufa[I.value];
+                    if (bp != bt) *reinterpret_cast<u32x4*>(&sb[q]) = bufb[I.value];
+                }
+            });
+            __syncthreads();
+            const uint64_t tn = lead(t + gridDim.x);
+            const uint64_t btn = tn < d.ntiles ? block_base(tn, d.act, m) : 0;
+            const uint64_t bpn = tn < d.ntiles ? image(btn) : 0;
+            if (tn < d.ntiles) load_pair(btn, bpn);
+            write_pair(bt, bp);
+            if (tn >= d.ntiles) break;
+            t = tn;
+            bt = btn;
+            bp = bpn;
+            __syncthreads();
+        }
     }
 }
 
@@ -2378,6 +2449,8 @@ int launch_block_rb(int dtype, void* psi, const RbDesc& d, const void* prog, voi
 int launch_permute_pairs(int dtype, void* psi, const PermPairDesc& d, void* stream)
 {
     const size_t lds = (size_t)(dtype == QK_C128 ? 32 : 16) << d.m;   // two tiles
+    const uint64_t nch = (1ull << d.m) / (dtype == QK_C128 ? 1 : 2);
+    if (d.m < 4 || nch > (uint64_t)kPairChunks * kNT) return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;
     const void* f = dtype == QK_C128 ? reinterpret_cast<const void*>(k_permute_pairs<double2>)
                                      : reinterpret_cast<const void*>(k_permute_pairs<float2>);
