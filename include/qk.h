@@ -421,6 +421,20 @@ int plan_kernel_features(const qk_plan* p, int64_t i, float* out);
  * contents are changed (the kernel is applied reps + 1 times). */
 int time_kernel(qk_ctx* ctx, const qk_plan* p, int64_t i, qk_state* st, int reps, double* median_ms);
 
+/* Training rows for the learned model, which prices one kernel (section "Cost
+ * Function in Kernelize"): candidate i (a host circuit on n_i <= st's qubit
+ * count) becomes one kernel of type types[i] as kernelize_single makes it,
+ * is timed as time_kernel times it on the first 2^n_i amplitudes of st
+ * (viewed as an n_i-qubit state), and fills row i: feats[i * QK_NUM_FEATURES
+ * ..] = its features, log_ps[i] = log(median picoseconds per amplitude),
+ * ms[i] = median milliseconds (ms may be NULL).  ko NULL = defaults with
+ * st's dtype and k_max 7; otherwise its dtype must be st's.  The state's
+ * contents change.  On an error (an infeasible candidate: QK_EINVAL) the
+ * rows before the failing candidate are filled and *done (may be NULL)
+ * counts them.  Needs a device context (QK_EDEVICE otherwise). */
+int costmodel_collect(qk_ctx* ctx, qk_state* st, const qk_circuit* cands, const int32_t* types, int64_t count,
+                      const qk_kopts* ko, int reps, float* feats, float* log_ps, double* ms, int64_t* done);
+
 /* Learned model: MLP with QK_NUM_FEATURES inputs, two hidden ReLU layers of 64
  * and one output, FP32, predicting log(picoseconds per amplitude); trained
  * on the device by libqk's own forward, backward and Adam kernels. */

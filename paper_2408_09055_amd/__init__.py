@@ -142,6 +142,8 @@ _SIGS = {
     "kernelize_single": [_P, ctypes.POINTER(qk_circuit), ctypes.POINTER(qk_kopts), ctypes.c_int, _PP],
     "plan_kernel_features": [_P, _i64, _P],
     "time_kernel": [_P, _P, _i64, _P, ctypes.c_int, _dbl_p],
+    "costmodel_collect": [_P, _P, _P, _P, _i64, ctypes.POINTER(qk_kopts), ctypes.c_int, _P, _P, _P,
+                          ctypes.POINTER(_i64)],
     "costmodel_train": [_P, ctypes.c_int, _P, _P, _i64, ctypes.POINTER(qk_train_opts), ctypes.POINTER(qk_train_report)],
     "costmodel_save": [_P, ctypes.c_int, ctypes.c_char_p], "costmodel_load": [_P, ctypes.c_int, ctypes.c_char_p],
     "costmodel_unload": [_P, ctypes.c_int], "costmodel_loaded": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
@@ -587,6 +589,26 @@ def time_kernel(ctx: Context, plan: Plan, i: int, state: State, reps: int = 3) -
     v = ctypes.c_double()
     _check(_lib.time_kernel(ctx.h, plan.h, i, state.h, reps, ctypes.byref(v)))
     return v.value
+
+
+def costmodel_collect(ctx: Context, state: State, circuits, types, ko: qk_kopts | None = None, reps: int = 3):
+    """Times each candidate circuit as one kernel of its type on a view of
+    `state` (libqk's costmodel_collect).  Returns (features, log ps per
+    amplitude, ms) as arrays of len(circuits) rows."""
+    cnt = len(circuits)
+    assert len(types) == cnt
+    feats = np.zeros((cnt, NUM_FEATURES), np.float32)
+    log_ps = np.zeros(cnt, np.float32)
+    ms = np.zeros(cnt, np.float64)
+    if cnt == 0:
+        return feats, log_ps, ms
+    cstructs, keep = _circuit_array(circuits)
+    ty = np.ascontiguousarray(types, np.int32)
+    done = _i64()
+    _check(_lib.costmodel_collect(ctx.h, state.h, cstructs, ty.ctypes.data, cnt,
+                                  ctypes.byref(ko) if ko is not None else None, reps, feats.ctypes.data,
+                                  log_ps.ctypes.data, ms.ctypes.data, ctypes.byref(done)))
+    return feats, log_ps, ms
 
 
 def mlp_num_params() -> int:

@@ -1,9 +1,10 @@
 """Training data collection and training of the learned kernel cost model.
 
-The simulator times candidate kernels itself: each sample is one kernel
-(``kernelize_single``) on an n-qubit state, timed with HIP events
-(``time_kernel``), described by the library's own feature vector
-(``Plan.features``) and labelled with log(picoseconds per amplitude).  The
+The simulator times candidate kernels itself (``costmodel_collect`` in libqk):
+each sample is one kernel (as ``kernelize_single`` makes it) on an n-qubit
+view of one large state, timed with HIP events (as ``time_kernel``),
+described by the library's own feature vector and labelled with
+log(picoseconds per amplitude).  This module draws the candidates.  The
 network is then trained on the device by libqk (``Context.train_costmodel``).
 
 Sample distribution (n uniform on [24, 32]):
@@ -22,7 +23,6 @@ Usage:  python -m paper_2408_09055_amd.costmodel --dtype c64 --count 10000
 from __future__ import annotations
 
 import argparse
-import ctypes
 import math
 import os
 import sys
@@ -30,8 +30,8 @@ import time
 
 import numpy as np
 
-from . import (NUM_FEATURES, QK_C64, QK_C128, QK_KERNEL_FUSED, QK_KERNEL_LDS, QK_KERNELIZE_DP, Context, QkError, State,
-               costmodel_path, kernelize, kernelize_single, kopts, lib, time_kernel)
+from . import (NUM_FEATURES, QK_C64, QK_C128, QK_KERNEL_FUSED, QK_KERNEL_LDS, QK_KERNELIZE_DP, Context, State,
+               costmodel_collect, costmodel_path, kernelize, kopts)
 
 _ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if _ROOT not in sys.path:
@@ -166,37 +166,35 @@ def sample_kernels(count, dtype, seed, n_lo=24, n_hi=32, k_max=7):
 
 
 def collect(ctx: Context, dtype: int, count: int, seed: int, reps: int = 3, n_lo=24, n_hi=32, log=print,
-            budget_s: float | None = None):
-    """Times `count` sampled kernels (fewer if `budget_s` seconds run out
-    first); returns (features, log ps/amplitude, ms, n)."""
+            budget_s: float | None = None, chunk: int = 250):
+    """Times `count` sampled kernels with libqk's costmodel_collect, `chunk`
+    candidates per call (fewer kernels if `budget_s` seconds run out first);
+    returns (features, log ps/amplitude, ms, n)."""
     big = State.alloc(ctx, n_hi, dtype)
     big.init_basis(0)
-    ptr = big.device_ptr()
-    views = {}
-    for n in range(n_lo, n_hi + 1):
-        h = ctypes.c_void_p()
-        rc = lib().sv_wrap(ctx.h, ctypes.c_void_p(ptr), n, dtype, ctypes.byref(h))
-        if rc != 0:
-            raise QkError(rc, lib().qk_last_error().decode())
-        views[n] = State(ctx, h, n, dtype)
     feats, targets, times, ns = [], [], [], []
     t0 = time.time()
     ko = kopts(dtype=dtype, k_max=7)
+    pending = []
+
+    def flush():
+        f, lp, ms = costmodel_collect(ctx, big, [c for _, c, _ in pending], [t for _, _, t in pending], ko, reps)
+        feats.extend(f)
+        targets.extend(lp)
+        times.extend(ms)
+        ns.extend(n for n, _, _ in pending)
+        pending.clear()
+
     for i, (n, c, ktype) in enumerate(sample_kernels(count, dtype, seed, n_lo, n_hi)):
-        plan = kernelize_single(ctx, c, ko, ktype)
-        ms = time_kernel(ctx, plan, 0, views[n], reps)
-        feats.append(plan.features(0))
-        plan.free()
-        targets.append(math.log(ms * 1e9 / float(1 << n)))
-        times.append(ms)
-        ns.append(n)
-        if (i + 1) % 500 == 0:
+        pending.append((n, c, ktype))
+        if len(pending) == chunk:
+            flush()
             log(f"collected {i + 1}/{count} kernels in {time.time() - t0:.1f} s", flush=True)
-        if budget_s is not None and time.time() - t0 > budget_s:
-            log(f"time budget reached after {i + 1} kernels", flush=True)
-            break
-    for v in views.values():
-        v.free()
+            if budget_s is not None and time.time() - t0 > budget_s:
+                log(f"time budget reached after {i + 1} kernels", flush=True)
+                break
+    if pending:
+        flush()
     big.free()
     return (np.array(feats, np.float32), np.array(targets, np.float32), np.array(times), np.array(ns))
 

@@ -261,6 +261,52 @@ int time_kernel(qk_ctx* ctx, const qk_plan* p, int64_t i, qk_state* st, int reps
     return time_launch(ctx, p, i, st, reps, median_ms, -1);
 }
 
+int costmodel_collect(qk_ctx* ctx, qk_state* st, const qk_circuit* cands, const int32_t* types, int64_t count,
+                      const qk_kopts* ko, int reps, float* feats, float* log_ps, double* ms, int64_t* done)
+{
+    if (done) *done = 0;
+    if (!ctx || ctx->host_only) return fail(QK_EDEVICE, "costmodel_collect: needs a device context");
+    if (!st || (count > 0 && (!cands || !types || !feats || !log_ps)) || count < 0)
+        return fail(QK_EINVAL, "costmodel_collect: null argument or negative count");
+    if (st->host) return fail(QK_EINVAL, "costmodel_collect: the state must be in device memory");
+    if (reps < 1 || reps > 1000) return fail(QK_EINVAL, "costmodel_collect: reps must be 1..1000");
+    qk_kopts k;
+    if (ko) {
+        k = *ko;
+        if (k.dtype != st->dtype) return fail(QK_EINVAL, "costmodel_collect: kopts dtype differs from the state's");
+    } else {
+        qk_kopts_default(&k);
+        k.dtype = st->dtype;
+        k.k_max = kMaxFusedQubits;
+    }
+    // the first 2^n amplitudes of st, viewed as an n-qubit state (one view per n)
+    std::vector<qk_state*> views((size_t)kMaxQubits + 1, nullptr);
+    int rc = QK_OK;
+    int64_t i = 0;
+    for (; i < count; ++i) {
+        const int n = cands[i].n_qubits;
+        if (n < 1 || n > st->n) {
+            rc = fail(QK_EINVAL, "costmodel_collect: candidate " + std::to_string(i) + " has " + std::to_string(n) +
+                                     " qubits, the state " + std::to_string(st->n));
+            break;
+        }
+        if (!views[n] && (rc = sv_wrap(ctx, st->psi, n, st->dtype, &views[n])) != QK_OK) break;
+        qk_plan* P = nullptr;
+        if ((rc = kernelize_single(ctx, &cands[i], &k, types[i], &P)) != QK_OK) break;
+        double t = 0.0;
+        rc = time_kernel(ctx, P, 0, views[n], reps, &t);
+        if (rc == QK_OK) rc = plan_kernel_features(P, 0, feats + i * QK_NUM_FEATURES);
+        plan_free(P);
+        if (rc) break;
+        log_ps[i] = (float)std::log(t * 1e9 / (double)(1ull << n));
+        if (ms) ms[i] = t;
+    }
+    for (qk_state* v : views)
+        if (v) sv_free(v);
+    if (done) *done = i;
+    return rc;
+}
+
 int costmodel_calibrate(qk_ctx* ctx, int n, int dtype, int reps, qk_cost_tables* out)
 {
     if (!ctx || ctx->host_only) return fail(QK_EDEVICE, "costmodel_calibrate: needs a device context");

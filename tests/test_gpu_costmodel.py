@@ -266,3 +266,44 @@ def test_shipped_models_record_their_training_range(ctx, dtype):
         assert plan.cost_model()["learned_fallback"] == (not inside), n
         plan.free()
     ctx.unload_costmodel(dtype)
+
+
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_native_collection_matches_single_kernel_timing(ctx, dtype):
+    """costmodel_collect (the training-row loop in libqk) on candidates of
+    16..20 qubits over views of one 20-qubit state: each row's features
+    equal those of the same kernel built by kernelize_single, its log ps per
+    amplitude agrees with time_kernel's median for that kernel within a
+    factor of 3 (timing noise on small states), and an infeasible candidate
+    stops the call with QK_EINVAL after the rows before it."""
+    from paper_2408_09055_amd import costmodel as CM
+    cands = list(CM.sample_kernels(24, dtype, seed=5, n_lo=16, n_hi=20))
+    circs = [c for _, c, _ in cands]
+    types = [t for _, _, t in cands]
+    ko = qk.kopts(dtype=dtype, k_max=7)
+    big = qk.sv_alloc(ctx, 20, dtype)
+    big.init_basis(0)
+    feats, log_ps, ms = qk.costmodel_collect(ctx, big, circs, types, ko, reps=3)
+    assert np.all(ms > 0) and np.all(np.isfinite(log_ps))
+    for i, (n, c, t) in enumerate(cands):
+        plan = qk.kernelize_single(ctx, c, ko, t)
+        assert np.array_equal(feats[i], plan.features(0)), i
+        view = qk.sv_alloc(ctx, n, dtype)
+        view.init_basis(0)
+        ref = qk.time_kernel(ctx, plan, 0, view, 3)
+        view.free()
+        plan.free()
+        assert abs(log_ps[i] - math.log(ref * 1e9 / 2 ** n)) < math.log(3.0), (i, ms[i], ref)
+    # a fused candidate on 8 qubits is infeasible (k_max 7): rows before it are filled
+    bad = W.from_list(18, [W.gate(W.CX, [q, q + 1]) for q in range(7)])
+    with pytest.raises(qk.QkError) as ei:
+        qk.costmodel_collect(ctx, big, circs[:3] + [bad], types[:3] + [qk.QK_KERNEL_FUSED], ko)
+    assert ei.value.code == qk.QK_EINVAL
+    # a candidate wider than the state, and kopts of another dtype, are refused
+    with pytest.raises(qk.QkError) as ei:
+        qk.costmodel_collect(ctx, big, [W.ghz(21)], [qk.QK_KERNEL_LDS], ko)
+    assert ei.value.code == qk.QK_EINVAL
+    with pytest.raises(qk.QkError) as ei:
+        qk.costmodel_collect(ctx, big, circs[:1], types[:1], qk.kopts(dtype=1 - dtype))
+    assert ei.value.code == qk.QK_EINVAL
+    big.free()

@@ -156,6 +156,9 @@ def _expect(code, fn, *a):
 
 
 def test_error_paths(hctx):
+    # training-row collection needs a device context
+    rc = qk._lib.costmodel_collect(hctx.h, None, None, None, 0, None, 3, None, None, None, None)
+    assert rc == qk.QK_EDEVICE
     bad_q = W.from_list(4, [W.gate(W.H, [4])])
     _expect(qk.QK_EINVAL, qk.kernelize, hctx, bad_q, qk.kopts())
     rep = W.from_list(4, [W.gate(W.CX, [1, 1])])
