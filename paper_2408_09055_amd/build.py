@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "planner.cpp", "kernelize.cpp", "offload.cpp", "gates.cpp", "costmodel.cpp", "batch.cpp", "kernels.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "planner.cpp", "kernelize.cpp", "offload.cpp", "host_perm.cpp", "gates.cpp", "costmodel.cpp", "batch.cpp", "kernels.hip", "mlp.hip"]
 
 # Packed FP32 instructions are disabled for all device code.  Common-code
 # sinking is disabled because it merges the per-bit variants of register

@@ -12,9 +12,10 @@
 // ones.  Every chunk of a stage then runs an ordinary L-qubit plan: copied to
 // the device, its kernels applied, copied back, with two device buffers on
 // two streams so that copies overlap kernels.  Between stages the host
-// exchanges the bit pairs of the stage change in place (threads over index
-// ranges); at the end the state is put in logical order the same way (two
-// such passes when the final map is not its own inverse).
+// exchanges the bit pairs of the stage change in place (host_exchange: tile
+// pairs gathered into cache on several threads); at the end the state is put
+// in logical order the same way (two such passes when the final map is not
+// its own inverse).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +24,7 @@
 #include <cstring>
 #include <thread>
 
+#include "host_perm.hpp"
 #include "plan.hpp"
 
 namespace qk {
@@ -35,95 +37,7 @@ namespace {
 
 size_t amp_bytes(int dtype) { return dtype == QK_C128 ? 16 : 8; }
 
-// In place on host memory: amplitude i moves to index pi(i), pi = the bit
-// map perm (bit b -> bit perm[b]), which must be its own inverse.  As in the
-// device's in-place pass, the index splits into tile bits A (the lowest bits
-// with their images, closed under perm, at most kHostTileBits) and the rest:
-// amplitude (T, j) moves to (rho T, sigma j).  A thread takes the tile pair
-// {T, rho T} with base(T) <= base(rho T), gathers both tiles (runs of 2^r
-// contiguous amplitudes, r = the contiguous low bits of A) into buffers that
-// stay in cache, and writes each from the other permuted by sigma.  Tile
-// pairs are disjoint, so threads never touch the same amplitudes.
-constexpr int kHostTileBits = 14;
-
-void host_exchange(void* psi, int n, int dtype, const std::vector<int32_t>& perm)
-{
-    bool moved = false;
-    for (int b = 0; b < n; ++b) moved |= perm[b] != b;
-    if (!moved) return;
-    uint64_t A = 0;
-    for (int q = 0; q < n; ++q) {
-        if ((A >> q) & 1) continue;
-        const uint64_t add = (1ull << q) | (1ull << perm[q]);
-        if (__builtin_popcountll(A | add) > kHostTileBits) break;
-        A |= add;
-    }
-    int act[64], out[64], m = 0, no = 0, r = 0;
-    for (int q = 0; q < n; ++q) {
-        if ((A >> q) & 1) act[m++] = q;
-        else out[no++] = q;
-    }
-    while (r < m && act[r] == r) ++r;
-    // sigma on tile-local indices, and each local index's amplitude offset
-    int loc[64];
-    for (int t = 0; t < m; ++t) loc[act[t]] = t;
-    const uint32_t tsz = 1u << m;
-    std::vector<uint32_t> sig(tsz);
-    std::vector<uint64_t> off(tsz >> r);
-    for (uint32_t j = 0; j < tsz; ++j) {
-        uint32_t v = 0;
-        for (int t = 0; t < m; ++t)
-            if ((j >> t) & 1u) v |= 1u << loc[perm[act[t]]];
-        sig[j] = v;
-    }
-    for (uint32_t h = 0; h < (tsz >> r); ++h) {
-        uint64_t o = 0;
-        for (int t = r; t < m; ++t)
-            if (((uint64_t)h << r >> t) & 1u) o |= 1ull << act[t];
-        off[h] = o;
-    }
-    const size_t s = amp_bytes(dtype), run = (size_t)s << r;
-    const uint64_t ntiles = 1ull << no;
-    auto base = [&](uint64_t T) {
-        uint64_t b = 0;
-        for (int k = 0; k < no; ++k)
-            if ((T >> k) & 1ull) b |= 1ull << out[k];
-        return b;
-    };
-    auto image = [&](uint64_t i) {
-        uint64_t v = 0;
-        for (int b = 0; b < n; ++b) v |= ((i >> b) & 1ull) << perm[b];
-        return v;
-    };
-    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nt; ++t) {
-        th.emplace_back([&, t]() {
-            std::vector<char> ta((size_t)s << m), tb((size_t)s << m), w((size_t)s << m);
-            char* P = (char*)psi;
-            auto gather = [&](uint64_t bt, char* buf) {
-                for (uint32_t h = 0; h < (tsz >> r); ++h) std::memcpy(buf + h * run, P + (bt + off[h]) * s, run);
-            };
-            auto scatter = [&](uint64_t bt, const char* src) {   // tile bt <- src permuted by sigma
-                for (uint32_t j = 0; j < tsz; ++j) std::memcpy(w.data() + (size_t)j * s, src + (size_t)sig[j] * s, s);
-                for (uint32_t h = 0; h < (tsz >> r); ++h) std::memcpy(P + (bt + off[h]) * s, w.data() + h * run, run);
-            };
-            for (uint64_t T = t; T < ntiles; T += nt) {
-                const uint64_t bt = base(T), bp = image(bt);
-                if (bp < bt) continue;
-                gather(bt, ta.data());
-                if (bp == bt) {
-                    scatter(bt, ta.data());
-                    continue;
-                }
-                gather(bp, tb.data());
-                scatter(bt, tb.data());
-                scatter(bp, ta.data());
-            }
-        });
-    }
-    for (auto& x : th) x.join();
-}
+unsigned host_threads() { return std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
 
 bool involution(const std::vector<int32_t>& p)
 {
@@ -139,7 +53,7 @@ void host_relayout(qk_state* hs, const std::vector<int32_t>& have, const std::ve
     std::vector<int32_t> p(n);
     for (int v = 0; v < n; ++v) p[have[v]] = want[v];
     if (involution(p)) {
-        host_exchange(hs->psi, n, hs->dtype, p);
+        host_exchange(hs->psi, n, amp_bytes(hs->dtype), p, host_threads());
         return;
     }
     // a permutation is the product of two involutions: per cycle, the
@@ -156,8 +70,8 @@ void host_relayout(qk_state* hs, const std::vector<int32_t>& have, const std::ve
             r2[cyc[j]] = cyc[(L + 1 - j) % L];
         }
     }
-    host_exchange(hs->psi, n, hs->dtype, r1);
-    host_exchange(hs->psi, n, hs->dtype, r2);
+    host_exchange(hs->psi, n, amp_bytes(hs->dtype), r1, host_threads());
+    host_exchange(hs->psi, n, amp_bytes(hs->dtype), r2, host_threads());
 }
 
 qk_gate make_gate(uint32_t kind, int a, int b, double p0)

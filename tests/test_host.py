@@ -444,6 +444,28 @@ def planner_san(tmp_path_factory):
     return str(out)
 
 
+def test_host_permutation_under_sanitizers(tmp_path):
+    """The offload's in-place host permutation (csrc/host_perm.cpp), built
+    with AddressSanitizer and UndefinedBehaviorSanitizer: random involutions
+    of the index bits on 4..18-qubit states of both amplitude sizes, with one
+    and several threads, equal the per-amplitude definition."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ is not available")
+    exe = tmp_path / "host_perm_check"
+    csrc = os.path.join(ROOT, "paper_2408_09055_amd", "csrc")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-pthread", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", os.path.join(ROOT, "tests", "native", "host_perm_check.cpp"),
+           os.path.join(csrc, "host_perm.cpp"), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-4000:]
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    assert "240 cases, 0 mismatches" in r.stdout
+
+
 def _san_circuits():
     rng = np.random.default_rng(97)
     circs = [W.qft(14), W.random_layered(16, 6, 3), W.ghz(13), W.random_circuit(15, 140, rng),
