@@ -274,7 +274,7 @@ def test_native_collection_matches_single_kernel_timing(ctx, dtype):
     16..20 qubits over views of one 20-qubit state: each row's features
     equal those of the same kernel built by kernelize_single, its log ps per
     amplitude agrees with time_kernel's median for that kernel within a
-    factor of 3 (timing noise on small states), and an infeasible candidate
+    factor of 1.5 (measured: within 11%), and an infeasible candidate
     stops the call with QK_EINVAL after the rows before it."""
     from paper_2408_09055_amd import costmodel as CM
     cands = list(CM.sample_kernels(24, dtype, seed=5, n_lo=16, n_hi=20))
@@ -293,7 +293,7 @@ def test_native_collection_matches_single_kernel_timing(ctx, dtype):
         ref = qk.time_kernel(ctx, plan, 0, view, 3)
         view.free()
         plan.free()
-        assert abs(log_ps[i] - math.log(ref * 1e9 / 2 ** n)) < math.log(3.0), (i, ms[i], ref)
+        assert abs(log_ps[i] - math.log(ref * 1e9 / 2 ** n)) < math.log(1.5), (i, ms[i], ref)
     # a fused candidate on 8 qubits is infeasible (k_max 7): rows before it are filled
     bad = W.from_list(18, [W.gate(W.CX, [q, q + 1]) for q in range(7)])
     with pytest.raises(qk.QkError) as ei:
