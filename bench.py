@@ -294,14 +294,10 @@ def dominant_kernel(r, pass_bytes):
     return dom, kms, by_impl
 
 
-def batch_sweep(qk, ctx, reps: int = 3) -> dict:
-    """The batched-sweep workload: 256 hardware-efficient ansatz circuits
-    (seed 4, n uniform in [10, 22], depth in [4, 12]), complex64 from |0...0>,
-    dealt over the library's HIP streams (plans built before the timed
-    events).  Median of `reps` runs after one warm-up."""
+def _sweep_once(qk, ctx, circs, reps, tuned):
+    """Median (total, p50, p99) ms of `reps` batch runs after one warm-up, the
+    largest norm error, and the HBM bytes of the plans' passes."""
     import numpy as np
-    import workloads as W
-    circs = W.hea_batch(256, seed=4)
     states = [qk.sv_alloc(ctx, c.n_qubits, qk.QK_C64) for c in circs]
     runs = []
     for r in range(reps + 1):
@@ -313,20 +309,41 @@ def batch_sweep(qk, ctx, reps: int = 3) -> dict:
     norm_err = max(abs(st.norm2() - 1.0) for st in states)
     for st in states:
         st.free()
-    hctx = qk.Context(host_only=True)
     passes_bytes = 0
     for c in circs:
-        plan = qk.kernelize(hctx, c, qk.kopts(dtype=qk.QK_C64))
+        ko = qk.get_tuned(ctx, qk.QK_C64, c.n_qubits)[0] if tuned else qk.kopts(dtype=qk.QK_C64)
+        plan = qk.kernelize(ctx, c, ko)
         restore = 0 if list(plan.final_layout()) == list(range(c.n_qubits)) else 1
         passes_bytes += (len(plan.kernels()) + restore) * 2 * (1 << c.n_qubits) * 8
-    hctx.close()
+        plan.free()
     runs.sort()
     total, p50, p99 = runs[len(runs) // 2]
-    return {"workload": "256 ansatz circuits (seed 4, n 10..22, depth 4..12), complex64", "reps": reps,
-            "total_ms": round(total, 3), "circuits_per_s": round(256 / (total * 1e-3), 1),
+    return {"total_ms": round(total, 3), "circuits_per_s": round(len(circs) / (total * 1e-3), 1),
             "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
-            "aggregate_gbps": round(passes_bytes / (total * 1e-3) / 1e9, 1),
-            "state_bytes": int(sum((1 << c.n_qubits) * 8 for c in circs)), "max_norm2_error": norm_err}
+            "aggregate_gbps": round(passes_bytes / (total * 1e-3) / 1e9, 1), "max_norm2_error": norm_err}
+
+
+def batch_sweep(qk, ctx, reps: int = 3) -> dict:
+    """The batched-sweep workload: 256 hardware-efficient ansatz circuits
+    (seed 4, n uniform in [10, 22], depth in [4, 12]), complex64 from |0...0>,
+    dealt over the library's HIP streams (plans built before the timed
+    events).  Median of `reps` runs after one warm-up, first with the
+    default options, then with the options of the shipped autotuner cache
+    (per qubit count: k_max, block qubits, ell)."""
+    import os
+    import workloads as W
+    circs = W.hea_batch(256, seed=4)
+    out = {"workload": "256 ansatz circuits (seed 4, n 10..22, depth 4..12), complex64", "reps": reps,
+           "state_bytes": int(sum((1 << c.n_qubits) * 8 for c in circs))}
+    out.update(_sweep_once(qk, ctx, circs, reps, tuned=False))
+    path = qk.autotune_path(qk.QK_C64)
+    if os.path.exists(path):
+        qk.autotune_load(ctx, qk.QK_C64, path)
+        tuned = _sweep_once(qk, ctx, circs, reps, tuned=True)
+        tuned["cache"] = os.path.relpath(path, os.path.dirname(os.path.abspath(__file__)))
+        tuned["speedup_vs_default"] = round(out["total_ms"] / tuned["total_ms"], 3)
+        out["autotuned"] = tuned
+    return out
 
 
 KERNELIZERS = {"ordered": 0, "full": 1}

@@ -105,6 +105,11 @@ def costmodel_path(dtype: int) -> str:
     return os.path.join(DATA_DIR, f"costmodel_gfx950_{'c64' if dtype == 0 else 'c128'}.txt")
 
 
+def autotune_path(dtype: int) -> str:
+    """Default location of the shipped autotuner cache for a dtype."""
+    return os.path.join(DATA_DIR, f"autotune_gfx950_{'c64' if dtype == 0 else 'c128'}.txt")
+
+
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)
 _i32, _i64, _u64, _u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32

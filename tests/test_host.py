@@ -204,6 +204,19 @@ def test_autotune_cache_parse(hctx, tmp_path):
     assert found and (ko.k_max, ko.m_max, ko.ell) == (4, 12, 6)
 
 
+def test_shipped_autotune_cache_covers_the_batch_sweep():
+    """The shipped autotuner cache (written by paper_2408_09055_amd.tune on
+    the GPU) loads, and holds options for every qubit count of the batched
+    sweep (10..22) within the planner's limits."""
+    ctx = qk.Context(host_only=True)
+    qk.autotune_load(ctx, qk.QK_C64, qk.autotune_path(qk.QK_C64))
+    for n in range(10, 23):
+        ko, found = qk.get_tuned(ctx, qk.QK_C64, n)
+        assert found and 1 <= ko.k_max <= 7 and 2 <= ko.m_max <= min(n, 13) and 1 <= ko.ell <= ko.m_max, n
+        qk.kernelize(ctx, W.hea(n, 4, np.random.default_rng(n)), ko).free()
+    ctx.close()
+
+
 def test_plan_kernel_impl_reported(hctx):
     plan = qk.kernelize(hctx, W.random_layered(20, 4, 1), qk.kopts())
     impls = {k.impl for k in plan.kernels()}
