@@ -172,6 +172,39 @@ def test_autotune_and_cache(ctx, tmp_path):
     c2.close()
 
 
+def test_shipped_autotuned_options_keep_the_states():
+    """The batched sweep with the shipped autotuner cache loaded (each
+    circuit planned with the options tuned for its qubit count): every
+    circuit equals the one-circuit path with default options, and the
+    circuits of at most 16 qubits equal the oracle."""
+    c = qk.Context()
+    qk.autotune_load(c, qk.QK_C64, qk.autotune_path(qk.QK_C64))
+    circs = W.hea_batch(256, seed=4)
+    states = []
+    for circ in circs:
+        st = qk.sv_alloc(c, circ.n_qubits, qk.QK_C64)
+        st.init_basis(0)
+        states.append(st)
+    stats, lat = qk.simulate_batch(c, circs, states)
+    assert stats["errors"] == 0 and stats["items"] == len(circs)
+    print(f"tuned batch: {stats['total_ms']:.3f} ms, p50 {np.percentile(lat, 50):.3f} ms", flush=True)
+    checked = 0
+    for circ, st in zip(circs, states):
+        got = st.download()
+        one = qk.sv_alloc(c, circ.n_qubits, qk.QK_C64)
+        one.init_basis(0)
+        qk.simulate(c, circ, one, qk.kopts(dtype=qk.QK_C64))
+        assert oracle.fidelity_loss(got, one.download()) <= 1e-6, circ.name
+        one.free()
+        if circ.n_qubits <= 16:
+            ref = oracle.run(circ, oracle.basis(circ.n_qubits, 0))
+            assert oracle.fidelity_loss(got, ref) <= 1e-6, circ.name
+            checked += 1
+        st.free()
+    assert checked > 50
+    c.close()
+
+
 def _batch_states(ctx, circs, dtype, seed):
     states, psis = [], []
     for i, c in enumerate(circs):
