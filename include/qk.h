@@ -486,7 +486,7 @@ int mlp_adam_step(qk_ctx* ctx, float* params, const float* grads, float* m, floa
  * method, for parameter sweeps).  Each circuit is kernelized on the host with
  * kos[i] (or, when kos is NULL, the options tuned for its qubit count, else
  * defaults) and its plan uploaded; then the circuits are dealt, largest
- * predicted cost first, to the least-loaded of four HIP streams, which run
+ * predicted cost first, to the least-loaded of 32 HIP streams, which run
  * concurrently after the context's stream and before its later work.  States
  * must be distinct, share one dtype and be in logical order; they are in
  * logical order on return, and the call synchronises the context's stream.
