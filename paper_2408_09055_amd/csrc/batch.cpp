@@ -30,9 +30,10 @@ int launch_plan_kernel(const qk_plan* p, int64_t i, qk_state* st, void* stream);
 
 namespace {
 
-// streams of a batch: the box's few hardware queues still run kernels of
-// more streams side by side; on the 256-circuit ansatz sweep 4, 8, 16, 32 and
-// 64 streams measured 78.8, 68.8, 61.2, 56.5 and 54.2 ms
+// streams of a batch: a process gets few hardware queues (four by default),
+// yet kernels of more streams still run side by side; on the 256-circuit
+// ansatz sweep 4, 8, 16, 32 and 64 streams measured 78.8, 68.8, 61.2, 56.5
+// and 54.2 ms
 constexpr int kBatchStreams = 32;
 constexpr bool kPersistentBatchOff = true;
 
