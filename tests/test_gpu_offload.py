@@ -80,6 +80,31 @@ def test_offload_matches_oracle(ctx, dtype):
                   f"1-F={loss:.3e}", flush=True)
 
 
+@pytest.mark.parametrize("dtype", [qk.QK_C64, qk.QK_C128])
+def test_offload_with_the_commuting_lift(ctx, dtype):
+    """Offload over stages cut from a Kernelize plan whose order swaps gates
+    that share only insular qubits (QK_DP_COMMUTE, Kernelize's own kernels
+    and FULL): the chunks' local circuits follow that order; the result
+    must equal the oracle's."""
+    rng = np.random.default_rng(17)
+    n = 20
+    circ = _insular_mix(n, rng, 240)
+    psi = W.random_state(n, 22)
+    ref = oracle.run(circ, psi)
+    flags = qk.QK_DP_ATTACH_1Q | qk.QK_DP_SUBSUME | qk.QK_DP_PACK | qk.QK_DP_COMMUTE
+    for L, kz in ((14, qk.QK_KERNELIZE_DP), (16, qk.QK_KERNELIZE_FULL)):
+        hs = qk.sv_alloc_host(ctx, n, dtype)
+        hs.upload(psi.astype(hs.np_dtype))
+        ko = qk.kopts(dtype=dtype, local_qubits=L, kernelizer=kz, dp_flags=flags)
+        stages = qk.kernelize(ctx, circ, ko).num_stages()
+        qk.simulate_offload(ctx, circ, hs, ko)
+        out = hs.download()
+        hs.free()
+        loss = _check(out, ref, dtype, f"{circ.name} L={L} commute")
+        print(f"offload commute {circ.name} dtype={dtype} L={L} kernelizer={kz}: {stages} stages, 1-F={loss:.3e}",
+              flush=True)
+
+
 def test_offload_24q_against_device_path(ctx):
     """24 qubits, complex128, 2^18-amplitude chunks: the offloaded result
     equals the state the device path computes (same kernels' arithmetic up to
